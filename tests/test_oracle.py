@@ -1,0 +1,328 @@
+"""Pins of the FP64 oracle against facts fixed by the paper and by
+mathematics (closed forms, brute force on tiny grids, the paper's printed
+iteration counts, invariants).  CPU only."""
+import json
+import math
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+from oracle import coeffs, cn, examples as ex, krylov, operators as op
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------- coefficients
+
+@pytest.mark.parametrize("delta", [0.1, 0.3, 0.5, 0.7, 0.9])
+def test_coef_lemma_2_1_and_2_2(delta):
+    """Lemma 2.1 (signs, zero sum via telescoping, positive partial sums) and
+    Lemma 2.2 (q_0+q_2 < q_3 < q_4 < ...)."""
+    n = 400
+    q = coeffs.q_coeffs(delta, n)
+    s = coeffs.s_coeffs(delta, n)
+    assert q[1] > 0 and q[0] + q[2] < 0
+    assert np.all(q[3:] < 0)
+    # sum_{k=0}^{K} q_k = -s_K exactly (telescoping), and s_K -> 0
+    qm = coeffs.q_coeffs_mp(delta, n)
+    sm = coeffs.s_coeffs_mp(delta, n)
+    with mp.workdps(50):
+        for K in (1, 2, 5, 50, n):
+            assert abs(mp.fsum(qm[:K + 1]) + sm[K]) < mp.mpf(10) ** -40
+    assert abs(s[n]) < 1e-3 and abs(s[n]) < abs(s[n // 2])
+    # (iii) q_1 + sum_{k != 1, k <= s} q_k > 0 for s >= 2
+    assert np.all(np.cumsum(q)[2:] > 0)
+    # Lemma 2.2
+    assert q[0] + q[2] < q[3]
+    assert np.all(np.diff(q[3:]) > 0)
+
+
+def test_coef_mp_vs_naive_small_k():
+    """The float64 rounding of the 50-digit values agrees with the naive
+    float64 formula where cancellation is harmless (small k)."""
+    d = 0.37
+    s = coeffs.s_coeffs(d, 10)
+    naive = [0.5 ** d, 1.5 ** d - 2 * 0.5 ** d] + [
+        (k + 0.5) ** d - 2 * (k - 0.5) ** d + (k - 1.5) ** d for k in range(2, 11)]
+    np.testing.assert_allclose(s, naive, rtol=1e-13, atol=0)
+
+
+def test_delta_zero_gives_laplacian():
+    """At delta = 0 (outside the method's range) T_n = tridiag(-1, 2, -1)."""
+    q = coeffs.q_coeffs(0.0, 6)
+    T = op.T_mat(q, 6)
+    ref = 2 * np.eye(6) - np.eye(6, k=1) - np.eye(6, k=-1)
+    np.testing.assert_array_equal(T, ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 9])
+@pytest.mark.parametrize("delta,kp,km", [(0.2, 1.0, 1.0), (0.65, 19.0, 21.0), (0.9, 0.3, 1.7)])
+def test_B_from_hat_functions(n, delta, kp, km):
+    """B_n from q_k equals the entry-wise finite-volume assembly from the
+    Riemann-Liouville derivatives of the hat functions (Section 2)."""
+    q = coeffs.q_coeffs(delta, n)
+    np.testing.assert_allclose(op.B_mat(q, n, kp, km),
+                               op.B_from_hat_functions(delta, n, kp, km),
+                               rtol=0, atol=1e-14 * max(kp, km))
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 17])
+def test_a_eigs(n):
+    """Lemma 3.1: A_n is SPD with eigenvalues in (1/2, 1); closed form in the
+    DST-I basis."""
+    A = op.A_mat(n)
+    S = op.dst1_mat(n)
+    D = S @ A @ S
+    np.testing.assert_allclose(D, np.diag(coeffs.a_eigs(n)), atol=1e-14)
+    ev = np.linalg.eigvalsh(A)
+    assert ev.min() > 0.5 and ev.max() < 1.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 9, 16])
+def test_dst_orthogonal_symmetric(n):
+    S = op.dst1_mat(n)
+    np.testing.assert_allclose(S, S.T, atol=1e-15)
+    np.testing.assert_allclose(S @ S, np.eye(n), atol=1e-14)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 9, 20])
+@pytest.mark.parametrize("delta", [0.1, 0.5, 0.9])
+def test_tau_eigs_diagonalise(n, delta):
+    """Lemma 3.2 eigenvalue formula (index read as j): S tau(H(T)) S is
+    diagonal with those entries; tau(H(T)) and H(T) are SPD; Lemma 3.5
+    bound 1/2 < lambda(tau^{-1} H(T)) < 3/2."""
+    q = coeffs.q_coeffs(delta, n)
+    t = coeffs.sym_first_column(q, n)
+    tau = op.tau_of_symmetric_toeplitz(t)
+    S = op.dst1_mat(n)
+    D = S @ tau @ S
+    lam = coeffs.tau_eigs(q, n)
+    np.testing.assert_allclose(D, np.diag(lam), atol=1e-14)
+    assert lam.min() > 0
+    T = op.T_mat(q, n)
+    H = 0.5 * (T + T.T)
+    assert np.linalg.eigvalsh(H).min() > 0
+    if n >= 3:
+        ev = np.linalg.eigvals(np.linalg.solve(tau, H)).real
+        assert ev.min() > 0.5 and ev.max() < 1.5
+
+
+# ---------------------------------------------------------------- operators
+
+def _prob(dim, n, delta, kp, km, M=4):
+    return op.Problem(dim, n, delta, kp, km, T=1.0, M=M)
+
+
+PROBS = [
+    _prob(2, [5, 7], [0.3, 0.8], [1.0, 1.0], [1.0, 1.0]),
+    _prob(2, [6, 4], [0.4, 0.6], [19.0, 21.0], [21.0, 23.0]),
+    _prob(3, [3, 4, 5], [0.3, 0.5, 0.7], [1.0] * 3, [1.0] * 3),
+    _prob(3, [4, 3, 2], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
+]
+
+
+@pytest.mark.parametrize("prob", PROBS)
+def test_dense_kron_equals_hat_assembly(prob):
+    A1, R1 = op.dense_system(prob, "q")
+    A2, R2 = op.dense_system(prob, "hat")
+    scale = np.abs(A1).max()
+    np.testing.assert_allclose(A1, A2, atol=1e-14 * scale)
+    np.testing.assert_allclose(R1, R2, atol=1e-14 * scale)
+    if prob.symmetric:
+        np.testing.assert_allclose(A1, A1.T, atol=1e-15 * scale)
+        assert np.linalg.eigvalsh(A1).min() > 0
+
+
+@pytest.mark.parametrize("prob", PROBS)
+def test_structured_vs_dense(prob):
+    A, R = op.dense_system(prob)
+    rng = np.random.default_rng(3)
+    X = rng.standard_normal(prob.shape)
+    F = rng.standard_normal(prob.shape)
+    y = op.apply_A(prob, X)
+    np.testing.assert_allclose(y.reshape(-1), A @ X.reshape(-1), rtol=0,
+                               atol=1e-13 * np.abs(A).max() * np.abs(X).max())
+    b = op.apply_rhs(prob, X, F)
+    np.testing.assert_allclose(b.reshape(-1), R @ X.reshape(-1) + prob.dt * F.reshape(-1),
+                               rtol=0, atol=1e-13 * np.abs(R).max() * 3)
+    # independent route: multilevel circulant embedding + real FFT
+    yc = op.apply_A_circulant(prob, X)
+    np.testing.assert_allclose(yc, y, rtol=0, atol=1e-12 * np.abs(y).max())
+    bc = op.apply_A_circulant(prob, X, sign=-1.0) + prob.dt * F
+    np.testing.assert_allclose(bc, b, rtol=0, atol=1e-12 * np.abs(b).max())
+
+
+@pytest.mark.parametrize("prob", PROBS)
+def test_preconditioner(prob):
+    """P = S_N Lambda S_N equals the explicit tau-matrix preconditioner;
+    Lemma 3.3 lambda_min(P) > 1/8."""
+    P = op.dense_preconditioner(prob)
+    np.testing.assert_allclose(P, P.T, atol=1e-14 * np.abs(P).max())
+    rng = np.random.default_rng(5)
+    R = rng.standard_normal(prob.shape)
+    z = op.apply_Pinv(prob, R)
+    np.testing.assert_allclose(z.reshape(-1), np.linalg.solve(P, R.reshape(-1)),
+                               rtol=1e-11, atol=1e-13)
+    np.testing.assert_allclose(op.apply_P(prob, z), R, atol=1e-11 * np.abs(R).max())
+    assert np.linalg.eigvalsh(P).min() > 1.0 / 8.0
+    Lam = op.precond_eigs(prob)
+    np.testing.assert_allclose(np.sort(Lam.reshape(-1)), np.linalg.eigvalsh(P),
+                               rtol=1e-12)
+
+
+def test_theorem_3_1_spectrum():
+    """Theorem 3.1: symmetric case, lambda(P^{-1} A) in (1/2, 3/2)."""
+    for delta in ([0.3, 0.5, 0.7], [0.1, 0.2, 0.3], [0.7, 0.8, 0.9]):
+        prob = _prob(3, [7, 7, 7], delta, [1.0] * 3, [1.0] * 3)
+        A, _ = op.dense_system(prob)
+        P = op.dense_preconditioner(prob)
+        ev = np.linalg.eigvals(np.linalg.solve(P, A))
+        assert np.abs(ev.imag).max() < 1e-10
+        assert ev.real.min() > 0.5 and ev.real.max() < 1.5
+
+
+def test_lemmas_3_7_3_10_nonsymmetric():
+    """Lemma 3.7: lambda(P^{-1/2} H(A) P^{-1/2}) in (1/2, 3/2); Lemma 3.10:
+    rho(P^{-1/2} S(A) P^{-1/2}) <= (3/2) max_i tan(delta_i pi/2)
+    |k+ - k-|/(k+ + k-); Theorem 3.2 rate omega < 1."""
+    prob = _prob(3, [7, 7, 7], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3])
+    A, _ = op.dense_system(prob)
+    P = op.dense_preconditioner(prob)
+    w, V = np.linalg.eigh(P)
+    Pmh = V @ np.diag(w ** -0.5) @ V.T
+    H = 0.5 * (A + A.T)
+    S = 0.5 * (A - A.T)
+    evH = np.linalg.eigvalsh(Pmh @ H @ Pmh)
+    assert evH.min() > 0.5 and evH.max() < 1.5
+    rho = np.abs(np.linalg.eigvals(Pmh @ S @ Pmh)).max()
+    vs = 1.5 * max(math.tan(prob.delta[i] * math.pi / 2) * abs(prob.kplus[i] - prob.kminus[i])
+                   / (prob.kplus[i] + prob.kminus[i]) for i in range(3))
+    assert rho <= vs
+    omega = math.sqrt((2 + 4 * vs ** 2) / (3 + 4 * vs ** 2))
+    assert omega < 1
+
+
+# ---------------------------------------------------------------- solvers
+
+@pytest.mark.parametrize("prob", PROBS)
+def test_krylov_vs_lu(prob):
+    A, _ = op.dense_system(prob)
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(prob.shape)
+    x_ref = np.linalg.solve(A, b.reshape(-1)).reshape(prob.shape)
+    x, info = cn.solve_step(prob, b, None, 1e-13)
+    assert info.converged
+    np.testing.assert_allclose(x, x_ref, rtol=0, atol=1e-11 * np.abs(x_ref).max())
+    # with a nonzero initial guess
+    x2, info2 = cn.solve_step(prob, b, rng.standard_normal(prob.shape), 1e-13)
+    np.testing.assert_allclose(x2, x_ref, rtol=0, atol=1e-11 * np.abs(x_ref).max())
+    # both solvers on the same (possibly non-symmetric) system: GMRES always
+    # applies; PCG only in the symmetric case
+    x3, _ = cn.solve_step(prob, b, None, 1e-13, solver="gmres", restart=3)
+    np.testing.assert_allclose(x3, x_ref, rtol=0, atol=1e-10 * np.abs(x_ref).max())
+
+
+def test_delta_zero_one_iteration():
+    """At delta = 0, tau(H(T)) = T, so P = A and both solvers converge in one
+    iteration (classical heat-equation limit; a test case outside (0,1))."""
+    for kp, km in (([1.0, 1.0, 1.0], [1.0, 1.0, 1.0]), ([1.0, 2.0, 0.5], [3.0, 1.0, 0.7])):
+        prob = _prob(3, [6, 5, 7], [0.0, 0.0, 0.0], kp, km)
+        b = np.random.default_rng(1).standard_normal(prob.shape)
+        x, info = cn.solve_step(prob, b, None, 1e-12)
+        assert info.iters == 1
+        A, _ = op.dense_system(prob)
+        np.testing.assert_allclose(x.reshape(-1), np.linalg.solve(A, b.reshape(-1)), atol=1e-12)
+
+
+def test_cn_run_vs_lu():
+    for prob in PROBS:
+        rng = np.random.default_rng(2)
+        u0 = rng.standard_normal(prob.shape)
+        F = rng.standard_normal(prob.shape)
+        u, its = cn.run(prob, u0, lambda m: F * m, tol=1e-13)
+        u_ref = cn.run_direct(prob, u0, lambda m: F * m)
+        np.testing.assert_allclose(u, u_ref, rtol=0, atol=1e-11 * np.abs(u_ref).max())
+        assert len(its) == prob.M
+
+
+# ---------------------------------------------------------------- examples
+
+def test_example_sources_match_printed():
+    x = np.linspace(0.01, 0.99, 17)
+    y = np.linspace(0.03, 0.97, 13)[:, None]
+    for d, kp, km in (([0.1, 0.9], [5, 5], [5, 5]), ([0.4, 0.5], [19, 21], [21, 23])):
+        a = ex.ex41_source(x, y, 0.3, d, kp, km)
+        b = ex.ex41_source_printed(x, y, 0.3, d, kp, km)
+        np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-14)
+
+
+@pytest.mark.parametrize("delta,kp,km,x", [(0.3, 1.0, 0.0, 0.37), (0.7, 0.0, 1.0, 0.61),
+                                          (0.5, 19.0, 21.0, 0.2)])
+def test_flux_derivative_vs_quadrature(delta, kp, km, x):
+    """d/dx D^delta p from the Riemann-Liouville integrals (Section 1),
+    evaluated by mpmath quadrature.  Since p(0) = p'(0) = p(1) = p'(1) = 0 the
+    two x-derivatives move under the integral sign:
+    d/dx D^delta p = (1/Gamma(delta)) int_0^x w^(delta-1) [k+ p''(x-w)] dw
+                   + (1/Gamma(delta)) int_0^(1-x) w^(delta-1) [k- p''(x+w)] dw."""
+    with mp.workdps(30):
+        d = mp.mpf(delta)
+        xx = mp.mpf(x)
+        p2 = lambda s: 2 - 12 * s + 12 * s ** 2      # (s^2 (1-s)^2)''
+        left = mp.quad(lambda w: w ** (d - 1) * p2(xx - w), [0, xx])
+        right = mp.quad(lambda w: w ** (d - 1) * p2(xx + w), [0, 1 - xx])
+        ref = float((kp * left + km * right) / mp.gamma(d))
+    got = float(ex.flux_derivative(np.array(x), delta, kp, km))
+    assert abs(got - ref) <= 1e-9 * max(1.0, abs(ref))
+
+
+def test_second_order_convergence_2d():
+    """Remark 2.1: symmetric case, second order in space and time; the max
+    relative error at T=1 drops about 4x per halving of h and dt."""
+    errs = []
+    for n1 in (16, 32, 64):
+        prob = op.Problem(2, [n1 - 1] * 2, [0.4, 0.5], [5, 5], [5, 5], T=1.0, M=n1 // 4)
+        h = prob.h
+        F = lambda m: ex.cell_average(lambda X, Y: ex.ex41_source(
+            X, Y, (m - 0.5) * prob.dt, prob.delta, prob.kplus, prob.kminus), prob.n, h)
+        u0 = ex.nodal(lambda X, Y: ex.ex41_exact(X, Y, 0.0), prob.n, h)
+        u, _ = cn.run(prob, u0, F, tol=1e-12)
+        ue = ex.nodal(lambda X, Y: ex.ex41_exact(X, Y, 1.0), prob.n, h)
+        errs.append(np.abs(u - ue).max() / np.abs(ue).max())
+    r1, r2 = errs[0] / errs[1], errs[1] / errs[2]
+    assert 3.0 < r1 < 5.5 and 3.0 < r2 < 5.5, errs
+
+
+# ---------------------------------------------------------------- paper tables
+
+def _golden_rows(max_2d=128, max_3d=32):
+    rows = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))["rows"]
+    out = []
+    for tab, dim, orders, M, n1, it in rows:
+        if (dim == 2 and n1 <= max_2d) or (dim == 3 and n1 <= max_3d):
+            out.append((tab, dim, tuple(orders), M, n1, it))
+    return out
+
+
+@pytest.mark.parametrize("row", _golden_rows())
+def test_paper_iteration_counts(row):
+    """The oracle with the replication settings (x0 = 0, tol 1e-9, restart
+    20) reproduces the printed average iteration counts of Tables 1-4."""
+    tab, dim, orders, M, n1, it = row
+    sym = tab in (1, 3)
+    kp = [5.0] * dim if sym else [19.0, 21.0, 23.0][:dim]
+    km = [5.0] * dim if sym else [21.0, 23.0, 25.0][:dim]
+    prob = op.Problem(dim, [n1 - 1] * dim, list(orders), kp, km, T=1.0, M=M)
+    h = prob.h
+    if dim == 2:
+        F = lambda m: ex.cell_average(lambda X, Y: ex.ex41_source(
+            X, Y, (m - 0.5) * prob.dt, prob.delta, kp, km), prob.n, h)
+        u0 = ex.nodal(lambda X, Y: ex.ex41_exact(X, Y, 0.0), prob.n, h)
+    else:
+        F = lambda m: ex.cell_average(lambda X, Y, Z: ex.ex42_source(
+            X, Y, Z, (m - 0.5) * prob.dt, prob.delta, kp, km), prob.n, h)
+        u0 = ex.nodal(lambda X, Y, Z: ex.ex42_exact(X, Y, Z, 0.0), prob.n, h)
+    _, its = cn.run(prob, u0, F, tol=1e-9, x0_mode="zero",
+                    maxit=(n1 - 1) ** 3, restart=20)
+    assert round(float(np.mean(its)), 2) == it
