@@ -1,0 +1,200 @@
+"""Benchmark: Crank-Nicolson steps per second at 255^3, mixed precision vs
+float64, on one MI355X.
+
+Workload (3D non-symmetric): (alpha, beta, gamma) = (0.4, 0.6, 0.8),
+k+ = (1.0, 0.8, 1.2), k- = (0.5, 1.0, 0.3), 255^3 interior unknowns, 16 CN
+steps to T = 1, f = 8 seeded Gaussian bumps, u0 = 0, left-preconditioned
+GMRES(20) with the sine-transform preconditioner, tol 1e-8.
+
+A step is one fsd_cn_step: right-hand side, then the solve.  The headline
+value is the mixed-precision solver (float32 inner GMRES, float64 defect
+correction); the same steps are run with the float64 solver for the
+comparison and the relative difference of the two final states.
+
+    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+
+Prints one JSON line (rank 0).  Inputs are generated on the host and copied
+to the GPU before timing.  The roofline entry is the dominant kernel of the
+timed mixed-precision steps, timed with hipEvents inside the library on its
+stream; `cpu_baseline` times the float64 oracle on this host for one CN step
+(the first step of the same workload).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "CN steps/s at 255^3, mixed vs FP64 (rel err 1e-8); Toeplitz matvec HBM GB/s"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def run_steps(prob, u0, F, steps, warmup, profile=False):
+    """Advance warmup + steps CN steps; time the last `steps`."""
+    import torch
+    u = u0.clone()
+    iters = []
+    outer = []
+    for _ in range(warmup):
+        u, st = prob.cn_step(u, F)
+        iters.append(st["iters"])
+        outer.append(st["outer_iters"])
+    torch.cuda.synchronize()
+    if profile:
+        prob.profile(True)
+        prob.profile_read()           # discard anything before the timed region
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        u, st = prob.cn_step(u, F)
+        iters.append(st["iters"])
+        outer.append(st["outer_iters"])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = prob.profile_read() if profile else None
+    if profile:
+        prob.profile(False)
+    return u, (t1 - t0), iters, outer, prof
+
+
+def cpu_baseline(w):
+    """Float64 oracle, first CN step of the workload, on this host."""
+    from oracle import cn, operators as op
+    prob = op.Problem(3, w.n, w.delta, w.kplus, w.kminus, T=w.T, M=w.M)
+    t0 = time.perf_counter()
+    u, its = cn.run(prob, w.u0, lambda m: w.F, tol=w.tol, x0_mode="prev", solver="gmres",
+                    steps=1)
+    dt = time.perf_counter() - t0
+    try:
+        cores = len(os.sched_getaffinity(0))
+    except AttributeError:
+        cores = os.cpu_count()
+    return {"value": 1.0 / dt, "unit": "CN steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"1 CN step (step 1 of 16, {its[0]} GMRES iterations) of the same workload, "
+                      f"float64 NumPy/SciPy oracle, {dt:.1f} s on {cpu_model()}"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=255)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
+    ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    a = ap.parse_args(argv)
+    if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not "
+                                   "supported (use --gpus 1)", "n_gpus": a.gpus}))
+        return 2
+    if a.warmup + a.steps > 16:
+        log("warning: more steps than the workload's 16; continuing past T = 1")
+
+    import torch
+    import workloads
+    from paper_2511_21198_amd.solver import Problem
+
+    w = workloads.config_3d_nonsymmetric(seed=0, n=a.n, M=16)
+    dev = torch.device("cuda:0")
+    F = torch.from_numpy(w.F).to(dev)
+    u0 = torch.zeros_like(F)
+    common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
+                  solver="gmres", restart=20, tol=w.tol, x0="prev")
+    res = {}
+    if a.only in ("fp64", "both"):
+        log("fp64 solver ...")
+        p64 = Problem(**common, precision="fp64")
+        u64, t64, it64, _, prof64 = run_steps(p64, u0, F, a.steps, a.warmup, profile=True)
+        res["fp64"] = dict(t=t64, iters=it64, prof=prof64)
+        del p64
+    if a.only in ("mixed", "both"):
+        log("mixed solver ...")
+        pmx = Problem(**common, precision="mixed", inner_tol=1e-4, max_outer=8)
+        umx, tmx, itmx, outmx, profmx = run_steps(pmx, u0, F, a.steps, a.warmup, profile=True)
+        res["mixed"] = dict(t=tmx, iters=itmx, outer=outmx, prof=profmx)
+        del pmx
+    head = "mixed" if "mixed" in res else "fp64"
+    T = res[head]["t"]
+    value = a.steps / T
+    rel = None
+    if "mixed" in res and "fp64" in res:
+        rel = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
+
+    prof = res[head]["prof"]
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    per_launch = dom["bytes"] / dom["launches"]
+    achieved = per_launch / (dom["avg_ms"] * 1e-3) / 1e9
+    toep = {k: round(v["gbps"], 1) for k, v in prof.items() if k.startswith("toep")}
+    if "fp64" in res:
+        toep.update({k: round(v["gbps"], 1) for k, v in res["fp64"]["prof"].items()
+                     if k.startswith("toep")})
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "CN steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(1e3 * T / a.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"3D non-symmetric {a.n}^3, (alpha,beta,gamma)=(0.4,0.6,0.8), "
+                               "k+=(1.0,0.8,1.2), k-=(0.5,1.0,0.3), 16 CN steps to T=1, "
+                               "8 seeded Gaussian bumps, u0=0, PGMRES(20) + sine-transform "
+                               "preconditioner, tol 1e-8",
+                   "solver": f"{head}: " + ("float32 inner GMRES in float64 defect correction"
+                                             if head == "mixed" else "float64 GMRES"),
+                   "n": a.n, "unknowns": a.n ** 3},
+        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "avg_launch_ms": round(dom["avg_ms"], 5),
+                     "algorithmic_bytes_per_launch": per_launch},
+        "toeplitz_matvec_gbps": toep,
+    }
+    if "fp64" in res:
+        out["fp64_steps_per_s"] = round(a.steps / res["fp64"]["t"], 3)
+        out["iters_fp64"] = res["fp64"]["iters"]
+    if "mixed" in res:
+        out["iters_mixed_inner"] = res["mixed"]["iters"]
+        out["outer_mixed"] = res["mixed"]["outer"]
+    if rel is not None:
+        out["speedup_vs_fp64"] = round(out["fp64_steps_per_s"] and value / out["fp64_steps_per_s"], 3)
+        out["rel_err_mixed_vs_fp64"] = rel
+    out["kernels"] = {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
+                          "gbps": round(v["gbps"], 1), "total_ms": round(v["total_ms"], 3)}
+                      for k, v in prof.items()}
+    if not a.no_cpu:
+        log("cpu baseline (oracle, 1 step) ...")
+        wc = workloads.config_3d_nonsymmetric(seed=0, n=a.n, M=16)
+        out["cpu_baseline"] = cpu_baseline(wc)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

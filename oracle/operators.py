@@ -358,3 +358,44 @@ def apply_P(prob: Problem, X: np.ndarray, Lam: np.ndarray | None = None) -> np.n
     if Lam is None:
         Lam = precond_eigs(prob)
     return dst_all(dst_all(X) * Lam)
+
+
+def apply_A_at(prob: Problem, X: np.ndarray, idx, sign: float = 1.0) -> float:
+    """Entry ``idx`` (a NumPy index tuple (k, j, i) / (j, i)) of
+    (A_N + sign*K) X, from the definition of the Kronecker terms: each term
+    is a product of one row per axis, contracted with X.  Cheap for any grid
+    size (dense B rows of length n_i, tridiagonal A rows)."""
+    d = prob.dim
+    rows_A, rows_B = [], []
+    for i in range(d):
+        n = prob.n[i]
+        r = idx[d - 1 - i]
+        a = np.zeros(n)
+        a[r] = 0.75
+        if r > 0:
+            a[r - 1] = 0.125
+        if r + 1 < n:
+            a[r + 1] = 0.125
+        q = prob.q[i]
+        b = np.zeros(n)
+        for p in range(n):
+            v = 0.0
+            if r - p + 1 >= 0:
+                v += prob.kplus[i] * q[r - p + 1]
+            if p - r + 1 >= 0:
+                v += prob.kminus[i] * q[p - r + 1]
+            b[p] = v
+        rows_A.append(a)
+        rows_B.append(b)
+
+    def contract(rows):
+        Y = X
+        for i in reversed(range(d)):          # outermost axis first
+            Y = np.tensordot(rows[i], Y, axes=([0], [0]))
+        return float(Y)
+
+    out = contract(rows_A)
+    for j in range(d):
+        rows = [rows_B[i] if i == j else rows_A[i] for i in range(d)]
+        out += sign * prob.eta[j] * contract(rows)
+    return out

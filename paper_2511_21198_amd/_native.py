@@ -1,0 +1,122 @@
+"""ctypes binding of libfsd.so (include/fsd.h).  Argument marshalling only:
+every step of the solver runs in the HIP library.
+
+The library is loaded after ``torch`` so that it shares torch's HIP runtime
+(same device memory, same streams).  A missing library raises at import
+time; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch  # noqa: F401  (loads the HIP runtime the library binds to)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfsd.so")
+
+# fsd_status
+OK, EINVAL, ENOTCONV, EBREAKDOWN, ENONFINITE, ESMALLWS, EHIP, EUNSUPPORTED, ENOTBOUND = range(9)
+# fsd_solver
+SOLVER_AUTO, SOLVER_PCG, SOLVER_PGMRES = 0, 1, 2
+# fsd_precision
+PREC_FP64, PREC_MIXED = 0, 1
+# fsd_x0_mode
+X0_PREV, X0_ZERO, X0_EXTERNAL = 0, 1, 2
+
+
+class Params(C.Structure):
+    _fields_ = [
+        ("dim", C.c_int),
+        ("n", C.c_int * 3),
+        ("a", C.c_double * 3),
+        ("b", C.c_double * 3),
+        ("delta", C.c_double * 3),
+        ("kplus", C.c_double * 3),
+        ("kminus", C.c_double * 3),
+        ("M", C.c_int),
+        ("T", C.c_double),
+        ("solver", C.c_int),
+        ("restart", C.c_int),
+        ("tol", C.c_double),
+        ("maxit", C.c_long),
+        ("precision", C.c_int),
+        ("inner_tol", C.c_double),
+        ("max_outer", C.c_int),
+        ("x0_mode", C.c_int),
+        ("allow_delta_zero", C.c_int),
+    ]
+
+
+class Stats(C.Structure):
+    _fields_ = [
+        ("iters", C.c_long),
+        ("outer_iters", C.c_int),
+        ("converged", C.c_int),
+        ("relres", C.c_double),
+        ("solver_relres", C.c_double),
+        ("status", C.c_int),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ProfileEntry(C.Structure):
+    _fields_ = [
+        ("name", C.c_char * 32),
+        ("launches", C.c_long),
+        ("total_ms", C.c_double),
+        ("bytes", C.c_double),
+    ]
+
+
+# Every symbol declared in include/fsd.h, with (restype, argtypes).
+_VP = C.c_void_p
+SIGNATURES = {
+    "fsd_default_params": (C.c_int, [C.POINTER(Params)]),
+    "fsd_init_problem": (C.c_int, [C.POINTER(Params), C.POINTER(_VP)]),
+    "fsd_destroy": (None, [_VP]),
+    "fsd_workspace_bytes": (C.c_size_t, [_VP]),
+    "fsd_bind": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
+    "fsd_apply_A": (C.c_int, [_VP, _VP, _VP]),
+    "fsd_apply_rhs": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "fsd_apply_Pinv": (C.c_int, [_VP, _VP, _VP]),
+    "fsd_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
+    "fsd_cn_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)]),
+    "fsd_get_coefficients": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_double),
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fsd_profile_enable": (C.c_int, [_VP, C.c_int]),
+    "fsd_profile_read": (C.c_int, [_VP, C.POINTER(ProfileEntry), C.c_int]),
+    "fsd_status_string": (C.c_char_p, [C.c_int]),
+    "fsd_last_error": (C.c_char_p, []),
+    "fsd_version": (C.c_char_p, []),
+}
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build it with `python -m paper_2511_21198_amd.build` "
+            "(the solver has no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = load()
+
+
+class FsdError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = lib.fsd_last_error().decode()
+        super().__init__(f"{where}: {lib.fsd_status_string(status).decode()} ({msg})")
+
+
+def check(status: int, where: str):
+    if status != OK:
+        raise FsdError(status, where)

@@ -1,0 +1,40 @@
+// Host launchers of the GMRES kernels (fsd_gmres.hip).
+#pragma once
+
+#include "fsd_internal.h"
+
+namespace fsd {
+
+constexpr int kGmGrid = 1024;
+
+enum GmOp : int {
+    GM_PBB = 0,    // bb = ||P^{-1} b||^2, thresh = tol^2 bb
+    GM_BETA = 1,   // beta = ||r0||, g = beta e1, scale = 1/beta (done if small)
+    GM_H1 = 2,     // H[0..j, j] = first Gram-Schmidt coefficients
+    GM_H2 = 3,     // second pass coefficients added to H[0..j, j] and kept in h2
+    GM_STEP = 4,   // H[j+1, j] = ||w||, Givens rotations, residual test
+    GM_SOLVE = 5,  // y = R^{-1} g for the k columns of the cycle
+};
+
+// Offsets inside Ctrl::gm for restart m.
+inline int gm_off_h2(int m) { return (m + 1) * m + m + m + (m + 1) + m; }
+inline int gm_off_y(int m) { return (m + 1) * m + m + m + (m + 1); }
+
+int gm_grid(long N);
+
+template <typename T>
+hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* partials,
+                   const Ctrl* ctrl, int* nparts, hipStream_t s);
+template <typename T>
+hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, const Ctrl* ctrl,
+                    int hoff, int want_dots, double* partials, int* nparts, hipStream_t s);
+template <typename T>
+hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ctrl, int yoff,
+                     hipStream_t s);
+template <typename T>
+hipError_t gm_scale(const T* in, T* out, long N, const Ctrl* ctrl, hipStream_t s);
+hipError_t gm_scalar(Ctrl* c, const double* partials, int nparts, int nv, int j, int op,
+                     hipStream_t s);
+hipError_t gm_restart(Ctrl* c, hipStream_t s);
+
+}  // namespace fsd

@@ -1,0 +1,305 @@
+// Kernels of the left-preconditioned restarted GMRES (Section 3.2,
+// ``one_side_system``): Arnoldi on w = P^{-1} A v_j with classical
+// Gram-Schmidt applied twice (CGS2), Givens rotations on the small
+// Hessenberg matrix held in device memory (one thread), and the final
+// update x += V y.
+//
+// Memory traffic per Arnoldi step j (nv = j + 1 basis vectors):
+//   k_mdot      reads V[0..j], w                 -> partials of V^T w
+//   k_maxpy     reads V[0..j], w, writes w       -> w -= V h1, partials of V^T w
+//   k_maxpy     reads V[0..j], w, writes v_{j+1} -> w -= V h2, partial ||w||^2
+// Each kernel loads the nv basis values of an element once into registers.
+#include "fsd_gmres.h"
+
+namespace fsd {
+
+namespace {
+
+constexpr int GT = 256;
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup; valid in thread 0.  sbuf holds GT/64 doubles.
+__device__ inline double block_sum(double v, double* sbuf) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sbuf[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < GT / 64; ++i) s += sbuf[i];
+    }
+    return s;
+}
+
+// partials[i * G + blk] = sum_e V_i[e] w[e], i < nv (nv <= NVMAX)
+template <typename T, int NVMAX>
+__global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, int nv,
+                                             const T* __restrict__ w, long N,
+                                             double* __restrict__ partials, const Ctrl* ctrl) {
+    __shared__ double sb[GT / 64];
+    if (ctrl->done) return;
+    double acc[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT) {
+        const double we = (double)w[e];
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i)
+            if (i < nv) acc[i] += (double)V[i * ld + e] * we;
+    }
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) {
+        if (i < nv) {
+            const double s = block_sum(acc[i], sb);
+            if (threadIdx.x == 0) partials[(long)i * gridDim.x + blockIdx.x] = s;
+        }
+    }
+}
+
+// out = in - sum_i h_i V_i (h from ctrl->gm + hoff); then either partial dots
+// V_i^T out (want_dots) or the partial ||out||^2.
+template <typename T, int NVMAX>
+__global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, int nv,
+                                              const T* in, T* out, long N, const Ctrl* ctrl,
+                                              int hoff, int want_dots, double* __restrict__ partials) {
+    __shared__ double sb[GT / 64];
+    if (ctrl->done) return;
+    T h[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) h[i] = i < nv ? (T)ctrl->gm[hoff + i] : T(0);
+    double acc[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
+    double nrm = 0.0;
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT) {
+        T v[NVMAX];
+        T o = in[e];
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i) {
+            v[i] = i < nv ? V[i * ld + e] : T(0);
+            o -= h[i] * v[i];
+        }
+        out[e] = o;
+        if (want_dots) {
+#pragma unroll
+            for (int i = 0; i < NVMAX; ++i) acc[i] += (double)v[i] * (double)o;
+        } else {
+            nrm += (double)o * (double)o;
+        }
+    }
+    if (want_dots) {
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i) {
+            if (i < nv) {
+                const double s = block_sum(acc[i], sb);
+                if (threadIdx.x == 0) partials[(long)i * gridDim.x + blockIdx.x] = s;
+            }
+        }
+    } else {
+        const double s = block_sum(nrm, sb);
+        if (threadIdx.x == 0) partials[blockIdx.x] = s;
+    }
+}
+
+// x += sum_{i < k} y_i V_i with k = ctrl->gm_k and y in ctrl->gm (yoff).
+template <typename T, int NVMAX>
+__global__ __launch_bounds__(GT) void k_gm_update(T* x, const T* __restrict__ V, long ld, long N,
+                                                  const Ctrl* ctrl, int yoff) {
+    const int k = ctrl->gm_k;
+    T y[NVMAX];
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) y[i] = i < k ? (T)ctrl->gm[yoff + i] : T(0);
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT) {
+        T acc = x[e];
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i)
+            if (i < k) acc += y[i] * V[i * ld + e];
+        x[e] = acc;
+    }
+}
+
+// out = ctrl->gm_scale * in
+template <typename T>
+__global__ __launch_bounds__(GT) void k_scale(const T* in, T* out, long N, const Ctrl* ctrl) {
+    if (ctrl->done) return;
+    const T s = (T)ctrl->gm_scale;
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT)
+        out[e] = s * in[e];
+}
+
+// v_cmp_class based; an arithmetic test such as v - v == 0 is unsound under
+// FP contraction (the subtraction can fuse with the multiply producing v).
+__device__ inline bool gm_isfinite(double v) { return __builtin_isfinite(v); }
+
+// Scalar GMRES steps (one workgroup; thread 0 updates the state).
+// Layout of ctrl->gm for restart m: H (m+1) x m column-major at 0,
+// cs at GM_CS, sn at GM_SN, g at GM_G (m+1), y at GM_Y (m), h2 at GM_T (m+1).
+__global__ __launch_bounds__(GT) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
+                                                  int nparts, int nv, int j, int op) {
+    __shared__ double sb[GT / 64];
+    const int m = c->gm_m;
+    const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m, oY = oG + m + 1, oT = oY + m;
+    double* gm = c->gm;
+    if (op == GM_SOLVE) {
+        // back substitution R y = g on the rotated Hessenberg matrix
+        if (threadIdx.x == 0) {
+            const int k = c->gm_k;
+            for (int i = k - 1; i >= 0; --i) {
+                double s = gm[oG + i];
+                for (int l = i + 1; l < k; ++l) s -= gm[oH + i + (m + 1) * l] * gm[oY + l];
+                gm[oY + i] = s / gm[oH + i + (m + 1) * i];
+            }
+        }
+        return;
+    }
+    if (c->done) return;
+    for (int i = 0; i < nv; ++i) {
+        double acc = 0.0;
+        for (int t = threadIdx.x; t < nparts; t += GT) acc += partials[(long)i * nparts + t];
+        const double S = block_sum(acc, sb);
+        if (threadIdx.x == 0) {
+            if (op == GM_H1) gm[oH + i + (m + 1) * j] = S;
+            else if (op == GM_H2) { gm[oT + i] = S; gm[oH + i + (m + 1) * j] += S; }
+            else gm[oT + i] = S;   // GM_PBB, GM_BETA, GM_STEP: a single norm
+        }
+    }
+    if (threadIdx.x != 0) return;
+    if (op == GM_PBB) {
+        const double S = gm[oT];
+        c->bb = S;
+        c->thresh = c->tol2 * S;
+        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; }
+        else if (S == 0.0) { c->rr = 0.0; c->done = 1; }
+    } else if (op == GM_BETA) {
+        const double S = gm[oT];
+        c->rr = S;
+        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
+        if (S <= c->thresh) { c->done = 1; c->gm_k = 0; return; }
+        const double beta = sqrt(S);
+        c->gm_beta = beta;
+        c->gm_scale = 1.0 / beta;
+        for (int i = 0; i <= m; ++i) gm[oG + i] = 0.0;
+        gm[oG] = beta;
+        c->gm_k = 0;
+        c->gm_j = 0;
+    } else if (op == GM_STEP) {
+        const double S = gm[oT];
+        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
+        const double hnext = sqrt(S);
+        double* H = gm + oH + (m + 1) * j;   // column j
+        H[j + 1] = hnext;
+        for (int i = 0; i < j; ++i) {
+            const double cs = gm[oCS + i], sn = gm[oSN + i];
+            const double t = cs * H[i] + sn * H[i + 1];
+            H[i + 1] = -sn * H[i] + cs * H[i + 1];
+            H[i] = t;
+        }
+        const double den = hypot(H[j], H[j + 1]);
+        double cs = 1.0, sn = 0.0;
+        if (den > 0.0) { cs = H[j] / den; sn = H[j + 1] / den; }
+        gm[oCS + j] = cs;
+        gm[oSN + j] = sn;
+        H[j] = den;
+        H[j + 1] = 0.0;
+        gm[oG + j + 1] = -sn * gm[oG + j];
+        gm[oG + j] = cs * gm[oG + j];
+        c->iters += 1;
+        c->gm_k = j + 1;
+        c->gm_j = j + 1;
+        const double res = gm[oG + j + 1];
+        c->rr = res * res;
+        c->gm_hnext = hnext;
+        c->gm_scale = hnext > 0.0 ? 1.0 / hnext : 0.0;
+        if (!gm_isfinite(res)) { c->status = 4; c->done = 1; }
+        else if (res * res <= c->thresh || hnext == 0.0) c->done = 1;
+        else if (c->iters >= c->maxit) { c->status = 2; c->done = 1; }
+        else if (j + 1 >= m) c->done = 2;   // cycle full: restart
+    }
+}
+
+__global__ void k_gm_restart(Ctrl* c) {
+    if (threadIdx.x == 0 && c->done == 2) c->done = 0;
+}
+
+inline int ggrid(long N) {
+    long g = (N + GT * 4 - 1) / (GT * 4);
+    if (g > kGmGrid) g = kGmGrid;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+}  // namespace
+
+int gm_grid(long N) { return ggrid(N); }
+
+#define FSD_NV_DISPATCH(KER, T, nv, ...)                                                     \
+    do {                                                                                     \
+        if ((nv) <= 8) hipLaunchKernelGGL((KER<T, 8>), __VA_ARGS__);                         \
+        else if ((nv) <= 24) hipLaunchKernelGGL((KER<T, 24>), __VA_ARGS__);                  \
+        else hipLaunchKernelGGL((KER<T, kMaxRestart + 1>), __VA_ARGS__);                     \
+    } while (0)
+
+template <typename T>
+hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* partials,
+                   const Ctrl* ctrl, int* nparts, hipStream_t s) {
+    const int g = ggrid(N);
+    *nparts = g;
+    FSD_NV_DISPATCH(k_mdot, T, nv, dim3(g), dim3(GT), 0, s, V, ld, nv, w, N, partials, ctrl);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, const Ctrl* ctrl,
+                    int hoff, int want_dots, double* partials, int* nparts, hipStream_t s) {
+    const int g = ggrid(N);
+    *nparts = g;
+    FSD_NV_DISPATCH(k_maxpy, T, nv, dim3(g), dim3(GT), 0, s, V, ld, nv, in, out, N, ctrl, hoff,
+                    want_dots, partials);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ctrl, int yoff,
+                     hipStream_t s) {
+    const int g = ggrid(N);
+    FSD_NV_DISPATCH(k_gm_update, T, kmax, dim3(g), dim3(GT), 0, s, x, V, ld, N, ctrl, yoff);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t gm_scale(const T* in, T* out, long N, const Ctrl* ctrl, hipStream_t s) {
+    hipLaunchKernelGGL((k_scale<T>), dim3(ggrid(N)), dim3(GT), 0, s, in, out, N, ctrl);
+    return hipGetLastError();
+}
+
+hipError_t gm_scalar(Ctrl* c, const double* partials, int nparts, int nv, int j, int op,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_scalar, dim3(1), dim3(GT), 0, s, c, partials, nparts, nv, j, op);
+    return hipGetLastError();
+}
+
+hipError_t gm_restart(Ctrl* c, hipStream_t s) {
+    hipLaunchKernelGGL(k_gm_restart, dim3(1), dim3(64), 0, s, c);
+    return hipGetLastError();
+}
+
+#define FSD_GM_INST(T)                                                                          \
+    template hipError_t gm_mdot<T>(const T*, long, int, const T*, long, double*, const Ctrl*,   \
+                                   int*, hipStream_t);                                          \
+    template hipError_t gm_maxpy<T>(const T*, long, int, const T*, T*, long, const Ctrl*, int,  \
+                                    int, double*, int*, hipStream_t);                           \
+    template hipError_t gm_update<T>(T*, const T*, long, long, int, const Ctrl*, int,           \
+                                     hipStream_t);                                              \
+    template hipError_t gm_scale<T>(const T*, T*, long, const Ctrl*, hipStream_t);
+
+FSD_GM_INST(double)
+FSD_GM_INST(float)
+
+}  // namespace fsd

@@ -1,0 +1,897 @@
+// C ABI (include/fsd.h): parameter validation, workspace layout, operator
+// pass sequences, and the device-resident PCG / left-GMRES / mixed-precision
+// defect-correction drivers.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "fsd_gmres.h"
+#include "fsd_host.h"
+#include "fsd_vec.h"
+
+using namespace fsd;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fsd_status fail(fsd_status s, const std::string& msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(FSD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// ------------------------------------------------------------ profiling
+
+enum Kind : int {
+    K_TOEP_X, K_TOEP_Y, K_TOEP_Z, K_DST_X, K_DST_Y, K_DSTS_Y, K_DSTS_Z,
+    K_GM_MDOT, K_GM_MAXPY, K_GM_UPDATE, K_PCG_UPDATE, K_NKINDS
+};
+const char* const kKindNames[K_NKINDS] = {"toep_x", "toep_y", "toep_z", "dst_x", "dst_y",
+                                          "dsts_y", "dsts_z", "gm_mdot", "gm_maxpy",
+                                          "gm_update", "pcg_update"};
+
+hipEvent_t prof_event(fsd_problem P) {
+    if (P->prof_next < P->prof_pool.size()) return P->prof_pool[P->prof_next++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    P->prof_pool.push_back(e);
+    P->prof_next = P->prof_pool.size();
+    return e;
+}
+
+// Records hipEvents on the problem's stream around the launches in its scope.
+struct ProfScope {
+    fsd_problem P;
+    int kind;
+    double bytes;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(fsd_problem P_, int kind_, bool f32, double bytes_)
+        : P(P_), kind(kind_ * 2 + (f32 ? 1 : 0)), bytes(bytes_) {
+        if (!P->prof_on) return;
+        a = prof_event(P);
+        b = prof_event(P);
+        if (a && b) (void)hipEventRecord(a, P->stream);
+        else a = nullptr;
+    }
+    ~ProfScope() {
+        if (!a) return;
+        (void)hipEventRecord(b, P->stream);
+        P->prof.push_back(ProfRec{kind, a, b, bytes});
+    }
+};
+
+template <typename T>
+constexpr bool is_f32() { return sizeof(T) == 4; }
+
+// ------------------------------------------------------------ layout
+
+struct Bump {
+    char* base;
+    size_t off = 0;
+    template <typename T>
+    T* take(size_t count) {
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off = align256(off + count * sizeof(T));
+        return p;
+    }
+};
+
+template <typename T>
+void layout_tables(fsd_problem P, Bump& B, Tables<T>& t) {
+    for (int i = 0; i < P->dim; ++i) {
+        const int L = P->ax[i].L, n = P->ax[i].n;
+        t.tw[i] = B.take<T>(2 * (size_t)L);
+        t.specA[i] = B.take<T>(2 * (size_t)L);
+        t.specR[i] = B.take<T>(2 * (size_t)L);
+        t.a[i] = B.take<T>((size_t)n);
+        t.lc[i] = B.take<T>((size_t)n);
+    }
+}
+
+template <typename T>
+void layout_vecs(fsd_problem P, Bump& B, Vecs<T>& v, bool gmres) {
+    const size_t Np = (size_t)P->Np;
+    v.x = B.take<T>(Np);
+    v.r = B.take<T>(Np);
+    v.p = B.take<T>(Np);
+    v.q = B.take<T>(Np);
+    v.z = B.take<T>(Np);
+    v.b = B.take<T>(Np);
+    for (int i = 0; i < 4; ++i) v.t[i] = B.take<T>(Np);
+    if (gmres) {
+        v.V = B.take<T>(Np * (size_t)(P->restart + 1));
+        v.w = B.take<T>(Np);
+    }
+}
+
+size_t layout(fsd_problem P, char* base) {
+    Bump B{base};
+    P->ctrl = B.take<Ctrl>(0);
+    B.off = align256(kCtrlBytes);
+    const int nslots = std::max(2, P->restart + 2);
+    P->partials = B.take<double>((size_t)P->maxparts * nslots);
+    layout_tables<double>(P, B, P->t64);
+    if (P->mixed) layout_tables<float>(P, B, P->t32);
+    const bool gm = P->solver == FSD_SOLVER_PGMRES;
+    layout_vecs<double>(P, B, P->v64, gm && !P->mixed);
+    if (P->mixed) layout_vecs<float>(P, B, P->v32, gm);
+    return B.off;
+}
+
+// ------------------------------------------------------------ geometry
+
+PassGeo geo_x(fsd_problem P) {
+    PassGeo g{};
+    g.n = P->ax[0].n;
+    g.P1 = P->P1;
+    g.estride = 1;
+    g.nrows = (int)P->rows;
+    g.n1 = P->ax[0].n;
+    g.nx = P->ax[0].n;
+    return g;
+}
+
+PassGeo geo_y(fsd_problem P) {
+    PassGeo g{};
+    const int n2 = P->ax[1].n;
+    g.n = n2;
+    g.P1 = P->P1;
+    g.estride = P->P1;
+    g.ostride = (long)P->P1 * n2;
+    g.n_outer = P->dim == 3 ? P->ax[2].n : 1;
+    g.n1 = P->ax[0].n;
+    g.fr_i = 1;
+    g.fr_o = n2;
+    g.nx = P->ax[0].n;
+    return g;
+}
+
+PassGeo geo_z(fsd_problem P) {
+    PassGeo g{};
+    const int n2 = P->ax[1].n;
+    g.n = P->ax[2].n;
+    g.P1 = P->P1;
+    g.estride = (long)P->P1 * n2;
+    g.ostride = P->P1;
+    g.n_outer = n2;
+    g.n1 = P->ax[0].n;
+    g.fr_i = n2;
+    g.fr_o = 1;
+    g.nx = P->ax[0].n;
+    return g;
+}
+
+template <typename T> Tables<T>& tabs(fsd_problem P);
+template <> Tables<double>& tabs<double>(fsd_problem P) { return P->t64; }
+template <> Tables<float>& tabs<float>(fsd_problem P) { return P->t32; }
+template <typename T> Vecs<T>& vecs(fsd_problem P);
+template <> Vecs<double>& vecs<double>(fsd_problem P) { return P->v64; }
+template <> Vecs<float>& vecs<float>(fsd_problem P) { return P->v32; }
+
+// ------------------------------------------------------------ operators
+// Matvec (Section 2, ``linear_sys``), factored axis by axis:
+//   x pass:  c = (A1 + s eta1 B1) u,  a = A1 u
+//   y pass:  d = A2 c + s eta2 B2 a,  e = A2 a      (2D: d is the result)
+//   z pass:  y = A3 d + s eta3 B3 e
+// so that y = A3 A2 (A1 + s eta1 B1) u + s eta2 A3 B2 A1 u + s eta3 B3 A2 A1 u,
+// with s = +1 for A and s = -1 for the right-hand-side operator.
+struct MatvecOpts {
+    bool rhs = false;
+    int epi = EPI_NONE;
+    const double* F = nullptr;
+    int pro = PRO_NONE;
+};
+
+template <typename T>
+fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, const T* dot_p,
+                     const T* bvec, T* pro_p, const Ctrl* ctrl, int* nparts) {
+    Tables<T>& tb = tabs<T>(P);
+    Vecs<T>& v = vecs<T>(P);
+    T *c = v.t[0], *a = v.t[1], *d = v.t[2], *e = v.t[3];
+    ToepArgs<T> A{};
+    A.g = geo_x(P);
+    A.u_fft = in;
+    A.o1 = c;
+    A.o2 = a;
+    A.spec = o.rhs ? tb.specR[0] : tb.specA[0];
+    A.tw = tb.tw[0];
+    A.pro = o.pro;
+    A.pro_p = pro_p;
+    A.ctrl = ctrl;
+    const double nb = (double)P->N * sizeof(T);
+    {
+        const int extra = o.pro == PRO_PUPDATE ? 2 : (o.pro == PRO_SCALE ? 1 : 0);
+        ProfScope ps(P, K_TOEP_X, is_f32<T>(), nb * (3 + extra));
+        HIP_TRY(launch_toep_x<T>(P->ax[0].L, A, nullptr, P->stream));
+    }
+    const double epi_bytes = o.epi == EPI_ADD_F ? (double)P->N * 8.0
+                           : (o.epi == EPI_DOT_P || o.epi == EPI_RESID) ? nb : 0.0;
+
+    ToepArgs<T> Y{};
+    Y.g = geo_y(P);
+    Y.u_fft = a;
+    Y.u_sten = c;
+    Y.spec = o.rhs ? tb.specR[1] : tb.specA[1];
+    Y.tw = tb.tw[1];
+    Y.ctrl = ctrl;
+    Y.dt = (double)(P->p.T / P->p.M);
+    if (P->dim == 2) {
+        Y.o1 = out;
+        Y.epi = o.epi;
+        Y.F = o.F;
+        Y.dot_p = dot_p;
+        Y.b = bvec;
+        Y.partials = P->partials;
+        ProfScope ps(P, K_TOEP_Y, is_f32<T>(), nb * 3 + epi_bytes);
+        HIP_TRY(launch_toep_s<T>(P->ax[1].L, Y, nparts, P->stream));
+        return FSD_OK;
+    }
+    Y.o1 = d;
+    Y.o2 = e;
+    {
+        ProfScope ps(P, K_TOEP_Y, is_f32<T>(), nb * 4);
+        HIP_TRY(launch_toep_s<T>(P->ax[1].L, Y, nullptr, P->stream));
+    }
+
+    ToepArgs<T> Z{};
+    Z.g = geo_z(P);
+    Z.u_fft = e;
+    Z.u_sten = d;
+    Z.o1 = out;
+    Z.spec = o.rhs ? tb.specR[2] : tb.specA[2];
+    Z.tw = tb.tw[2];
+    Z.epi = o.epi;
+    Z.F = o.F;
+    Z.dt = (double)(P->p.T / P->p.M);
+    Z.dot_p = dot_p;
+    Z.b = bvec;
+    Z.partials = P->partials;
+    Z.ctrl = ctrl;
+    ProfScope ps(P, K_TOEP_Z, is_f32<T>(), nb * 3 + epi_bytes);
+    HIP_TRY(launch_toep_s<T>(P->ax[2].L, Z, nparts, P->stream));
+    return FSD_OK;
+}
+
+// Preconditioner z = S_N Lambda^{-1} S_N r (Section 3, ``diag_tau_pre``):
+// DST-I along x, (y,) then DST-I / Lambda^{-1} / DST-I along the last axis,
+// then back.  With `partials`, the last-axis pass also leaves the Parseval
+// partial sums of (r, z).
+template <typename T>
+fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, double* partials,
+                      int* nparts) {
+    Tables<T>& tb = tabs<T>(P);
+    Vecs<T>& v = vecs<T>(P);
+    const int last = P->dim - 1;
+    auto mk = [&](int axis, PassGeo g, const T* u, T* o) {
+        DstArgs<T> D{};
+        D.g = g;
+        D.u = u;
+        D.o = o;
+        D.tw = tb.tw[axis];
+        D.c = (T)(0.5 * std::sqrt(2.0 / (P->ax[axis].n + 1)));
+        D.ctrl = ctrl;
+        D.dim = P->dim;
+        return D;
+    };
+    // forward x
+    const double nb = 2.0 * (double)P->N * sizeof(T);
+    DstArgs<T> X1 = mk(0, geo_x(P), in, v.t[0]);
+    {
+        ProfScope ps(P, K_DST_X, is_f32<T>(), nb);
+        HIP_TRY(launch_dst_x<T>(P->ax[0].L, X1, nullptr, P->stream));
+    }
+    const T* cur = v.t[0];
+    T* mid = v.t[1];
+    if (P->dim == 3) {
+        DstArgs<T> Y1 = mk(1, geo_y(P), cur, v.t[1]);
+        ProfScope ps(P, K_DST_Y, is_f32<T>(), nb);
+        HIP_TRY(launch_dst_s<T>(P->ax[1].L, Y1, nullptr, P->stream));
+        cur = v.t[1];
+        mid = v.t[2];
+    }
+    DstArgs<T> S = mk(last, last == 1 ? geo_y(P) : geo_z(P), cur, mid);
+    S.a_last = tb.a[last];
+    S.lc_last = tb.lc[last];
+    S.a1 = tb.a[0];
+    S.lc1 = tb.lc[0];
+    if (P->dim == 3) { S.a2 = tb.a[1]; S.lc2 = tb.lc[1]; }
+    S.partials = partials;
+    {
+        ProfScope ps(P, last == 1 ? K_DSTS_Y : K_DSTS_Z, is_f32<T>(), nb);
+        HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream));
+    }
+    cur = mid;
+    if (P->dim == 3) {
+        DstArgs<T> Y2 = mk(1, geo_y(P), cur, v.t[3]);
+        ProfScope ps(P, K_DST_Y, is_f32<T>(), nb);
+        HIP_TRY(launch_dst_s<T>(P->ax[1].L, Y2, nullptr, P->stream));
+        cur = v.t[3];
+    }
+    DstArgs<T> X2 = mk(0, geo_x(P), cur, out);
+    ProfScope ps(P, K_DST_X, is_f32<T>(), nb);
+    HIP_TRY(launch_dst_x<T>(P->ax[0].L, X2, nullptr, P->stream));
+    return FSD_OK;
+}
+
+#define FSD_TRY(expr)                          \
+    do {                                       \
+        fsd_status s_ = (expr);                \
+        if (s_ != FSD_OK) return s_;           \
+    } while (0)
+
+fsd_status read_ctrl(fsd_problem P) {
+    HIP_TRY(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return FSD_OK;
+}
+
+long default_maxit(fsd_problem P) {
+    if (P->p.maxit > 0) return P->p.maxit;
+    return std::min<long>(P->N, 1L << 30);
+}
+
+struct SolveOut {
+    long iters = 0;
+    double relres = 0.0;   // solver's own stopping quantity
+    int status = FSD_OK;
+};
+
+// ------------------------------------------------------------ PCG
+// Section 3.1: alpha = (r,z)/(p,Ap), x += alpha p, r -= alpha Ap,
+// z = P^{-1} r, beta = (r_new, z_new)/(r, z), p = z + beta p; stop when
+// ||r||_2 <= tol ||b||_2.  One iteration = 3 matvec passes (the p update
+// rides on the first, (p, Ap) on the last), one x/r update with ||r||^2,
+// 3 or 5 preconditioner passes ((r, z) by Parseval in the middle one) and
+// three one-workgroup scalar kernels.
+template <typename T>
+fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit, SolveOut& out) {
+    Vecs<T>& v = vecs<T>(P);
+    hipStream_t s = P->stream;
+    const long Np = P->Np;
+    int np = 0;
+    HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), P->restart, s));
+    HIP_TRY(vec_dot<T>(b, b, Np, P->partials, P->ctrl, &np, s));
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_BB, s));
+    if (x0_zero) {
+        HIP_TRY(vec_fill<T>(x, Np, T(0), s));
+        HIP_TRY(vec_copy<T>(b, v.r, Np, s));
+        HIP_TRY(vec_dot<T>(v.r, v.r, Np, P->partials, P->ctrl, &np, s));
+    } else {
+        MatvecOpts o;
+        o.epi = EPI_RESID;
+        FSD_TRY(op_matvec<T>(P, x, v.r, o, nullptr, b, nullptr, P->ctrl, &np));
+    }
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_RR0, s));
+    FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_RZ0, s));
+
+    int chunk = std::max(2, P->last_iters);
+    long enq = 0;
+    for (;;) {
+        for (int c = 0; c < chunk && enq < maxit; ++c, ++enq) {
+            MatvecOpts o;
+            o.epi = EPI_DOT_P;
+            o.pro = PRO_PUPDATE;
+            FSD_TRY(op_matvec<T>(P, v.z, v.q, o, v.p, nullptr, v.p, P->ctrl, &np));
+            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_ALPHA, s));
+            {
+                ProfScope ps(P, K_PCG_UPDATE, is_f32<T>(), 6.0 * (double)P->N * sizeof(T));
+                HIP_TRY(vec_update_xr<T>(x, v.r, v.p, v.q, Np, P->ctrl, P->partials, &np, s));
+            }
+            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_CHECK, s));
+            FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
+            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_BETA, s));
+        }
+        FSD_TRY(read_ctrl(P));
+        if (P->h_ctrl->done || enq >= maxit) break;
+        chunk = 2;
+    }
+    const Ctrl& c = *P->h_ctrl;
+    out.iters = c.iters;
+    out.relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
+    out.status = c.status;
+    if (c.bb == 0.0) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
+    if (!c.done && out.status == FSD_OK) out.status = FSD_ENOTCONV;
+    P->last_iters = std::max(1, (int)c.iters);
+    return FSD_OK;
+}
+
+// ------------------------------------------------------------ GMRES
+// Left-preconditioned restarted GMRES (Section 3.2, ``one_side_system``):
+// stop when ||P^{-1}(b - A x_k)||_2 <= tol ||P^{-1} b||_2.
+template <typename T>
+fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
+                 SolveOut& out) {
+    Vecs<T>& v = vecs<T>(P);
+    hipStream_t s = P->stream;
+    const long Np = P->Np;
+    const int m = P->restart;
+    int np = 0;
+    HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), m, s));
+    // ||P^{-1} b||
+    FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr));
+    HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
+    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s));
+    if (x0_zero) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
+    const int yoff = gm_off_y(m), h2off = gm_off_h2(m);
+    bool converged = false;
+    long total_enq = 0;
+    for (int cycle = 0; !converged; ++cycle) {
+        // r0 = P^{-1}(b - A x)
+        if (!(x0_zero && cycle == 0)) {   // with x = 0, w still holds P^{-1} b
+            MatvecOpts o;
+            o.epi = EPI_RESID;
+            FSD_TRY(op_matvec<T>(P, x, v.r, o, nullptr, b, nullptr, P->ctrl, &np));
+            FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr));
+        }
+        HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
+        HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
+        int chunk = std::max(2, P->last_iters);
+        int j = 0;
+        for (;;) {
+            for (int c = 0; c < chunk && j < m; ++c, ++j) {
+                T* vj = v.V + (long)j * Np;
+                // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
+                MatvecOpts o;
+                o.pro = PRO_SCALE;
+                FSD_TRY(op_matvec<T>(P, j == 0 ? v.w : vj, v.q, o, nullptr, nullptr, vj, P->ctrl,
+                                     &np));
+                FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr));
+                const double vb = (double)P->N * sizeof(T);
+                {
+                    ProfScope ps(P, K_GM_MDOT, is_f32<T>(), vb * (j + 2));
+                    HIP_TRY(gm_mdot<T>(v.V, Np, j + 1, v.w, Np, P->partials, P->ctrl, &np, s));
+                }
+                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H1, s));
+                {
+                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (j + 3));
+                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, v.w, Np, P->ctrl, j * (m + 1), 1,
+                                        P->partials, &np, s));
+                }
+                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H2, s));
+                {
+                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (j + 3));
+                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, v.V + (long)(j + 1) * Np, Np,
+                                        P->ctrl, h2off, 0, P->partials, &np, s));
+                }
+                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, j, GM_STEP, s));
+                ++total_enq;
+            }
+            FSD_TRY(read_ctrl(P));
+            if (P->h_ctrl->done || j >= m) break;
+            chunk = 2;
+        }
+        const Ctrl& c = *P->h_ctrl;
+        // x += V y over the columns of this cycle
+        HIP_TRY(gm_scalar(P->ctrl, P->partials, 0, 0, 0, GM_SOLVE, s));
+        {
+            ProfScope ps(P, K_GM_UPDATE, is_f32<T>(), (double)P->N * sizeof(T) * (c.gm_k + 2));
+            HIP_TRY(gm_update<T>(x, v.V, Np, Np, std::max(1, c.gm_k), P->ctrl, yoff, s));
+        }
+        if (c.done == 1) {
+            converged = true;
+            out.status = c.status;
+            break;
+        }
+        if (c.iters >= maxit) { out.status = FSD_ENOTCONV; break; }
+        HIP_TRY(gm_restart(P->ctrl, s));
+    }
+    FSD_TRY(read_ctrl(P));
+    const Ctrl& c = *P->h_ctrl;
+    out.iters = c.iters;
+    out.relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
+    if (c.bb == 0.0) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
+    if (out.status == FSD_OK && c.status != 0) out.status = c.status;
+    P->last_iters = std::max(1, (int)c.iters);
+    (void)total_enq;
+    return FSD_OK;
+}
+
+template <typename T>
+fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit, SolveOut& o) {
+    if (P->solver == FSD_SOLVER_PGMRES) return gmres<T>(P, x, b, x0_zero, tol, maxit, o);
+    return pcg<T>(P, x, b, x0_zero, tol, maxit, o);
+}
+
+// True residual r = b - A x in float64; *rnorm = ||r||_2.
+fsd_status true_residual(fsd_problem P, const double* x, const double* b, double* r, double* rnorm) {
+    hipStream_t s = P->stream;
+    int np = 0;
+    HIP_TRY(ctrl_init(P->ctrl, 0.0, 1, P->restart, s));
+    MatvecOpts o;
+    o.epi = EPI_RESID;
+    FSD_TRY(op_matvec<double>(P, x, r, o, nullptr, b, nullptr, nullptr, &np));
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
+    FSD_TRY(read_ctrl(P));
+    *rnorm = std::sqrt(P->h_ctrl->pq);
+    return FSD_OK;
+}
+
+fsd_status norm2(fsd_problem P, const double* b, double* nrm) {
+    hipStream_t s = P->stream;
+    int np = 0;
+    HIP_TRY(ctrl_init(P->ctrl, 0.0, 1, P->restart, s));
+    HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
+    FSD_TRY(read_ctrl(P));
+    *nrm = std::sqrt(P->h_ctrl->pq);
+    return FSD_OK;
+}
+
+// Solve A x = b on the internal padded vectors (x, b float64).
+fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zero, fsd_stats* st) {
+    const double tol = P->p.tol;
+    const long maxit = default_maxit(P);
+    fsd_stats S{};
+    if (!P->mixed) {
+        SolveOut o;
+        FSD_TRY(krylov<double>(P, x, b, x0_zero, tol, maxit, o));
+        S.iters = o.iters;
+        S.outer_iters = 1;
+        S.solver_relres = o.relres;
+        S.relres = o.relres;
+        S.status = o.status;
+        S.converged = o.status == FSD_OK;
+    } else {
+        // Defect correction: r = b - A x (float64); solve A d = r in float32
+        // to inner_tol; x += d; stop when ||b - A x|| <= tol ||b||.
+        Vecs<float>& f = P->v32;
+        double* r = P->v64.r;
+        if (x0_zero) HIP_TRY(vec_fill<double>(x, P->Np, 0.0, P->stream));
+        long iters = 0;
+        int outer = 0;
+        int status = FSD_ENOTCONV;
+        double relres = 0.0, bnorm = 0.0;
+        FSD_TRY(norm2(P, b, &bnorm));
+        for (;;) {
+            double rnorm = 0.0;
+            FSD_TRY(true_residual(P, x, b, r, &rnorm));
+            relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
+            if (!std::isfinite(relres)) { status = FSD_ENONFINITE; break; }
+            if (relres <= tol || rnorm == 0.0) { status = FSD_OK; break; }
+            if (outer >= P->p.max_outer || iters >= maxit) break;
+            HIP_TRY((vec_cast<double, float>(r, f.b, P->Np, 1.0 / rnorm, P->stream)));
+            SolveOut o;
+            const int saved = P->last_iters;
+            P->last_iters = P->last_inner_iters;
+            FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o));
+            P->last_inner_iters = P->last_iters;
+            P->last_iters = saved;
+            iters += o.iters;
+            ++outer;
+            if (o.status == FSD_ENONFINITE || o.status == FSD_EBREAKDOWN) { status = o.status; break; }
+            HIP_TRY(vec_axpy64<float>(x, f.x, P->Np, rnorm, P->stream));
+        }
+        S.iters = iters;
+        S.outer_iters = outer;
+        S.relres = relres;
+        S.solver_relres = relres;
+        S.status = status;
+        S.converged = status == FSD_OK;
+    }
+    if (st) *st = S;
+    if (S.status != FSD_OK) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "solve stopped: iters=%ld relres=%.3e", S.iters, S.relres);
+        return fail((fsd_status)S.status, buf);
+    }
+    return FSD_OK;
+}
+
+bool valid_delta(double d, bool allow0) { return allow0 ? (d >= 0.0 && d < 1.0) : (d > 0.0 && d < 1.0); }
+
+fsd_status check_bound(fsd_problem P) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    if (!P->bound) return fail(FSD_ENOTBOUND, "fsd_bind() has not been called");
+    return FSD_OK;
+}
+
+template <typename T>
+fsd_status upload_vec(fsd_problem P, T* dst, const std::vector<double>& src) {
+    std::vector<T> tmp(src.size());
+    for (size_t i = 0; i < src.size(); ++i) tmp[i] = (T)src[i];
+    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return FSD_OK;
+}
+
+template <typename T>
+fsd_status upload_all(fsd_problem P, Tables<T>& t) {
+    for (int i = 0; i < P->dim; ++i) {
+        const Axis& ax = P->ax[i];
+        FSD_TRY(upload_vec<T>(P, t.tw[i], ax.tw));
+        FSD_TRY(upload_vec<T>(P, t.specA[i], ax.specA));
+        FSD_TRY(upload_vec<T>(P, t.specR[i], ax.specR));
+        FSD_TRY(upload_vec<T>(P, t.a[i], ax.aeig));
+        std::vector<double> lc(ax.n);
+        const double ci = ax.eta * (ax.kp + ax.km);
+        for (int k = 0; k < ax.n; ++k) lc[k] = ci * ax.lam[k];
+        FSD_TRY(upload_vec<T>(P, t.lc[i], lc));
+    }
+    return FSD_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+
+extern "C" {
+
+const char* fsd_version(void) { return "fsd-mi355x 0.1.0 (gfx950)"; }
+
+const char* fsd_last_error(void) { return g_last_error.c_str(); }
+
+const char* fsd_status_string(fsd_status s) {
+    switch (s) {
+        case FSD_OK: return "ok";
+        case FSD_EINVAL: return "invalid argument";
+        case FSD_ENOTCONV: return "not converged";
+        case FSD_EBREAKDOWN: return "Krylov breakdown";
+        case FSD_ENONFINITE: return "non-finite value";
+        case FSD_ESMALLWS: return "workspace too small";
+        case FSD_EHIP: return "HIP runtime error";
+        case FSD_EUNSUPPORTED: return "unsupported grid size";
+        case FSD_ENOTBOUND: return "workspace not bound";
+    }
+    return "unknown status";
+}
+
+fsd_status fsd_default_params(fsd_params* p) {
+    if (!p) return fail(FSD_EINVAL, "null params");
+    std::memset(p, 0, sizeof *p);
+    p->dim = 3;
+    for (int i = 0; i < 3; ++i) {
+        p->n[i] = 63;
+        p->a[i] = 0.0;
+        p->b[i] = 1.0;
+        p->delta[i] = 0.5;
+        p->kplus[i] = 1.0;
+        p->kminus[i] = 1.0;
+    }
+    p->M = 1;
+    p->T = 1.0;
+    p->solver = FSD_SOLVER_AUTO;
+    p->restart = 20;
+    p->tol = 1e-9;
+    p->maxit = 0;
+    p->precision = FSD_PREC_FP64;
+    p->inner_tol = 1e-5;
+    p->max_outer = 8;
+    p->x0_mode = FSD_X0_PREV;
+    p->allow_delta_zero = 0;
+    return FSD_OK;
+}
+
+fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
+    if (!p || !out) return fail(FSD_EINVAL, "null argument");
+    *out = nullptr;
+    if (p->dim != 2 && p->dim != 3) return fail(FSD_EINVAL, "dim must be 2 or 3");
+    for (int i = 0; i < p->dim; ++i) {
+        char buf[200];
+        if (p->n[i] < 1) { snprintf(buf, sizeof buf, "n[%d] = %d < 1", i, p->n[i]); return fail(FSD_EINVAL, buf); }
+        if (!valid_delta(p->delta[i], p->allow_delta_zero != 0)) {
+            snprintf(buf, sizeof buf, "delta[%d] = %g outside (0, 1)", i, p->delta[i]);
+            return fail(FSD_EINVAL, buf);
+        }
+        if (!(p->kplus[i] > 0.0) || !(p->kminus[i] > 0.0)) {
+            snprintf(buf, sizeof buf, "k[%d] must be positive", i);
+            return fail(FSD_EINVAL, buf);
+        }
+        if (!(p->b[i] > p->a[i])) { snprintf(buf, sizeof buf, "empty domain on axis %d", i); return fail(FSD_EINVAL, buf); }
+        if (!length_supported(2 * (p->n[i] + 1))) {
+            snprintf(buf, sizeof buf,
+                     "n[%d] = %d: n+1 must be 2^a or 3*2^a with 2(n+1) <= 2048", i, p->n[i]);
+            return fail(FSD_EUNSUPPORTED, buf);
+        }
+    }
+    if (!(p->T > 0.0)) return fail(FSD_EINVAL, "T must be positive");
+    if (p->M < 1) return fail(FSD_EINVAL, "M must be >= 1");
+    if (!(p->tol > 0.0)) return fail(FSD_EINVAL, "tol must be positive");
+    if (p->restart < 1 || p->restart > kMaxRestart) return fail(FSD_EINVAL, "restart outside [1, 64]");
+    if (p->precision != FSD_PREC_FP64 && p->precision != FSD_PREC_MIXED)
+        return fail(FSD_EINVAL, "unknown precision");
+    if (p->precision == FSD_PREC_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
+        return fail(FSD_EINVAL, "inner_tol must be in (0, 1)");
+    if (p->solver < 0 || p->solver > 2) return fail(FSD_EINVAL, "unknown solver");
+    if (p->x0_mode < 0 || p->x0_mode > 2) return fail(FSD_EINVAL, "unknown x0_mode");
+
+    fsd_problem P = new (std::nothrow) fsd_problem_s();
+    if (!P) return fail(FSD_EINVAL, "out of host memory");
+    P->p = *p;
+    if (P->p.max_outer < 1) P->p.max_outer = 8;
+    P->dim = p->dim;
+    if (P->dim == 2) P->p.n[2] = 1;
+    const double dt = p->T / p->M;
+    for (int i = 0; i < P->dim; ++i) {
+        axis_setup(P->ax[i], p->n[i], p->a[i], p->b[i], p->delta[i], p->kplus[i], p->kminus[i], dt);
+        axis_spectra(P->ax[i], i);
+    }
+    P->symmetric = true;
+    for (int i = 0; i < P->dim; ++i) P->symmetric &= (p->kplus[i] == p->kminus[i]);
+    P->solver = p->solver == FSD_SOLVER_AUTO ? (P->symmetric ? FSD_SOLVER_PCG : FSD_SOLVER_PGMRES)
+                                             : p->solver;
+    P->mixed = p->precision == FSD_PREC_MIXED;
+    P->restart = p->restart;
+    P->P1 = (p->n[0] + 31) / 32 * 32;
+    P->rows = (long)p->n[1] * (P->dim == 3 ? p->n[2] : 1);
+    P->Np = (long)P->P1 * P->rows;
+    P->N = (long)p->n[0] * P->rows;
+    // partial-sum slots: the largest workgroup count of any reducing kernel
+    int mp = std::max(kVecGrid, kGmGrid);
+    for (int i = 1; i < P->dim; ++i) {
+        const int L = P->ax[i].L;
+        const long outer = (i == 1) ? (P->dim == 3 ? p->n[2] : 1) : p->n[1];
+        for (int f64 = 0; f64 < 2; ++f64) {
+            const int tx = 2 * lines_per_block(L, f64 != 0);
+            mp = std::max<long>(mp, (long)(P->P1 / tx) * outer);
+        }
+    }
+    P->maxparts = mp;
+    P->ws_bytes = layout(P, nullptr);
+    *out = P;
+    return FSD_OK;
+}
+
+void fsd_destroy(fsd_problem P) {
+    if (!P) return;
+    if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
+    for (hipEvent_t e : P->prof_pool) (void)hipEventDestroy(e);
+    delete P;
+}
+
+size_t fsd_workspace_bytes(fsd_problem P) { return P ? P->ws_bytes : 0; }
+
+fsd_status fsd_bind(fsd_problem P, void* d_ws, size_t bytes, void* stream) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    if (!d_ws) return fail(FSD_EINVAL, "null workspace");
+    if (((uintptr_t)d_ws & 255) != 0) return fail(FSD_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < P->ws_bytes) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "workspace has %zu bytes, needs %zu", bytes, P->ws_bytes);
+        return fail(FSD_ESMALLWS, buf);
+    }
+    P->ws = (char*)d_ws;
+    P->stream = (hipStream_t)stream;
+    layout(P, P->ws);
+    if (!P->h_ctrl) HIP_TRY(hipHostMalloc((void**)&P->h_ctrl, sizeof(Ctrl), hipHostMallocDefault));
+    // every vector starts at zero so the padding columns stay zero
+    HIP_TRY(hipMemsetAsync(P->ws, 0, P->ws_bytes, P->stream));
+    FSD_TRY(upload_all<double>(P, P->t64));
+    if (P->mixed) FSD_TRY(upload_all<float>(P, P->t32));
+    P->bound = true;
+    return FSD_OK;
+}
+
+fsd_status fsd_apply_A(fsd_problem P, const double* d_x, double* d_y) {
+    FSD_TRY(check_bound(P));
+    if (!d_x || !d_y) return fail(FSD_EINVAL, "null vector");
+    Vecs<double>& v = P->v64;
+    HIP_TRY(vec_pack<double>(d_x, v.p, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    MatvecOpts o;
+    FSD_TRY(op_matvec<double>(P, v.p, v.q, o, nullptr, nullptr, nullptr, nullptr, nullptr));
+    HIP_TRY(vec_unpack<double>(v.q, d_y, P->ax[0].n, P->P1, P->rows, P->stream));
+    return FSD_OK;
+}
+
+fsd_status fsd_apply_rhs(fsd_problem P, const double* d_u, const double* d_F, double* d_b) {
+    FSD_TRY(check_bound(P));
+    if (!d_u || !d_b) return fail(FSD_EINVAL, "null vector");
+    Vecs<double>& v = P->v64;
+    HIP_TRY(vec_pack<double>(d_u, v.p, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    MatvecOpts o;
+    o.rhs = true;
+    o.epi = d_F ? EPI_ADD_F : EPI_NONE;
+    o.F = d_F;
+    FSD_TRY(op_matvec<double>(P, v.p, v.q, o, nullptr, nullptr, nullptr, nullptr, nullptr));
+    HIP_TRY(vec_unpack<double>(v.q, d_b, P->ax[0].n, P->P1, P->rows, P->stream));
+    return FSD_OK;
+}
+
+fsd_status fsd_apply_Pinv(fsd_problem P, const double* d_r, double* d_z) {
+    FSD_TRY(check_bound(P));
+    if (!d_r || !d_z) return fail(FSD_EINVAL, "null vector");
+    Vecs<double>& v = P->v64;
+    HIP_TRY(vec_pack<double>(d_r, v.p, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    FSD_TRY(op_precond<double>(P, v.p, v.q, nullptr, nullptr, nullptr));
+    HIP_TRY(vec_unpack<double>(v.q, d_z, P->ax[0].n, P->P1, P->rows, P->stream));
+    return FSD_OK;
+}
+
+fsd_status fsd_solve(fsd_problem P, const double* d_b, double* d_x, fsd_stats* st) {
+    FSD_TRY(check_bound(P));
+    if (!d_b || !d_x) return fail(FSD_EINVAL, "null vector");
+    Vecs<double>& v = P->v64;
+    HIP_TRY(vec_pack<double>(d_b, v.b, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    HIP_TRY(vec_pack<double>(d_x, v.x, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    fsd_status s = solve_internal(P, v.x, v.b, false, st);
+    if (s == FSD_EHIP) return s;
+    HIP_TRY(vec_unpack<double>(v.x, d_x, P->ax[0].n, P->P1, P->rows, P->stream));
+    return s;
+}
+
+fsd_status fsd_cn_step(fsd_problem P, const double* d_u_prev, const double* d_F, const double* d_guess,
+                       double* d_u_next, fsd_stats* st) {
+    FSD_TRY(check_bound(P));
+    if (!d_u_prev || !d_u_next) return fail(FSD_EINVAL, "null vector");
+    if (P->p.x0_mode == FSD_X0_EXTERNAL && !d_guess) return fail(FSD_EINVAL, "x0_mode EXTERNAL needs a guess");
+    Vecs<double>& v = P->v64;
+    hipStream_t s = P->stream;
+    const int n1 = P->ax[0].n;
+    HIP_TRY(vec_pack<double>(d_u_prev, v.x, n1, P->P1, P->rows, 1.0, s));
+    // b = (A_N - K) u_prev + dt F
+    MatvecOpts o;
+    o.rhs = true;
+    o.epi = d_F ? EPI_ADD_F : EPI_NONE;
+    o.F = d_F;
+    FSD_TRY(op_matvec<double>(P, v.x, v.b, o, nullptr, nullptr, nullptr, nullptr, nullptr));
+    bool x0_zero = false;
+    if (P->p.x0_mode == FSD_X0_ZERO) x0_zero = true;
+    else if (P->p.x0_mode == FSD_X0_EXTERNAL)
+        HIP_TRY(vec_pack<double>(d_guess, v.x, n1, P->P1, P->rows, 1.0, s));
+    fsd_status stt = solve_internal(P, v.x, v.b, x0_zero, st);
+    if (stt == FSD_EHIP) return stt;
+    HIP_TRY(vec_unpack<double>(v.x, d_u_next, n1, P->P1, P->rows, s));
+    return stt;
+}
+
+fsd_status fsd_profile_enable(fsd_problem P, int on) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    P->prof_on = on != 0;
+    return FSD_OK;
+}
+
+int fsd_profile_read(fsd_problem P, fsd_profile_entry* out, int max) {
+    if (!P || (!out && max > 0)) { fail(FSD_EINVAL, "null argument"); return -1; }
+    if (P->stream || P->bound) {
+        hipError_t e = hipStreamSynchronize(P->stream);
+        if (e != hipSuccess) { fail(FSD_EHIP, hipGetErrorString(e)); return -1; }
+    }
+    long cnt[2 * K_NKINDS] = {0};
+    double ms[2 * K_NKINDS] = {0}, by[2 * K_NKINDS] = {0};
+    for (const ProfRec& r : P->prof) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) continue;
+        cnt[r.kind] += 1;
+        ms[r.kind] += t;
+        by[r.kind] += r.bytes;
+    }
+    P->prof.clear();
+    P->prof_next = 0;
+    int k = 0;
+    for (int i = 0; i < 2 * K_NKINDS; ++i) {
+        if (!cnt[i]) continue;
+        if (k < max) {
+            snprintf(out[k].name, sizeof out[k].name, "%s_%s", kKindNames[i / 2], (i & 1) ? "f32" : "f64");
+            out[k].launches = cnt[i];
+            out[k].total_ms = ms[i];
+            out[k].bytes = by[i];
+        }
+        ++k;
+    }
+    return std::min(k, max);
+}
+
+fsd_status fsd_get_coefficients(fsd_problem P, int axis, double* q, double* lam, double* eta) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    if (axis < 0 || axis >= P->dim) return fail(FSD_EINVAL, "axis out of range");
+    const Axis& ax = P->ax[axis];
+    if (q)
+        for (int k = 0; k <= ax.n; ++k) q[k] = (double)ax.q[k];
+    if (lam)
+        for (int k = 0; k < ax.n; ++k) lam[k] = ax.lam[k];
+    if (eta) *eta = ax.eta;
+    return FSD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// Host-side problem state (plan, workspace layout, device pointers).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "../../include/fsd.h"
+#include "fsd_internal.h"
+
+namespace fsd {
+
+struct Axis {
+    int n = 0, L = 0;
+    double h = 0, delta = 0, kp = 0, km = 0, eta = 0;
+    std::vector<long double> q;        // q_0..q_n
+    std::vector<double> aeig, lam;     // A_n and tau(H(T_n)) eigenvalues, k = 1..n
+    std::vector<double> specA, specR;  // pass spectra for A and for the right-hand side
+    std::vector<double> tw;            // twiddles exp(-2 pi i e/L), interleaved
+};
+
+void q_coefficients(double delta, int n, std::vector<long double>& q);
+void axis_setup(Axis& ax, int n, double a, double b, double delta, double kp, double km, double dt);
+void axis_spectra(Axis& ax, int axis_index);
+
+template <typename T>
+struct Tables {
+    T* tw[3] = {nullptr, nullptr, nullptr};
+    T* specA[3] = {nullptr, nullptr, nullptr};
+    T* specR[3] = {nullptr, nullptr, nullptr};
+    T* a[3] = {nullptr, nullptr, nullptr};    // A_n eigenvalues
+    T* lc[3] = {nullptr, nullptr, nullptr};   // eta_i (k+ + k-) * tau eigenvalues
+};
+
+template <typename T>
+struct Vecs {
+    T* x = nullptr;
+    T* r = nullptr;
+    T* p = nullptr;
+    T* q = nullptr;
+    T* z = nullptr;
+    T* b = nullptr;
+    T* t[4] = {nullptr, nullptr, nullptr, nullptr};
+    T* V = nullptr;   // GMRES basis, (restart + 1) vectors
+    T* w = nullptr;   // GMRES work vector
+};
+
+}  // namespace fsd
+
+namespace fsd {
+// One profiled launch: hipEvents recorded on the problem's stream around a
+// kernel, with the algorithmic bytes that launch moves.
+struct ProfRec {
+    int kind;
+    hipEvent_t a, b;
+    double bytes;
+};
+}  // namespace fsd
+
+struct fsd_problem_s {
+    fsd_params p{};
+    int dim = 3;
+    fsd::Axis ax[3];
+    int P1 = 0;           // padded pitch (n1 rounded up to 32)
+    long rows = 0;        // n2 * n3
+    long Np = 0;          // P1 * rows (padded vector length)
+    long N = 0;           // n1 * n2 * n3
+    bool symmetric = false;
+    int solver = FSD_SOLVER_PCG;
+    bool mixed = false;
+    int restart = 20;
+    int maxparts = 0;     // partial sums per reduction slot
+    size_t ws_bytes = 0;
+
+    bool bound = false;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    fsd::Ctrl* ctrl = nullptr;
+    double* partials = nullptr;
+    fsd::Tables<double> t64;
+    fsd::Tables<float> t32;
+    fsd::Vecs<double> v64;
+    fsd::Vecs<float> v32;
+    fsd::Ctrl* h_ctrl = nullptr;   // pinned host mirror of the ctrl header
+    int last_iters = 4;
+    int last_inner_iters = 4;
+
+    bool prof_on = false;
+    std::vector<fsd::ProfRec> prof;
+    std::vector<hipEvent_t> prof_pool;
+    size_t prof_next = 0;
+};

@@ -1,0 +1,140 @@
+// Internal declarations shared by the host plan/solver code and the HIP
+// kernels.  Not part of the public ABI (include/fsd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fsd {
+
+// Device-resident solver state.  Written only by the single-workgroup scalar
+// kernels (thread 0, vector stores); read by every kernel of a Krylov loop,
+// which returns at once when `done` is set so that iterations enqueued after
+// convergence cost a launch each and nothing else.
+struct Ctrl {
+    double bb;        // ||b||^2 (or ||P^{-1} b||^2 for left GMRES)
+    double rr;        // ||r||^2 of the current residual
+    double rz;        // (r, z) of PCG
+    double pq;        // (p, A p)
+    double alpha, beta;
+    double thresh;    // tol^2 * bb: stop when rr <= thresh
+    double tol2;
+    int iters;        // iterations taken in the current solve
+    int maxit;
+    int done;         // 1: converged or stopped
+    int status;       // fsd_status of the solve
+    int first;        // PCG: next p-update is p = z
+    int gm_j;         // GMRES: current Arnoldi column
+    int gm_m;         // GMRES: restart length
+    int gm_k;         // GMRES: columns in the current cycle
+    double gm_beta;   // GMRES: ||r0|| of the current cycle
+    double gm_hnext;  // GMRES: norm of the new basis vector before scaling
+    double gm_scale;  // GMRES: 1 / gm_hnext
+    double pad_[4];
+    // GMRES small dense state: H is (m+1) x m column-major, then cs, sn, g, y, h
+    double gm[1];
+};
+
+constexpr int kMaxRestart = 64;
+constexpr size_t kCtrlBytes = 256 + sizeof(double) * ((kMaxRestart + 1) * kMaxRestart
+                                                        + 6 * (kMaxRestart + 1) + 64);
+
+// Epilogue of the last matvec pass.
+enum Epi : int {
+    EPI_NONE = 0,
+    EPI_ADD_F = 1,    // o1 += dt * F (F dense float64 input)
+    EPI_DOT_P = 2,    // partial sums of (p, o1)
+    EPI_RESID = 3,    // o1 = b - o1, partial sums of ||o1||^2
+};
+
+// Prologue of the first matvec pass (x axis).
+enum Pro : int {
+    PRO_NONE = 0,
+    PRO_PUPDATE = 1,  // u = z + beta p (p = z when ctrl->first); p <- u
+    PRO_SCALE = 2,    // u = scale * u_in, scale = ctrl->gm_scale (GMRES v_{j+1} = w / h)
+};
+
+// Geometry of one pass over the padded internal layout.
+// The internal layout of a grid function is [n3][n2][P1] with P1 = n1
+// rounded up to a multiple of 32; columns x >= n1 hold zeros.
+struct PassGeo {
+    int n;            // line length (points along the pass axis)
+    int P1;           // padded row pitch
+    long estride;     // element stride along the line
+    long ostride;     // stride between outer indices (strided passes)
+    int n_outer;      // number of outer indices (strided passes)
+    int nrows;        // number of rows (x pass)
+    // dense (ABI) layout of F for EPI_ADD_F: index = x + n1 * (i*fr_i + o*fr_o)
+    int n1;
+    long fr_i, fr_o;
+    // preconditioner scale (strided DST-scale-DST pass)
+    int nx;           // n1 (lines with x >= n1 are padding)
+};
+
+template <typename T>
+struct ToepArgs {
+    PassGeo g;
+    const T* u_fft;       // input transformed by the Toeplitz factor
+    const T* u_sten;      // input of the tridiagonal stencil (may be null)
+    T* o1;                // Toeplitz(u_fft) [+ A(u_sten)] with epilogue
+    T* o2;                // A(u_fft) (may be null)
+    const T* spec;        // circulant spectrum, interleaved (re, im), L entries, 1/L folded
+    const T* tw;          // twiddles exp(-2 pi i e / L), interleaved, L entries
+    int epi;
+    const double* F;      // EPI_ADD_F
+    double dt;
+    const T* dot_p;       // EPI_DOT_P
+    const T* b;           // EPI_RESID
+    double* partials;     // one double per workgroup
+    int pro;
+    T* pro_p;             // PRO_PUPDATE: p (read and written)
+    const Ctrl* ctrl;     // may be null (no early exit, no beta)
+};
+
+template <typename T>
+struct DstArgs {
+    PassGeo g;
+    const T* u;
+    T* o;
+    const T* tw;
+    T c;                  // sqrt(2/(n+1)) / 2 per transform
+    // scale pass: Lambda = a_last[k] * P + lc_last[k] * Q per line
+    const T* a_last;      // eigenvalues of A_n on the pass axis
+    const T* lc_last;     // c_i * tau eigenvalues on the pass axis
+    const T* a1; const T* lc1;   // x axis factors
+    const T* a2; const T* lc2;   // y axis factors (3D scale pass only)
+    int dim;
+    double* partials;     // Parseval partials of (r, P^{-1} r)
+    const Ctrl* ctrl;
+};
+
+// ---------------------------------------------------------------- launchers
+// Each launcher dispatches on the transform length L = 2(n+1) of the pass.
+
+template <typename T> hipError_t launch_toep_x(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s);
+template <typename T> hipError_t launch_toep_s(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s);
+template <typename T> hipError_t launch_dst_x(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s);
+template <typename T> hipError_t launch_dst_s(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s);
+template <typename T> hipError_t launch_dsts_s(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s);
+
+// Complex lines per workgroup tile for transform length L (two real lines
+// each).  Sized so one tile plus its twiddle table stays below 80 KB of LDS
+// at L = 512, leaving room for two workgroups per CU (160 KB).
+__host__ __device__ constexpr int lines_per_block(int L, bool fp64) {
+    return fp64 ? (L <= 512 ? 8 : (L <= 1024 ? 4 : 2)) : (L <= 512 ? 16 : (L <= 1024 ? 8 : 4));
+}
+
+// Transform lengths with a compiled plan: L = 2(n+1) in {2^a, 3*2^a}, 4..2048.
+inline bool length_supported(int L) {
+    switch (L) {
+        case 4: case 6: case 8: case 12: case 16: case 24: case 32: case 48: case 64:
+        case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024:
+        case 1536: case 2048:
+            return true;
+        default:
+            return false;
+    }
+}
+
+}  // namespace fsd

@@ -1,0 +1,693 @@
+// Line-transform engine for gfx950: LDS-resident Stockham FFTs and the
+// per-axis passes of the Toeplitz matvec and of the sine-transform
+// preconditioner.
+//
+// Every pass applies a one-dimensional operator along one axis of a grid
+// function stored in the padded internal layout [n3][n2][P1] (x fastest,
+// P1 = n1 rounded up to 32, padding columns hold zeros):
+//   * Toeplitz passes (the multilevel Toeplitz matvec of Section 2,
+//     ``linear_sys``): y = Toep(u) [+ A_n w], with the Toeplitz factor applied
+//     by embedding it in a circulant of length L = 2(n+1) (Section 1 notes the
+//     FFT matvec) and diagonalising that circulant by an FFT.
+//   * DST passes (the preconditioner P = S_N Lambda S_N of Section 3,
+//     ``diag_tau_pre``): the orthonormal DST-I S_n along one axis, computed as
+//     an FFT of length L = 2(n+1) of the odd extension of the line; on the
+//     last axis the pass applies S_n, the diagonal Lambda^{-1} and S_n again.
+//
+// Two real lines share one complex FFT: the first goes in the real part, the
+// second in the imaginary part.  A real circulant maps (x1 + i x2) to
+// (C x1 + i C x2), and the DFT of an odd real extension is purely imaginary,
+// so both packings separate exactly.  Only forward FFTs are used: the inverse
+// of the Toeplitz product is taken as conj(FFT(conj(.))) with the conjugations
+// folded into the spectrum multiply and the output read.
+//
+// Workgroup tile: NCL complex lines (2*NCL real lines) of length L held in
+// LDS as split re/im arrays with one padding slot per 16 (double) or 32
+// (float) entries to spread bank accesses of the strided Stockham writes.
+// x passes take 2*NCL consecutive rows; y and z passes take 2*NCL
+// consecutive x positions (a 128-byte row segment) so every global access is
+// a coalesced row read or write.
+#pragma once
+
+#include "fsd_internal.h"
+
+namespace fsd {
+
+// ------------------------------------------------------------------ plans
+
+struct Plan {
+    int nst;
+    int r[8];
+};
+
+// Radix sequence for a length L = 2^a * 3^b: radix-8 stages first, then 4,
+// then 2, then 3.
+__host__ __device__ constexpr Plan make_plan(int L) {
+    Plan p{0, {0, 0, 0, 0, 0, 0, 0, 0}};
+    int x = L, f3 = 0;
+    while (x % 3 == 0) { x /= 3; ++f3; }
+    while (x >= 8 && x != 16) { p.r[p.nst++] = 8; x /= 8; }
+    while (x >= 4) { p.r[p.nst++] = 4; x /= 4; }
+    if (x == 2) { p.r[p.nst++] = 2; x /= 2; }
+    for (int i = 0; i < f3; ++i) p.r[p.nst++] = 3;
+    return p;
+}
+
+template <typename T, int L>
+struct Tile {
+    static constexpr bool kF64 = sizeof(T) == 8;
+    static constexpr int NCL = lines_per_block(L, kF64);
+    static constexpr int NT = 256;
+    static constexpr int TX = 2 * NCL;          // real lines per tile
+    static constexpr int SH = kF64 ? 4 : 5;     // LDS padding: one slot per 2^SH
+    static constexpr int LP = L + (L >> SH) + 1; // padded line pitch in LDS
+    __device__ static constexpr int idx(int e) { return e + (e >> SH); }
+};
+
+// ------------------------------------------------------------ butterflies
+// Forward DFT of size R on (xr, xi), sign exp(-2 pi i r s / R).
+
+template <typename T>
+__device__ inline void dft2(T* xr, T* xi) {
+    T ar = xr[0] + xr[1], ai = xi[0] + xi[1];
+    T br = xr[0] - xr[1], bi = xi[0] - xi[1];
+    xr[0] = ar; xi[0] = ai; xr[1] = br; xi[1] = bi;
+}
+
+template <typename T>
+__device__ inline void dft3(T* xr, T* xi) {
+    const T h = T(0.5);
+    const T s3 = T(0.86602540378443864676372317075294);  // sin(pi/3)
+    T tr = xr[1] + xr[2], ti = xi[1] + xi[2];
+    T dr = xr[1] - xr[2], di = xi[1] - xi[2];
+    T mr = xr[0] - h * tr, mi = xi[0] - h * ti;
+    xr[0] = xr[0] + tr; xi[0] = xi[0] + ti;
+    // c1 = m - i s3 d ; c2 = m + i s3 d
+    xr[1] = mr + s3 * di; xi[1] = mi - s3 * dr;
+    xr[2] = mr - s3 * di; xi[2] = mi + s3 * dr;
+}
+
+template <typename T>
+__device__ inline void dft4(T* xr, T* xi) {
+    T t0r = xr[0] + xr[2], t0i = xi[0] + xi[2];
+    T t1r = xr[0] - xr[2], t1i = xi[0] - xi[2];
+    T t2r = xr[1] + xr[3], t2i = xi[1] + xi[3];
+    T t3r = xr[1] - xr[3], t3i = xi[1] - xi[3];
+    xr[0] = t0r + t2r; xi[0] = t0i + t2i;
+    xr[2] = t0r - t2r; xi[2] = t0i - t2i;
+    // c1 = t1 - i t3 ; c3 = t1 + i t3
+    xr[1] = t1r + t3i; xi[1] = t1i - t3r;
+    xr[3] = t1r - t3i; xi[3] = t1i + t3r;
+}
+
+template <typename T>
+__device__ inline void dft8(T* xr, T* xi) {
+    const T r2 = T(0.70710678118654752440084436210485);
+    T er[4] = {xr[0], xr[2], xr[4], xr[6]}, ei[4] = {xi[0], xi[2], xi[4], xi[6]};
+    T orr[4] = {xr[1], xr[3], xr[5], xr[7]}, oi[4] = {xi[1], xi[3], xi[5], xi[7]};
+    dft4(er, ei);
+    dft4(orr, oi);
+    // twiddles w8^s, s = 0..3: 1, (1-i)/sqrt2, -i, -(1+i)/sqrt2
+    T w1r = r2 * (orr[1] + oi[1]), w1i = r2 * (oi[1] - orr[1]);
+    T w2r = oi[2], w2i = -orr[2];
+    T w3r = r2 * (oi[3] - orr[3]), w3i = -r2 * (orr[3] + oi[3]);
+    xr[0] = er[0] + orr[0]; xi[0] = ei[0] + oi[0];
+    xr[4] = er[0] - orr[0]; xi[4] = ei[0] - oi[0];
+    xr[1] = er[1] + w1r;    xi[1] = ei[1] + w1i;
+    xr[5] = er[1] - w1r;    xi[5] = ei[1] - w1i;
+    xr[2] = er[2] + w2r;    xi[2] = ei[2] + w2i;
+    xr[6] = er[2] - w2r;    xi[6] = ei[2] - w2i;
+    xr[3] = er[3] + w3r;    xi[3] = ei[3] + w3i;
+    xr[7] = er[3] - w3r;    xi[7] = ei[3] - w3i;
+}
+
+template <int R, typename T>
+__device__ inline void dft(T* xr, T* xi) {
+    if constexpr (R == 2) dft2(xr, xi);
+    else if constexpr (R == 3) dft3(xr, xi);
+    else if constexpr (R == 4) dft4(xr, xi);
+    else dft8(xr, xi);
+}
+
+// ---------------------------------------------------------------- stages
+// Stockham autosort stage with radix R after a span M (product of the
+// earlier radices): butterfly b reads X[b + r L/R], scales input r by
+// w^{r k} (w = exp(-2 pi i/(M R)), k = b mod M), and writes output s to
+// Y[(b / M) M R + k + s M].  In place: all reads of the stage land in
+// registers before a barrier, then all writes.
+
+template <typename T, int L, int R, int M>
+__device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
+                                 const T* __restrict__ twr, const T* __restrict__ twi,
+                                 int tid) {
+    using TL = Tile<T, L>;
+    constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
+    constexpr int NBL = L / R;
+    constexpr int NB = NCL * NBL;
+    constexpr int PER = (NB + NT - 1) / NT;
+    constexpr int TWS = L / (M * R);
+    T ar[PER][R], ai[PER][R];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int g = tid + q * NT;
+        if (NB % NT == 0 || g < NB) {
+            const int line = g / NBL;
+            const int b = g - line * NBL;
+            const T* lr = re + line * LP;
+            const T* li = im + line * LP;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int e = TL::idx(b + r * NBL);
+                ar[q][r] = lr[e];
+                ai[q][r] = li[e];
+            }
+            if constexpr (M > 1) {
+                const int k = b % M;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    const int t = r * k * TWS;
+                    const T wr = twr[t], wi = twi[t];
+                    const T xr = ar[q][r], xi = ai[q][r];
+                    ar[q][r] = xr * wr - xi * wi;
+                    ai[q][r] = xr * wi + xi * wr;
+                }
+            }
+            dft<R>(ar[q], ai[q]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int g = tid + q * NT;
+        if (NB % NT == 0 || g < NB) {
+            const int line = g / NBL;
+            const int b = g - line * NBL;
+            const int k = b % M;
+            const int j = b / M;
+            T* lr = re + line * LP;
+            T* li = im + line * LP;
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int e = TL::idx(j * M * R + k + s * M);
+                lr[e] = ar[q][s];
+                li[e] = ai[q][s];
+            }
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int L, int S, int M>
+struct FFTRun {
+    __device__ static inline void run(T* re, T* im, const T* twr, const T* twi, int tid) {
+        constexpr Plan P = make_plan(L);
+        if constexpr (S < P.nst) {
+            constexpr int R = P.r[S];
+            fft_stage<T, L, R, M>(re, im, twr, twi, tid);
+            FFTRun<T, L, S + 1, M * R>::run(re, im, twr, twi, tid);
+        }
+    }
+};
+
+// Forward FFT of all NCL lines of the tile (input and output in LDS).
+template <typename T, int L>
+__device__ inline void fft_lines(T* re, T* im, const T* twr, const T* twi, int tid) {
+    FFTRun<T, L, 0, 1>::run(re, im, twr, twi, tid);
+}
+
+// ------------------------------------------------------------- reductions
+
+template <int NT>
+__device__ inline double block_sum(double v, double* sbuf) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sbuf[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NT / 64; ++i) s += sbuf[i];
+    }
+    return s;
+}
+
+template <typename T, int L>
+__device__ inline void load_twiddles(const T* __restrict__ tw, T* twr, T* twi, int tid) {
+    constexpr int NT = Tile<T, L>::NT;
+    for (int e = tid; e < L; e += NT) {
+        twr[e] = tw[2 * e];
+        twi[e] = tw[2 * e + 1];
+    }
+}
+
+// Y = conj(C * Z) for every entry of every line (Toeplitz spectrum multiply).
+template <typename T, int L>
+__device__ inline void spectrum_multiply(T* re, T* im, const T* __restrict__ spec, int tid) {
+    using TL = Tile<T, L>;
+    for (int e = tid; e < TL::NCL * L; e += TL::NT) {
+        const int line = e / L, f = e - line * L;
+        const int a = line * TL::LP + TL::idx(f);
+        const T cr = spec[2 * f], ci = spec[2 * f + 1];
+        const T zr = re[a], zi = im[a];
+        re[a] = cr * zr - ci * zi;
+        im[a] = -(cr * zi + ci * zr);
+    }
+    __syncthreads();
+}
+
+// ------------------------------------------------------------ x-axis pass
+// Lines are rows (contiguous): tile = 2*NCL consecutive rows.
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_toep_x(ToepArgs<T> a) {
+    using TL = Tile<T, L>;
+    constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_twr[L], s_twi[L];
+    const int tid = threadIdx.x;
+    const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
+    const int row0 = blockIdx.x * (2 * NCL);
+    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+
+    T beta = 0, scale = 1;
+    bool first = true;
+    if (a.pro == PRO_PUPDATE) { first = a.ctrl->first != 0; beta = (T)a.ctrl->beta; }
+    if (a.pro == PRO_SCALE) scale = (T)a.ctrl->gm_scale;
+
+#pragma unroll
+    for (int rr = 0; rr < 2 * NCL; ++rr) {
+        const int row = row0 + rr;
+        T* dst = ((rr & 1) ? s_im : s_re) + (rr >> 1) * LP;
+        const bool rv = row < nrows;
+        const long base = (long)row * P1;
+        for (int i = tid; i < L; i += NT) {
+            T v = 0;
+            if (rv && i < n) {
+                if (a.pro == PRO_PUPDATE) {
+                    const T z = a.u_fft[base + i];
+                    v = first ? z : z + beta * a.pro_p[base + i];
+                    a.pro_p[base + i] = v;
+                } else if (a.pro == PRO_SCALE) {
+                    v = scale * a.u_fft[base + i];
+                    a.pro_p[base + i] = v;
+                } else {
+                    v = a.u_fft[base + i];
+                }
+            }
+            dst[TL::idx(i)] = v;
+        }
+    }
+    __syncthreads();
+
+    if (a.o2) {
+        // o2 = A_n u along x: (u_{i-1} + 6 u_i + u_{i+1}) / 8
+#pragma unroll
+        for (int rr = 0; rr < 2 * NCL; ++rr) {
+            const int row = row0 + rr;
+            if (row >= nrows) break;
+            const T* src = ((rr & 1) ? s_im : s_re) + (rr >> 1) * LP;
+            const long base = (long)row * P1;
+            for (int i = tid; i < n; i += NT) {
+                const T l = i > 0 ? src[TL::idx(i - 1)] : T(0);
+                const T c = src[TL::idx(i)];
+                const T r = src[TL::idx(i + 1)];
+                a.o2[base + i] = (l + T(6) * c + r) * T(0.125);
+            }
+        }
+    }
+
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    spectrum_multiply<T, L>(s_re, s_im, a.spec, tid);
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+
+#pragma unroll
+    for (int rr = 0; rr < 2 * NCL; ++rr) {
+        const int row = row0 + rr;
+        if (row >= nrows) break;
+        const long base = (long)row * P1;
+        for (int i = tid; i < n; i += NT) {
+            const int e = (rr >> 1) * LP + TL::idx(i);
+            a.o1[base + i] = (rr & 1) ? -s_im[e] : s_re[e];
+        }
+    }
+}
+
+// ------------------------------------------------------ strided y/z pass
+// Tile = 2*NCL consecutive x positions at one outer index; element (x, i)
+// of the tile sits at o*ostride + x + i*estride.
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_toep_s(ToepArgs<T> a) {
+    using TL = Tile<T, L>;
+    constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
+    constexpr int GRP = NT / TX;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_twr[L], s_twi[L];
+    __shared__ double s_red[NT / 64];
+    const int tid = threadIdx.x;
+    const int n = a.g.n, P1 = a.g.P1;
+    const long es = a.g.estride;
+    const int ntx = P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int x0 = xt * TX;
+    const int xl = tid % TX, ig = tid / TX;
+    const long base = (long)o * a.g.ostride + x0 + xl;
+    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+
+    T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    for (int i = ig; i < L; i += GRP) {
+        T v = 0;
+        if (i < n) v = a.u_fft[base + (long)i * es];
+        line[TL::idx(i)] = v;
+    }
+    __syncthreads();
+
+    // Padding lines (x >= n1) share a complex FFT with an interior line, so
+    // their outputs would carry that line's round-off; they are stored as
+    // exact zeros to keep every padding column identically zero.
+    const bool pad_line = x0 + xl >= a.g.nx;
+    if (a.o2) {
+        for (int i = ig; i < n; i += GRP) {
+            const T l = i > 0 ? line[TL::idx(i - 1)] : T(0);
+            const T c = line[TL::idx(i)];
+            const T r = line[TL::idx(i + 1)];
+            a.o2[base + (long)i * es] = pad_line ? T(0) : (l + T(6) * c + r) * T(0.125);
+        }
+    }
+
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    spectrum_multiply<T, L>(s_re, s_im, a.spec, tid);
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+
+    // Output: thread handles the contiguous chunk [ib, ie) of its line so the
+    // stencil on u_sten needs one new global load per output.
+    const int CH = (n + GRP - 1) / GRP;
+    const int ib = ig * CH;
+    const int ie = min(n, ib + CH);
+    const T sgn = (xl & 1) ? T(-1) : T(1);
+    const int x = x0 + xl;
+    double acc = 0.0;
+    const bool has_sten = a.u_sten != nullptr;
+    T prev = 0, cur = 0;
+    if (has_sten && ib < ie) {
+        prev = ib > 0 ? a.u_sten[base + (long)(ib - 1) * es] : T(0);
+        cur = a.u_sten[base + (long)ib * es];
+    }
+    for (int i = ib; i < ie; ++i) {
+        T v = sgn * line[TL::idx(i)];
+        if (has_sten) {
+            const T next = (i + 1 < n) ? a.u_sten[base + (long)(i + 1) * es] : T(0);
+            v += (prev + T(6) * cur + next) * T(0.125);
+            prev = cur;
+            cur = next;
+        }
+        const long gi = base + (long)i * es;
+        if (pad_line) v = T(0);
+        if (a.epi == EPI_ADD_F) {
+            if (x < a.g.n1)
+                v += (T)(a.dt * a.F[x + (long)a.g.n1 * ((long)i * a.g.fr_i + (long)o * a.g.fr_o)]);
+        } else if (a.epi == EPI_DOT_P) {
+            acc += (double)a.dot_p[gi] * (double)v;
+        } else if (a.epi == EPI_RESID) {
+            v = a.b[gi] - v;
+            acc += (double)v * (double)v;
+        }
+        a.o1[gi] = v;
+    }
+    if (a.epi == EPI_DOT_P || a.epi == EPI_RESID) {
+        const double s = block_sum<NT>(acc, s_red);
+        if (tid == 0) a.partials[blockIdx.x] = s;
+    }
+}
+
+// -------------------------------------------------------------- DST passes
+// Odd extension of two real lines (re: first, im: second):
+// V[0] = V[n+1] = 0, V[j] = u[j-1], V[L-j] = -u[j-1] (j = 1..n), L = 2(n+1).
+// After the FFT, DST(first)_k = -Im Z[k] * c2 and DST(second)_k = Re Z[k] * c2
+// with c2 = sqrt(2/(n+1))/2, k = 1..n.
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_dst_x(DstArgs<T> a) {
+    using TL = Tile<T, L>;
+    constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_twr[L], s_twi[L];
+    const int tid = threadIdx.x;
+    const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
+    const int row0 = blockIdx.x * (2 * NCL);
+    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+#pragma unroll
+    for (int rr = 0; rr < 2 * NCL; ++rr) {
+        const int row = row0 + rr;
+        T* dst = ((rr & 1) ? s_im : s_re) + (rr >> 1) * LP;
+        const long base = (long)row * P1;
+        const bool rv = row < nrows;
+        for (int i = tid; i < n; i += NT) {
+            const T v = rv ? a.u[base + i] : T(0);
+            dst[TL::idx(i + 1)] = v;
+            dst[TL::idx(L - 1 - i)] = -v;
+        }
+        if (tid == 0) { dst[TL::idx(0)] = 0; dst[TL::idx(n + 1)] = 0; }
+    }
+    __syncthreads();
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+#pragma unroll
+    for (int rr = 0; rr < 2 * NCL; ++rr) {
+        const int row = row0 + rr;
+        if (row >= nrows) break;
+        const long base = (long)row * P1;
+        for (int i = tid; i < n; i += NT) {
+            const int e = (rr >> 1) * LP + TL::idx(i + 1);
+            a.o[base + i] = (rr & 1) ? s_re[e] * a.c : -s_im[e] * a.c;
+        }
+    }
+}
+
+template <typename T, int L>
+__device__ inline void dst_load_strided(const T* __restrict__ u, T* line, long base, long es,
+                                        int n, int ig) {
+    using TL = Tile<T, L>;
+    constexpr int GRP = TL::NT / TL::TX;
+    for (int i = ig; i < n; i += GRP) {
+        const T v = u[base + (long)i * es];
+        line[TL::idx(i + 1)] = v;
+        line[TL::idx(L - 1 - i)] = -v;
+    }
+    if (ig == 0) { line[TL::idx(0)] = 0; line[TL::idx(n + 1)] = 0; }
+}
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_dst_s(DstArgs<T> a) {
+    using TL = Tile<T, L>;
+    constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
+    constexpr int GRP = NT / TX;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_twr[L], s_twi[L];
+    const int tid = threadIdx.x;
+    const int n = a.g.n, P1 = a.g.P1;
+    const long es = a.g.estride;
+    const int ntx = P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int xl = tid % TX, ig = tid / TX;
+    const long base = (long)o * a.g.ostride + xt * TX + xl;
+    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    dst_load_strided<T, L>(a.u, line, base, es, n, ig);
+    __syncthreads();
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    // the DST of the real-part line is -Im Z, of the imaginary-part line Re Z
+    const bool odd = xl & 1;
+    const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
+    const bool pad_line = xt * TX + xl >= a.g.nx;   // stored as exact zeros
+    for (int i = ig; i < n; i += GRP) {
+        const T z = other[TL::idx(i + 1)];
+        a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
+    }
+}
+
+// Last-axis pass of P^{-1}: DST-I, multiply by Lambda^{-1}, DST-I, with the
+// Parseval partial sums of (r, P^{-1} r) = sum_k |S_N r|_k^2 / Lambda_k.
+// Lambda on line (x, outer) at frequency k is a_last[k] * P + lc_last[k] * Q:
+//   2D (pass along y): P = a1 + lc1,                Q = a1        (x factors)
+//   3D (pass along z): P = a2 (a1 + lc1) + lc2 a1,  Q = a2 a1     (outer = y)
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_dsts_s(DstArgs<T> a) {
+    using TL = Tile<T, L>;
+    constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
+    constexpr int GRP = NT / TX;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_twr[L], s_twi[L];
+    __shared__ T s_P[TX], s_Q[TX];
+    __shared__ double s_red[NT / 64];
+    const int tid = threadIdx.x;
+    const int n = a.g.n, P1 = a.g.P1;
+    const long es = a.g.estride;
+    const int ntx = P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int x0 = xt * TX;
+    const int xl = tid % TX, ig = tid / TX;
+    const long base = (long)o * a.g.ostride + x0 + xl;
+    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    if (tid < TX) {
+        const int x = x0 + tid;
+        T P = 0, Q = 0;
+        if (x < a.g.nx) {
+            const T a1 = a.a1[x], l1 = a.lc1[x];
+            if (a.dim == 2) {
+                P = a1 + l1;
+                Q = a1;
+            } else {
+                const T a2 = a.a2[o], l2 = a.lc2[o];
+                P = a2 * (a1 + l1) + l2 * a1;
+                Q = a2 * a1;
+            }
+        }
+        s_P[tid] = P;
+        s_Q[tid] = Q;
+    }
+    T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    dst_load_strided<T, L>(a.u, line, base, es, n, ig);
+    __syncthreads();
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+
+    double acc = 0.0;
+    for (int e = tid; e < NCL * L; e += NT) {
+        const int ln = e / L, f = e - ln * L;
+        const int ad = ln * LP + TL::idx(f);
+        T wr = 0, wi = 0;
+        const int k = f <= n ? f : L - f;
+        if (k >= 1 && k <= n && f != n + 1) {
+            const T P0 = s_P[2 * ln], Q0 = s_Q[2 * ln];
+            const T P1v = s_P[2 * ln + 1], Q1v = s_Q[2 * ln + 1];
+            const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
+            const T lam0 = ak * P0 + lk * Q0;
+            const T lam1 = ak * P1v + lk * Q1v;
+            const T inv0 = P0 != T(0) ? T(1) / lam0 : T(0);
+            const T inv1 = P1v != T(0) ? T(1) / lam1 : T(0);
+            const T s1 = -s_im[ad] * a.c;
+            const T s2 = s_re[ad] * a.c;
+            wr = s1 * inv0;
+            wi = s2 * inv1;
+            if (f <= n) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
+        }
+        s_re[ad] = wr;
+        s_im[ad] = wi;
+    }
+    __syncthreads();
+    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    const bool odd = xl & 1;
+    const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
+    const bool pad_line = xt * TX + xl >= a.g.nx;   // stored as exact zeros
+    for (int i = ig; i < n; i += GRP) {
+        const T z = other[TL::idx(i + 1)];
+        a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
+    }
+    if (a.partials) {
+        const double s = block_sum<NT>(acc, s_red);
+        if (tid == 0) a.partials[blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+
+#define FSD_FOR_EACH_L(X) \
+    X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
+    X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+
+template <typename T>
+inline int x_blocks(int L, int nrows) {
+    int ncl = lines_per_block(L, sizeof(T) == 8);
+    return (nrows + 2 * ncl - 1) / (2 * ncl);
+}
+
+template <typename T>
+inline int s_blocks(int L, int P1, int n_outer) {
+    int ncl = lines_per_block(L, sizeof(T) == 8);
+    return (P1 / (2 * ncl)) * n_outer;
+}
+
+#define FSD_CASE_TOEP_X(LL) \
+    case LL: hipLaunchKernelGGL((k_toep_x<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+#define FSD_CASE_TOEP_S(LL) \
+    case LL: hipLaunchKernelGGL((k_toep_s<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+#define FSD_CASE_DST_X(LL) \
+    case LL: hipLaunchKernelGGL((k_dst_x<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+#define FSD_CASE_DST_S(LL) \
+    case LL: hipLaunchKernelGGL((k_dst_s<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+#define FSD_CASE_DSTS_S(LL) \
+    case LL: hipLaunchKernelGGL((k_dsts_s<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+
+#define FSD_DEFINE_LAUNCHERS(T)                                                              \
+    template <>                                                                              \
+    hipError_t launch_toep_x<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
+        using FT = T;                                                                        \
+        const int g = x_blocks<T>(L, a.g.nrows);                                             \
+        if (nb) *nb = g;                                                                     \
+        if (g == 0) return hipSuccess;                                                       \
+        switch (L) {                                                                         \
+            FSD_FOR_EACH_L(FSD_CASE_TOEP_X)                                                  \
+            default: return hipErrorInvalidValue;                                            \
+        }                                                                                    \
+        return hipGetLastError();                                                            \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_toep_s<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
+        using FT = T;                                                                        \
+        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);                                   \
+        if (nb) *nb = g;                                                                     \
+        if (g == 0) return hipSuccess;                                                       \
+        switch (L) {                                                                         \
+            FSD_FOR_EACH_L(FSD_CASE_TOEP_S)                                                  \
+            default: return hipErrorInvalidValue;                                            \
+        }                                                                                    \
+        return hipGetLastError();                                                            \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_dst_x<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
+        using FT = T;                                                                        \
+        const int g = x_blocks<T>(L, a.g.nrows);                                             \
+        if (nb) *nb = g;                                                                     \
+        if (g == 0) return hipSuccess;                                                       \
+        switch (L) {                                                                         \
+            FSD_FOR_EACH_L(FSD_CASE_DST_X)                                                   \
+            default: return hipErrorInvalidValue;                                            \
+        }                                                                                    \
+        return hipGetLastError();                                                            \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_dst_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
+        using FT = T;                                                                        \
+        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);                                   \
+        if (nb) *nb = g;                                                                     \
+        if (g == 0) return hipSuccess;                                                       \
+        switch (L) {                                                                         \
+            FSD_FOR_EACH_L(FSD_CASE_DST_S)                                                   \
+            default: return hipErrorInvalidValue;                                            \
+        }                                                                                    \
+        return hipGetLastError();                                                            \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_dsts_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {        \
+        using FT = T;                                                                        \
+        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);                                   \
+        if (nb) *nb = g;                                                                     \
+        if (g == 0) return hipSuccess;                                                       \
+        switch (L) {                                                                         \
+            FSD_FOR_EACH_L(FSD_CASE_DSTS_S)                                                  \
+            default: return hipErrorInvalidValue;                                            \
+        }                                                                                    \
+        return hipGetLastError();                                                            \
+    }
+
+}  // namespace fsd

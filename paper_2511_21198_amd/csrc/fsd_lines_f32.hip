@@ -1,0 +1,7 @@
+// float32 instantiations of the line-transform passes (inner solves of the
+// mixed-precision defect correction).
+#include "fsd_lines.hpp"
+
+namespace fsd {
+FSD_DEFINE_LAUNCHERS(float)
+}  // namespace fsd

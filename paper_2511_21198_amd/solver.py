@@ -1,0 +1,152 @@
+"""Thin Python front end of the C ABI: device memory and streams come from
+PyTorch, every computation runs in libfsd.so.
+
+    prob = Problem(dim=3, n=(127,)*3, delta=(0.3, 0.5, 0.7), kplus=(1,)*3,
+                   kminus=(1,)*3, M=32, T=1.0, tol=1e-10)
+    u = torch.zeros(prob.shape, dtype=torch.float64, device="cuda")
+    u, stats = prob.cn_step(u, F)
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence
+
+import torch
+
+from . import _native as nat
+from ._native import check, lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or t.dtype != torch.float64 or not t.is_contiguous():
+        raise ValueError("expected a contiguous float64 CUDA tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class Problem:
+    """One CN-FV problem bound to a caller-owned device workspace."""
+
+    def __init__(self, dim: int, n: Sequence[int], delta: Sequence[float],
+                 kplus: Sequence[float], kminus: Sequence[float], M: int = 1, T: float = 1.0,
+                 solver: str = "auto", restart: int = 20, tol: float = 1e-9, maxit: int = 0,
+                 precision: str = "fp64", inner_tol: float = 1e-5, max_outer: int = 8,
+                 x0: str = "prev", domain=None, allow_delta_zero: bool = False,
+                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+        p = nat.Params()
+        check(lib.fsd_default_params(C.byref(p)), "fsd_default_params")
+        p.dim = dim
+        for i in range(dim):
+            p.n[i] = int(n[i])
+            p.delta[i] = float(delta[i])
+            p.kplus[i] = float(kplus[i])
+            p.kminus[i] = float(kminus[i])
+            if domain is not None:
+                p.a[i], p.b[i] = float(domain[i][0]), float(domain[i][1])
+        p.M = int(M)
+        p.T = float(T)
+        p.solver = {"auto": nat.SOLVER_AUTO, "pcg": nat.SOLVER_PCG, "gmres": nat.SOLVER_PGMRES,
+                    "pgmres": nat.SOLVER_PGMRES}[solver]
+        p.restart = int(restart)
+        p.tol = float(tol)
+        p.maxit = int(maxit)
+        p.precision = {"fp64": nat.PREC_FP64, "mixed": nat.PREC_MIXED}[precision]
+        p.inner_tol = float(inner_tol)
+        p.max_outer = int(max_outer)
+        p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL}[x0]
+        p.allow_delta_zero = int(allow_delta_zero)
+        self.params = p
+        self.dim = dim
+        self.n = tuple(int(v) for v in n[:dim])
+        h = C.c_void_p()
+        check(lib.fsd_init_problem(C.byref(p), C.byref(h)), "fsd_init_problem")
+        self._h = h
+        self.device = torch.device(device or "cuda")
+        nbytes = int(lib.fsd_workspace_bytes(h))
+        # 256-byte alignment: over-allocate and offset
+        self._ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        off = (-base) % 256
+        self.stream = stream or torch.cuda.current_stream(self.device)
+        check(lib.fsd_bind(h, C.c_void_p(base + off), nbytes, C.c_void_p(self.stream.cuda_stream)),
+              "fsd_bind")
+        self.workspace_bytes = nbytes
+
+    @property
+    def shape(self):
+        return tuple(reversed(self.n))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.fsd_destroy(h)
+            self._h = None
+
+    def _out(self, out):
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        return out
+
+    def apply_A(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self._out(out)
+        check(lib.fsd_apply_A(self._h, _ptr(x), _ptr(out)), "fsd_apply_A")
+        return out
+
+    def apply_rhs(self, u: torch.Tensor, F: Optional[torch.Tensor] = None,
+                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self._out(out)
+        check(lib.fsd_apply_rhs(self._h, _ptr(u), _ptr(F), _ptr(out)), "fsd_apply_rhs")
+        return out
+
+    def apply_Pinv(self, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self._out(out)
+        check(lib.fsd_apply_Pinv(self._h, _ptr(r), _ptr(out)), "fsd_apply_Pinv")
+        return out
+
+    def solve(self, b: torch.Tensor, x: torch.Tensor, raise_on_error: bool = True):
+        st = nat.Stats()
+        s = lib.fsd_solve(self._h, _ptr(b), _ptr(x), C.byref(st))
+        if raise_on_error:
+            check(s, "fsd_solve")
+        return x, st.as_dict()
+
+    def cn_step(self, u_prev: torch.Tensor, F: Optional[torch.Tensor] = None,
+                guess: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                stats: bool = True, raise_on_error: bool = True):
+        out = self._out(out)
+        st = nat.Stats()
+        s = lib.fsd_cn_step(self._h, _ptr(u_prev), _ptr(F), _ptr(guess), _ptr(out),
+                            C.byref(st) if stats else None)
+        if raise_on_error:
+            check(s, "fsd_cn_step")
+        return out, (st.as_dict() if stats else None)
+
+    def profile(self, on: bool = True):
+        """Record hipEvents around every heavy kernel launch (see
+        fsd_profile_enable)."""
+        check(lib.fsd_profile_enable(self._h, int(on)), "fsd_profile_enable")
+
+    def profile_read(self):
+        """Per-kernel-kind totals since the last read: name -> dict(launches,
+        total_ms, bytes, avg_ms, gbps)."""
+        buf = (nat.ProfileEntry * 64)()
+        k = lib.fsd_profile_read(self._h, buf, 64)
+        if k < 0:
+            raise nat.FsdError(nat.EHIP, "fsd_profile_read")
+        out = {}
+        for e in buf[:k]:
+            avg = e.total_ms / max(e.launches, 1)
+            out[e.name.decode()] = dict(launches=e.launches, total_ms=e.total_ms, bytes=e.bytes,
+                                        avg_ms=avg,
+                                        gbps=(e.bytes / max(e.launches, 1)) / (avg * 1e-3) / 1e9
+                                        if avg > 0 else 0.0)
+        return out
+
+    def coefficients(self, axis: int):
+        n = self.n[axis]
+        q = (C.c_double * (n + 1))()
+        lam = (C.c_double * n)()
+        eta = C.c_double()
+        check(lib.fsd_get_coefficients(self._h, axis, q, lam, C.byref(eta)), "fsd_get_coefficients")
+        return list(q), list(lam), eta.value

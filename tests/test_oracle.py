@@ -326,3 +326,15 @@ def test_paper_iteration_counts(row):
     _, its = cn.run(prob, u0, F, tol=1e-9, x0_mode="zero",
                     maxit=(n1 - 1) ** 3, restart=20)
     assert round(float(np.mean(its)), 2) == it
+
+
+@pytest.mark.parametrize("prob", PROBS)
+def test_apply_A_at_sampled_entries(prob):
+    """Single entries of A X and of the right-hand-side operator from the
+    Kronecker rows agree with the full structured application."""
+    X = np.random.default_rng(8).standard_normal(prob.shape)
+    Y = op.apply_A(prob, X)
+    R = op.apply_rhs(prob, X, None)
+    for idx in np.ndindex(*prob.shape):
+        assert abs(op.apply_A_at(prob, X, idx) - Y[idx]) <= 1e-13 * np.abs(Y).max()
+        assert abs(op.apply_A_at(prob, X, idx, -1.0) - R[idx]) <= 1e-13 * np.abs(R).max()
