@@ -125,6 +125,15 @@ __host__ __device__ constexpr int lines_per_block(int L, bool fp64) {
     return fp64 ? (L <= 512 ? 8 : (L <= 1024 ? 4 : 2)) : (L <= 512 ? 16 : (L <= 1024 ? 8 : 4));
 }
 
+// Threads per workgroup tile: about one radix-8 butterfly per thread per
+// stage (NCL * L / 8), rounded down to a power of two in [64, 512].
+__host__ __device__ constexpr int threads_per_block(int L, bool fp64) {
+    int w = lines_per_block(L, fp64) * L / 8;
+    int t = 64;
+    while (t * 2 <= w && t < 512) t *= 2;
+    return t;
+}
+
 // Transform lengths with a compiled plan: L = 2(n+1) in {2^a, 3*2^a}, 4..2048.
 inline bool length_supported(int L) {
     switch (L) {

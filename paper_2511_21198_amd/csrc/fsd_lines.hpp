@@ -57,7 +57,7 @@ template <typename T, int L>
 struct Tile {
     static constexpr bool kF64 = sizeof(T) == 8;
     static constexpr int NCL = lines_per_block(L, kF64);
-    static constexpr int NT = 256;
+    static constexpr int NT = threads_per_block(L, kF64);
     static constexpr int TX = 2 * NCL;          // real lines per tile
     static constexpr int SH = kF64 ? 4 : 5;     // LDS padding: one slot per 2^SH
     static constexpr int LP = L + (L >> SH) + 1; // padded line pitch in LDS
@@ -260,7 +260,7 @@ __device__ inline void spectrum_multiply(T* re, T* im, const T* __restrict__ spe
 // Lines are rows (contiguous): tile = 2*NCL consecutive rows.
 
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_toep_x(ToepArgs<T> a) {
+__global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
     using TL = Tile<T, L>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
     if (a.ctrl && a.ctrl->done) return;
@@ -340,7 +340,7 @@ __global__ __launch_bounds__(256) void k_toep_x(ToepArgs<T> a) {
 // of the tile sits at o*ostride + x + i*estride.
 
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_toep_s(ToepArgs<T> a) {
+__global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
     using TL = Tile<T, L>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
     constexpr int GRP = NT / TX;
@@ -432,7 +432,7 @@ __global__ __launch_bounds__(256) void k_toep_s(ToepArgs<T> a) {
 // with c2 = sqrt(2/(n+1))/2, k = 1..n.
 
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_dst_x(DstArgs<T> a) {
+__global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
     using TL = Tile<T, L>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
     if (a.ctrl && a.ctrl->done) return;
@@ -484,7 +484,7 @@ __device__ inline void dst_load_strided(const T* __restrict__ u, T* line, long b
 }
 
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_dst_s(DstArgs<T> a) {
+__global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
     using TL = Tile<T, L>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
     constexpr int GRP = NT / TX;
@@ -520,7 +520,7 @@ __global__ __launch_bounds__(256) void k_dst_s(DstArgs<T> a) {
 //   2D (pass along y): P = a1 + lc1,                Q = a1        (x factors)
 //   3D (pass along z): P = a2 (a1 + lc1) + lc2 a1,  Q = a2 a1     (outer = y)
 template <typename T, int L>
-__global__ __launch_bounds__(256) void k_dsts_s(DstArgs<T> a) {
+__global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     using TL = Tile<T, L>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
     constexpr int GRP = NT / TX;
@@ -618,15 +618,15 @@ inline int s_blocks(int L, int P1, int n_outer) {
 }
 
 #define FSD_CASE_TOEP_X(LL) \
-    case LL: hipLaunchKernelGGL((k_toep_x<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+    case LL: hipLaunchKernelGGL((k_toep_x<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
 #define FSD_CASE_TOEP_S(LL) \
-    case LL: hipLaunchKernelGGL((k_toep_s<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+    case LL: hipLaunchKernelGGL((k_toep_s<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
 #define FSD_CASE_DST_X(LL) \
-    case LL: hipLaunchKernelGGL((k_dst_x<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+    case LL: hipLaunchKernelGGL((k_dst_x<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
 #define FSD_CASE_DST_S(LL) \
-    case LL: hipLaunchKernelGGL((k_dst_s<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+    case LL: hipLaunchKernelGGL((k_dst_s<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
 #define FSD_CASE_DSTS_S(LL) \
-    case LL: hipLaunchKernelGGL((k_dsts_s<FT, LL>), dim3(g), dim3(256), 0, s, a); break;
+    case LL: hipLaunchKernelGGL((k_dsts_s<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
 
 #define FSD_DEFINE_LAUNCHERS(T)                                                              \
     template <>                                                                              \
