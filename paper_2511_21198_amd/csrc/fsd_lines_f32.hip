@@ -1,7 +1,7 @@
 // float32 instantiations of the line-transform passes (inner solves of the
 // mixed-precision defect correction).
-#include "fsd_lines.hpp"
+#include "fsd_wave.hpp"
 
 namespace fsd {
-FSD_DEFINE_LAUNCHERS(float)
+FSD_DEFINE_LAUNCHERS2(float)
 }  // namespace fsd

@@ -1,6 +1,6 @@
 // float64 instantiations of the line-transform passes.
-#include "fsd_lines.hpp"
+#include "fsd_wave.hpp"
 
 namespace fsd {
-FSD_DEFINE_LAUNCHERS(double)
+FSD_DEFINE_LAUNCHERS2(double)
 }  // namespace fsd

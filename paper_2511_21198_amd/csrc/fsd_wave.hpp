@@ -1,0 +1,640 @@
+// Wave-resident line FFT engine for gfx950 (transform lengths L = 64..512).
+//
+// A group of G = L/8 lanes owns one complex line; lane tl of the group holds
+// the eight points tl + G q (q = 0..7) in registers.  Every Stockham stage
+// (radix 8, or 4 / 2 for the last one) works on registers: with that layout
+// the inputs of butterfly b = tl + G u are registers u + r (8/R), and the
+// last stage leaves the result in the same natural layout, so a forward FFT,
+// a pointwise spectrum multiply and a second forward FFT chain without any
+// data movement.  Between stages the group exchanges its line through a
+// private LDS region with wavefront-scope barriers only (the group never
+// spans two wavefronts), so workgroup barriers are needed only where a tile
+// is transposed between global rows and lines.
+//
+// Lines per wavefront: LW = 64/G; each lane may carry LPL lines at once
+// (LPL = 2 for float to give the float kernels the register reuse of the
+// double ones).
+#pragma once
+
+#include "fsd_lines.hpp"
+
+namespace fsd {
+
+// Wavefront-scope barrier with LDS ordering (release / acquire at
+// wavefront scope around the s_barrier-free wave barrier).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int L>
+struct WGeo {
+    static constexpr int G = L / 8;                  // lanes per line
+    static constexpr int LW = 64 / G;                // lines per wavefront
+    static constexpr int SH = sizeof(T) == 8 ? 4 : 5;
+    static constexpr int LP = L + (L >> SH) + 1;     // LDS pitch of one line
+    static constexpr int LPL = sizeof(T) == 8 ? 1 : 2;
+    __device__ static constexpr int idx(int e) { return e + (e >> SH); }
+};
+
+// Radix-R DFT on the registers u, u + 8/R, ..., u + (R-1) 8/R.
+template <int R, typename T>
+__device__ inline void dft_sub(T (&xr)[8], T (&xi)[8], int u) {
+    constexpr int S = 8 / R;
+    T ar[R], ai[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) { ar[r] = xr[u + r * S]; ai[r] = xi[u + r * S]; }
+    dft<R>(ar, ai);
+#pragma unroll
+    for (int r = 0; r < R; ++r) { xr[u + r * S] = ar[r]; xi[u + r * S] = ai[r]; }
+}
+
+// One stage (radix R, span M) on the registers of lane tl; twiddles read
+// from the interleaved global table tw (exp(-2 pi i e / L)).
+template <typename T, int L, int R, int M>
+__device__ inline void wstage(T (&xr)[8], T (&xi)[8], int tl, const T* __restrict__ tw) {
+    constexpr int G = L / 8, S = 8 / R, TWS = L / (M * R);
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        if constexpr (M > 1) {
+            const int k = (tl + G * u) % M;
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                const int t = r * k * TWS;
+                const T wr = tw[2 * t], wi = tw[2 * t + 1];
+                const int q = u + r * S;
+                const T a = xr[q], b = xi[q];
+                xr[q] = a * wr - b * wi;
+                xi[q] = a * wi + b * wr;
+            }
+        }
+        dft_sub<R, T>(xr, xi, u);
+    }
+}
+
+// Exchange after a non-final stage (radix R, span M): scatter the outputs
+// Y[(b/M) M R + b%M + s M] to the line region, read back X[tl + G q].
+template <typename T, int L, int R, int M>
+__device__ inline void wexchange(T (&xr)[8], T (&xi)[8], int tl, T* re, T* im) {
+    using W = WGeo<T, L>;
+    constexpr int G = W::G, S = 8 / R;
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+        const int b = tl + G * u;
+        const int base = (b / M) * M * R + b % M;
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+            const int e = W::idx(base + s * M);
+            re[e] = xr[u + s * S];
+            im[e] = xi[u + s * S];
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int e = W::idx(tl + G * q);
+        xr[q] = re[e];
+        xi[q] = im[e];
+    }
+    wave_sync();
+}
+
+template <typename T, int L, int S, int M>
+struct WRun {
+    __device__ static inline void run(T (&xr)[8], T (&xi)[8], int tl, const T* tw, T* re, T* im) {
+        constexpr Plan P = make_plan(L);
+        if constexpr (S < P.nst) {
+            constexpr int R = P.r[S];
+            wstage<T, L, R, M>(xr, xi, tl, tw);
+            if constexpr (S + 1 < P.nst) wexchange<T, L, R, M>(xr, xi, tl, re, im);
+            WRun<T, L, S + 1, M * R>::run(xr, xi, tl, tw, re, im);
+        }
+    }
+};
+
+// Forward FFT of one line held as points tl + G q; LDS region re/im of
+// length WGeo::LP is private to the lane group.
+template <typename T, int L>
+__device__ inline void wfft(T (&xr)[8], T (&xi)[8], int tl, const T* tw, T* re, T* im) {
+    WRun<T, L, 0, 1>::run(xr, xi, tl, tw, re, im);
+}
+
+// Toeplitz spectrum multiply in registers: Y = conj(C Z).
+template <typename T, int L>
+__device__ inline void wspec(T (&xr)[8], T (&xi)[8], int tl, const T* __restrict__ spec) {
+    constexpr int G = L / 8;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int f = tl + G * q;
+        const T cr = spec[2 * f], ci = spec[2 * f + 1];
+        const T zr = xr[q], zi = xi[q];
+        xr[q] = cr * zr - ci * zi;
+        xi[q] = -(cr * zi + ci * zr);
+    }
+}
+
+template <int L>
+constexpr bool wave_engine_length() {
+    return L == 64 || L == 128 || L == 256 || L == 512;
+}
+
+// ------------------------------------------------------------ x-axis pass
+// Workgroup: 4 wavefronts; each lane group handles LPL complex lines
+// (2 LPL rows).  No workgroup barrier: loads and stores go straight between
+// global rows and registers.
+
+template <typename T, int L>
+struct WX {
+    using W = WGeo<T, L>;
+    static constexpr int NW = 4;
+    static constexpr int NT = 64 * NW;
+    static constexpr int LINES = NW * W::LW * W::LPL;   // complex lines per workgroup
+};
+
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
+    using W = WGeo<T, L>;
+    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[WX<T, L>::LINES * LP];
+    __shared__ T s_im[WX<T, L>::LINES * LP];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / G, tl = lane % G;
+    const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
+    T beta = 0, scale = 1;
+    bool first = true;
+    if (a.pro == PRO_PUPDATE) { first = a.ctrl->first != 0; beta = (T)a.ctrl->beta; }
+    if (a.pro == PRO_SCALE) scale = (T)a.ctrl->gm_scale;
+
+    T xr[LPL][8], xi[LPL][8];
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+        T* re = s_re + (wave * LW * LPL + g + LW * p) * LP;
+        T* im = s_im + (wave * LW * LPL + g + LW * p) * LP;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 2 * line + h;
+            const bool rv = row < nrows;
+            const long base = (long)row * P1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = tl + G * q;
+                T v = 0;
+                if (rv && e < n) {
+                    if (a.pro == PRO_PUPDATE) {
+                        const T z = a.u_fft[base + e];
+                        v = first ? z : z + beta * a.pro_p[base + e];
+                        a.pro_p[base + e] = v;
+                    } else if (a.pro == PRO_SCALE) {
+                        v = scale * a.u_fft[base + e];
+                        a.pro_p[base + e] = v;
+                    } else {
+                        v = a.u_fft[base + e];
+                    }
+                }
+                if (h == 0) xr[p][q] = v; else xi[p][q] = v;
+            }
+        }
+        if (a.o2) {
+            // A_n u along x from the natural-order copy of the line
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = W::idx(tl + G * q);
+                re[e] = xr[p][q];
+                im[e] = xi[p][q];
+            }
+            wave_sync();
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = 2 * line + h;
+                if (row >= nrows) break;
+                const T* src = h ? im : re;
+                const long base = (long)row * P1;
+#pragma unroll
+                for (int q = 0; q < 8; ++q) {
+                    const int e = tl + G * q;
+                    if (e < n) {
+                        const T l = e > 0 ? src[W::idx(e - 1)] : T(0);
+                        const T r = src[W::idx(e + 1)];
+                        const T c = h ? xi[p][q] : xr[p][q];
+                        a.o2[base + e] = (l + T(6) * c + r) * T(0.125);
+                    }
+                }
+            }
+            wave_sync();
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+        wfft<T, L>(xr[p], xi[p], tl, a.tw, s_re + slot * LP, s_im + slot * LP);
+        wspec<T, L>(xr[p], xi[p], tl, a.spec);
+        wfft<T, L>(xr[p], xi[p], tl, a.tw, s_re + slot * LP, s_im + slot * LP);
+    }
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 2 * line + h;
+            if (row >= nrows) break;
+            const long base = (long)row * P1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int e = tl + G * q;
+                if (e < n) a.o1[base + e] = h ? -xi[p][q] : xr[p][q];
+            }
+        }
+    }
+}
+
+// DST-I of two real lines per complex line, x axis.
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
+    using W = WGeo<T, L>;
+    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[WX<T, L>::LINES * LP];
+    __shared__ T s_im[WX<T, L>::LINES * LP];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane / G, tl = lane % G;
+    const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
+    T xr[LPL][8], xi[LPL][8];
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 2 * line + h;
+            const bool rv = row < nrows;
+            const long base = (long)row * P1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                // odd extension: V[0] = V[n+1] = 0, V[j] = u[j-1], V[L-j] = -u[j-1]
+                const int e = tl + G * q;
+                T v = 0;
+                if (rv) {
+                    if (e >= 1 && e <= n) v = a.u[base + e - 1];
+                    else if (e >= n + 2) v = -a.u[base + (L - 1 - e)];
+                }
+                if (h == 0) xr[p][q] = v; else xi[p][q] = v;
+            }
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+        wfft<T, L>(xr[p], xi[p], tl, a.tw, s_re + slot * LP, s_im + slot * LP);
+    }
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int row = 2 * line + h;
+            if (row >= nrows) break;
+            const long base = (long)row * P1;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int k = tl + G * q;   // DST index k = 1..n -> output k-1
+                if (k >= 1 && k <= n) a.o[base + k - 1] = h ? xr[p][q] * a.c : -xi[p][q] * a.c;
+            }
+        }
+    }
+}
+
+template <typename T, int L, int GRP>
+__device__ inline void dst_load_strided_w(const T* __restrict__ u, T* line, long base, long es,
+                                          int n, int ig) {
+    using W = WGeo<T, L>;
+    for (int i = ig; i < n; i += GRP) {
+        const T v = u[base + (long)i * es];
+        line[W::idx(i + 1)] = v;
+        line[W::idx(L - 1 - i)] = -v;
+    }
+    if (ig == 0) { line[W::idx(0)] = 0; line[W::idx(n + 1)] = 0; }
+}
+
+// ------------------------------------------------------ strided y/z passes
+// Tile: NCL = 8 (double) or 16 (float) complex lines = 2 NCL consecutive x
+// positions (a 128-byte row segment) at one outer index.  Three workgroup
+// barriers: after the row loads, after the A_n stencil, before the row stores.
+
+template <typename T, int L>
+struct WS {
+    using W = WGeo<T, L>;
+    static constexpr int NCL = sizeof(T) == 8 ? 8 : 16;
+    static constexpr int TX = 2 * NCL;
+    static constexpr int NW = NCL / (W::LW * W::LPL);
+    static constexpr int NT = 64 * NW;
+    static constexpr int GRP = NT / TX;
+};
+
+template <typename T, int L>
+__global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
+    using W = WGeo<T, L>;
+    using S = WS<T, L>;
+    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    constexpr int NCL = S::NCL, TX = S::TX, NT = S::NT, GRP = S::GRP;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ double s_red[NT / 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane / G, tl = lane % G;
+    const int n = a.g.n, P1 = a.g.P1;
+    const long es = a.g.estride;
+    const int ntx = P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int x0 = xt * TX;
+    // row-transpose mapping
+    const int xl = tid % TX, ig = tid / TX;
+    const long base = (long)o * a.g.ostride + x0 + xl;
+    T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    for (int i = ig; i < n; i += GRP) rline[W::idx(i)] = a.u_fft[base + (long)i * es];
+    for (int i = n + ig; i < L; i += GRP) rline[W::idx(i)] = T(0);
+    __syncthreads();
+    const bool pad_line = x0 + xl >= a.g.nx;
+    if (a.o2) {
+        for (int i = ig; i < n; i += GRP) {
+            const T l = i > 0 ? rline[W::idx(i - 1)] : T(0);
+            const T c = rline[W::idx(i)];
+            const T r = rline[W::idx(i + 1)];
+            a.o2[base + (long)i * es] = pad_line ? T(0) : (l + T(6) * c + r) * T(0.125);
+        }
+    }
+    // lane groups pull their lines
+    T xr[LPL][8], xi[LPL][8];
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = W::idx(tl + G * q);
+            xr[p][q] = s_re[slot * LP + e];
+            xi[p][q] = s_im[slot * LP + e];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+        T* re = s_re + slot * LP;
+        T* im = s_im + slot * LP;
+        wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+        wspec<T, L>(xr[p], xi[p], tl, a.spec);
+        wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = W::idx(tl + G * q);
+            re[e] = xr[p][q];
+            im[e] = xi[p][q];
+        }
+    }
+    __syncthreads();
+    // row stores with the A_n stencil on u_sten and the epilogue
+    const int CH = (n + GRP - 1) / GRP;
+    const int ib = ig * CH;
+    const int ie = min(n, ib + CH);
+    const T sgn = (xl & 1) ? T(-1) : T(1);
+    const int x = x0 + xl;
+    double acc = 0.0;
+    const bool has_sten = a.u_sten != nullptr;
+    T prev = 0, cur = 0;
+    if (has_sten && ib < ie) {
+        prev = ib > 0 ? a.u_sten[base + (long)(ib - 1) * es] : T(0);
+        cur = a.u_sten[base + (long)ib * es];
+    }
+    for (int i = ib; i < ie; ++i) {
+        T v = sgn * rline[W::idx(i)];
+        if (has_sten) {
+            const T next = (i + 1 < n) ? a.u_sten[base + (long)(i + 1) * es] : T(0);
+            v += (prev + T(6) * cur + next) * T(0.125);
+            prev = cur;
+            cur = next;
+        }
+        const long gi = base + (long)i * es;
+        if (pad_line) v = T(0);
+        if (a.epi == EPI_ADD_F) {
+            if (x < a.g.n1)
+                v += (T)(a.dt * a.F[x + (long)a.g.n1 * ((long)i * a.g.fr_i + (long)o * a.g.fr_o)]);
+        } else if (a.epi == EPI_DOT_P) {
+            acc += (double)a.dot_p[gi] * (double)v;
+        } else if (a.epi == EPI_RESID) {
+            v = a.b[gi] - v;
+            acc += (double)v * (double)v;
+        }
+        a.o1[gi] = v;
+    }
+    if (a.epi == EPI_DOT_P || a.epi == EPI_RESID) {
+        const double s = block_sum<NT>(acc, s_red);
+        if (tid == 0) a.partials[blockIdx.x] = s;
+    }
+}
+
+// Strided DST pass; with SCALE, the last-axis pass S Lambda^{-1} S with the
+// Parseval partial sums of (r, P^{-1} r).
+template <typename T, int L, bool SCALE>
+__global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
+    using W = WGeo<T, L>;
+    using S = WS<T, L>;
+    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    constexpr int NCL = S::NCL, TX = S::TX, NT = S::NT, GRP = S::GRP;
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_P[TX], s_Q[TX];
+    __shared__ double s_red[NT / 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wave = tid >> 6;
+    const int g = lane / G, tl = lane % G;
+    const int n = a.g.n, P1 = a.g.P1;
+    const long es = a.g.estride;
+    const int ntx = P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int x0 = xt * TX;
+    const int xl = tid % TX, ig = tid / TX;
+    const long base = (long)o * a.g.ostride + x0 + xl;
+    if (SCALE && tid < TX) {
+        const int x = x0 + tid;
+        T P = 0, Q = 0;
+        if (x < a.g.nx) {
+            const T a1 = a.a1[x], l1 = a.lc1[x];
+            if (a.dim == 2) {
+                P = a1 + l1;
+                Q = a1;
+            } else {
+                const T a2 = a.a2[o], l2 = a.lc2[o];
+                P = a2 * (a1 + l1) + l2 * a1;
+                Q = a2 * a1;
+            }
+        }
+        s_P[tid] = P;
+        s_Q[tid] = Q;
+    }
+    T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    dst_load_strided_w<T, L, GRP>(a.u, rline, base, es, n, ig);
+    __syncthreads();
+    T xr[LPL][8], xi[LPL][8];
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = W::idx(tl + G * q);
+            xr[p][q] = s_re[slot * LP + e];
+            xi[p][q] = s_im[slot * LP + e];
+        }
+    }
+    __syncthreads();
+    double acc = 0.0;
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+        T* re = s_re + slot * LP;
+        T* im = s_im + slot * LP;
+        wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+        if constexpr (SCALE) {
+            const T P0 = s_P[2 * slot], Q0 = s_Q[2 * slot];
+            const T P1v = s_P[2 * slot + 1], Q1v = s_Q[2 * slot + 1];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int f = tl + G * q;
+                const int k = f <= n ? f : L - f;
+                T wr = 0, wi = 0;
+                if (k >= 1 && k <= n) {
+                    const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
+                    const T inv0 = P0 != T(0) ? T(1) / (ak * P0 + lk * Q0) : T(0);
+                    const T inv1 = P1v != T(0) ? T(1) / (ak * P1v + lk * Q1v) : T(0);
+                    const T s1 = -xi[p][q] * a.c;
+                    const T s2 = xr[p][q] * a.c;
+                    wr = s1 * inv0;
+                    wi = s2 * inv1;
+                    if (f <= n) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
+                }
+                xr[p][q] = wr;
+                xi[p][q] = wi;
+            }
+            wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = W::idx(tl + G * q);
+            re[e] = xr[p][q];
+            im[e] = xi[p][q];
+        }
+    }
+    __syncthreads();
+    const bool odd = xl & 1;
+    const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
+    const bool pad_line = x0 + xl >= a.g.nx;
+    for (int i = ig; i < n; i += GRP) {
+        const T z = other[W::idx(i + 1)];
+        a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
+    }
+    if (SCALE && a.partials) {
+        const double s = block_sum<NT>(acc, s_red);
+        if (tid == 0) a.partials[blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------------- dispatch
+// Lengths 64..512 use the wave engine; the others the LDS-stage engine of
+// fsd_lines.hpp.
+
+template <typename T, int L>
+hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
+    if constexpr (wave_engine_length<L>()) {
+        constexpr int rows = 2 * WX<T, L>::LINES;
+        const int g = (a.g.nrows + rows - 1) / rows;
+        if (nb) *nb = g;
+        if (g) hipLaunchKernelGGL((k2_toep_x<T, L>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
+    } else {
+        const int g = x_blocks<T>(L, a.g.nrows);
+        if (nb) *nb = g;
+        if (g) hipLaunchKernelGGL((k_toep_x<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t toep_s_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
+    const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
+    if (nb) *nb = g;
+    if (!g) return hipSuccess;
+    if constexpr (wave_engine_length<L>()) {
+        static_assert(WS<T, L>::TX == 2 * lines_per_block(L, sizeof(T) == 8), "tile width");
+        hipLaunchKernelGGL((k2_toep_s<T, L>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_toep_s<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int L>
+hipError_t dst_x_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
+    if constexpr (wave_engine_length<L>()) {
+        constexpr int rows = 2 * WX<T, L>::LINES;
+        const int g = (a.g.nrows + rows - 1) / rows;
+        if (nb) *nb = g;
+        if (g) hipLaunchKernelGGL((k2_dst_x<T, L>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
+    } else {
+        const int g = x_blocks<T>(L, a.g.nrows);
+        if (nb) *nb = g;
+        if (g) hipLaunchKernelGGL((k_dst_x<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int L, bool SCALE>
+hipError_t dst_s_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
+    const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
+    if (nb) *nb = g;
+    if (!g) return hipSuccess;
+    if constexpr (wave_engine_length<L>()) {
+        hipLaunchKernelGGL((k2_dst_s<T, L, SCALE>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
+    } else if constexpr (SCALE) {
+        hipLaunchKernelGGL((k_dsts_s<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_dst_s<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+#define FSD_W_CASE_TX(LL) case LL: return toep_x_one<FT, LL>(a, nb, s);
+#define FSD_W_CASE_TS(LL) case LL: return toep_s_one<FT, LL>(a, nb, s);
+#define FSD_W_CASE_DX(LL) case LL: return dst_x_one<FT, LL>(a, nb, s);
+#define FSD_W_CASE_DS(LL) case LL: return dst_s_one<FT, LL, false>(a, nb, s);
+#define FSD_W_CASE_DSS(LL) case LL: return dst_s_one<FT, LL, true>(a, nb, s);
+
+#define FSD_DEFINE_LAUNCHERS2(T)                                                              \
+    template <>                                                                              \
+    hipError_t launch_toep_x<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
+        using FT = T;                                                                        \
+        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_TX) default: return hipErrorInvalidValue; }   \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_toep_s<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
+        using FT = T;                                                                        \
+        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_TS) default: return hipErrorInvalidValue; }   \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_dst_x<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
+        using FT = T;                                                                        \
+        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_DX) default: return hipErrorInvalidValue; }   \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_dst_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
+        using FT = T;                                                                        \
+        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_DS) default: return hipErrorInvalidValue; }   \
+    }                                                                                        \
+    template <>                                                                              \
+    hipError_t launch_dsts_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {        \
+        using FT = T;                                                                        \
+        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_DSS) default: return hipErrorInvalidValue; }  \
+    }
+
+}  // namespace fsd
