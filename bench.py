@@ -95,6 +95,38 @@ def cpu_baseline(w):
                       f"float64 NumPy/SciPy oracle, {dt:.1f} s on {cpu_model()}"}
 
 
+def secondary_symmetric(a):
+    """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
+    PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
+    import torch
+    import workloads
+    from paper_2511_21198_amd.solver import Problem
+    w = workloads.config_3d_symmetric(seed=0, n=127, M=32)
+    F = torch.from_numpy(w.F).cuda()
+    u0 = torch.zeros_like(F)
+    common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
+                  solver="pcg", tol=w.tol, x0="prev")
+    out = {"workload": "3D symmetric 127^3, (alpha,beta,gamma)=(0.3,0.5,0.7), k=1, 32 CN steps "
+                       "to T=1, 8 seeded bumps, u0=0, PCG, tol 1e-10"}
+    us = {}
+    for name, kw in (("fp64", dict(precision="fp64")),
+                     ("mixed", dict(precision="mixed", inner_tol=1e-4))):
+        p = Problem(**common, **kw)
+        u, t, it, outer, _ = run_steps(p, u0, F, 8, 2)
+        us[name] = u
+        out[name] = {"steps_per_s": round(8 / t, 2), "iters": it, "outer": outer}
+        del p
+    pref = Problem(**{**common, "tol": 1e-13}, precision="fp64")
+    uref = u0.clone()
+    for _ in range(10):
+        uref, _ = pref.cn_step(uref, F)
+    for name in us:
+        out[name]["rel_err_vs_tight_fp64"] = float(torch.linalg.vector_norm(us[name] - uref)
+                                                   / torch.linalg.vector_norm(uref))
+    out["speedup"] = round(out["mixed"]["steps_per_s"] / out["fp64"]["steps_per_s"], 3)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +135,12 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
+    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--x0-mixed", default="prev", choices=["prev", "extrap"])
+    ap.add_argument("--no-ref", action="store_true",
+                    help="skip the tight float64 reference run used for the error figures")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 127^3 symmetric PCG comparison")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not "
@@ -130,10 +168,24 @@ def main(argv=None):
         del p64
     if a.only in ("mixed", "both"):
         log("mixed solver ...")
-        pmx = Problem(**common, precision="mixed", inner_tol=1e-4, max_outer=8)
+        pmx = Problem(**{**common, "x0": a.x0_mixed}, precision="mixed", inner_tol=a.inner_tol,
+                      max_outer=8)
         umx, tmx, itmx, outmx, profmx = run_steps(pmx, u0, F, a.steps, a.warmup, profile=True)
         res["mixed"] = dict(t=tmx, iters=itmx, outer=outmx, prof=profmx)
         del pmx
+    errs = {}
+    if not a.no_ref:
+        log("tight float64 reference (tol 1e-12, untimed) ...")
+        pref = Problem(**{**common, "tol": 1e-12}, precision="fp64")
+        uref = u0.clone()
+        for _ in range(a.warmup + a.steps):
+            uref, _ = pref.cn_step(uref, F)
+        del pref
+        nrm = torch.linalg.vector_norm(uref)
+        if "fp64" in res:
+            errs["fp64"] = float(torch.linalg.vector_norm(u64 - uref) / nrm)
+        if "mixed" in res:
+            errs["mixed"] = float(torch.linalg.vector_norm(umx - uref) / nrm)
     head = "mixed" if "mixed" in res else "fp64"
     T = res[head]["t"]
     value = a.steps / T
@@ -184,7 +236,11 @@ def main(argv=None):
         out["outer_mixed"] = res["mixed"]["outer"]
     if rel is not None:
         out["speedup_vs_fp64"] = round(out["fp64_steps_per_s"] and value / out["fp64_steps_per_s"], 3)
-        out["rel_err_mixed_vs_fp64"] = rel
+        out["rel_diff_mixed_vs_fp64"] = rel
+    if errs:
+        out["rel_err_vs_tight_fp64"] = errs
+    if not a.no_secondary:
+        out["secondary"] = secondary_symmetric(a)
     out["kernels"] = {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
                           "gbps": round(v["gbps"], 1), "total_ms": round(v["total_ms"], 3)}
                       for k, v in prof.items()}

@@ -77,7 +77,11 @@ typedef enum {
     FSD_X0_PREV = 0,       /* initial guess u^{m-1} */
     FSD_X0_ZERO = 1,       /* initial guess 0 (the setting that reproduces the
                               paper's iteration counts) */
-    FSD_X0_EXTERNAL = 2    /* initial guess passed to fsd_cn_step */
+    FSD_X0_EXTERNAL = 2,   /* initial guess passed to fsd_cn_step */
+    FSD_X0_EXTRAP = 3      /* 2 u^{m-1} - u^{m-2}: linear extrapolation in time
+                              from the previous call's u_prev (the history is
+                              kept in the workspace; u^{m-1} on the first call
+                              after fsd_bind or fsd_reset_history) */
 } fsd_x0_mode;
 
 /* Problem parameters.  Fill with fsd_default_params() first. */
@@ -167,6 +171,10 @@ fsd_status fsd_solve(fsd_problem prob, const double* d_b, double* d_x, fsd_stats
  * equal d_u_next.  st may be NULL. */
 fsd_status fsd_cn_step(fsd_problem prob, const double* d_u_prev, const double* d_F,
                        const double* d_guess, double* d_u_next, fsd_stats* st);
+
+/* Forget the time history used by FSD_X0_EXTRAP (call when the next
+ * fsd_cn_step does not continue the previous trajectory). */
+fsd_status fsd_reset_history(fsd_problem prob);
 
 /* Host copies of the per-axis coefficients (axis 0 = x):
  * q[0..n]   q_k of Section 2 (``coef_expression``), n+1 values;

@@ -22,7 +22,7 @@ SOLVER_AUTO, SOLVER_PCG, SOLVER_PGMRES = 0, 1, 2
 # fsd_precision
 PREC_FP64, PREC_MIXED = 0, 1
 # fsd_x0_mode
-X0_PREV, X0_ZERO, X0_EXTERNAL = 0, 1, 2
+X0_PREV, X0_ZERO, X0_EXTERNAL, X0_EXTRAP = 0, 1, 2, 3
 
 
 class Params(C.Structure):
@@ -86,6 +86,7 @@ SIGNATURES = {
     "fsd_cn_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)]),
     "fsd_get_coefficients": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
+    "fsd_reset_history": (C.c_int, [_VP]),
     "fsd_profile_enable": (C.c_int, [_VP, C.c_int]),
     "fsd_profile_read": (C.c_int, [_VP, C.POINTER(ProfileEntry), C.c_int]),
     "fsd_status_string": (C.c_char_p, [C.c_int]),

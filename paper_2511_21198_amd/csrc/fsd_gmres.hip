@@ -38,38 +38,73 @@ __device__ inline double block_sum(double v, double* sbuf) {
     return s;
 }
 
-// partials[i * G + blk] = sum_e V_i[e] w[e], i < nv (nv <= NVMAX)
+// Block sums of nv per-thread accumulators with one workgroup barrier:
+// wavefront reduction of each value, then one thread per value adds the
+// wavefront results in order.  Writes partials[i * gridDim.x + blockIdx.x].
+template <int NVMAX>
+__device__ inline void block_multi_sum(const double (&acc)[NVMAX], int nv, double* red,
+                                       double* __restrict__ partials) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NVMAX; ++i) {
+        if (i < nv) {
+            const double v = wave_sum(acc[i]);
+            if (lane == 0) red[w * NVMAX + i] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < nv) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < GT / 64; ++k) s += red[k * NVMAX + threadIdx.x];
+        partials[(long)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// partials[i * G + blk] = sum_e V_i[e] w[e], i < nv (nv <= NVMAX).  Each
+// thread takes two elements per iteration so that 2 (nv + 1) independent
+// loads are in flight.
 template <typename T, int NVMAX>
 __global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, int nv,
                                              const T* __restrict__ w, long N,
                                              double* __restrict__ partials, const Ctrl* ctrl) {
-    __shared__ double sb[GT / 64];
+    __shared__ double red[(GT / 64) * NVMAX];
     if (ctrl->done) return;
     double acc[NVMAX];
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
-    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT) {
+    const long stride = (long)gridDim.x * GT;
+    long e = blockIdx.x * (long)GT + threadIdx.x;
+    for (; e + stride < N; e += 2 * stride) {
+        const long e2 = e + stride;
+        const double w1 = (double)w[e], w2 = (double)w[e2];
+        T v1[NVMAX], v2[NVMAX];
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i) {
+            v1[i] = i < nv ? V[i * ld + e] : T(0);
+            v2[i] = i < nv ? V[i * ld + e2] : T(0);
+        }
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i) acc[i] += (double)v1[i] * w1 + (double)v2[i] * w2;
+    }
+    if (e < N) {
         const double we = (double)w[e];
 #pragma unroll
         for (int i = 0; i < NVMAX; ++i)
             if (i < nv) acc[i] += (double)V[i * ld + e] * we;
     }
-#pragma unroll
-    for (int i = 0; i < NVMAX; ++i) {
-        if (i < nv) {
-            const double s = block_sum(acc[i], sb);
-            if (threadIdx.x == 0) partials[(long)i * gridDim.x + blockIdx.x] = s;
-        }
-    }
+    block_multi_sum<NVMAX>(acc, nv, red, partials);
 }
 
 // out = in - sum_i h_i V_i (h from ctrl->gm + hoff); then either partial dots
-// V_i^T out (want_dots) or the partial ||out||^2.
+// V_i^T out (want_dots) or the partial ||out||^2.  Two elements per thread
+// per iteration.
 template <typename T, int NVMAX>
 __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, int nv,
                                               const T* in, T* out, long N, const Ctrl* ctrl,
                                               int hoff, int want_dots, double* __restrict__ partials) {
     __shared__ double sb[GT / 64];
+    __shared__ double red[(GT / 64) * NVMAX];
     if (ctrl->done) return;
     T h[NVMAX];
 #pragma unroll
@@ -78,30 +113,35 @@ __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, 
 #pragma unroll
     for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
     double nrm = 0.0;
-    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT) {
-        T v[NVMAX];
-        T o = in[e];
+    const long stride = (long)gridDim.x * GT;
+    for (long e0 = blockIdx.x * (long)GT + threadIdx.x; e0 < N; e0 += 2 * stride) {
+        const long e1 = e0 + stride;
+        const bool has1 = e1 < N;
+        T va[NVMAX], vb[NVMAX];
+        T oa = in[e0];
+        T ob = has1 ? in[e1] : T(0);
 #pragma unroll
         for (int i = 0; i < NVMAX; ++i) {
-            v[i] = i < nv ? V[i * ld + e] : T(0);
-            o -= h[i] * v[i];
+            va[i] = i < nv ? V[i * ld + e0] : T(0);
+            vb[i] = (i < nv && has1) ? V[i * ld + e1] : T(0);
         }
-        out[e] = o;
+#pragma unroll
+        for (int i = 0; i < NVMAX; ++i) {
+            oa -= h[i] * va[i];
+            ob -= h[i] * vb[i];
+        }
+        out[e0] = oa;
+        if (has1) out[e1] = ob;
         if (want_dots) {
 #pragma unroll
-            for (int i = 0; i < NVMAX; ++i) acc[i] += (double)v[i] * (double)o;
+            for (int i = 0; i < NVMAX; ++i)
+                acc[i] += (double)va[i] * (double)oa + (double)vb[i] * (double)ob;
         } else {
-            nrm += (double)o * (double)o;
+            nrm += (double)oa * (double)oa + (double)ob * (double)ob;
         }
     }
     if (want_dots) {
-#pragma unroll
-        for (int i = 0; i < NVMAX; ++i) {
-            if (i < nv) {
-                const double s = block_sum(acc[i], sb);
-                if (threadIdx.x == 0) partials[(long)i * gridDim.x + blockIdx.x] = s;
-            }
-        }
+        block_multi_sum<NVMAX>(acc, nv, red, partials);
     } else {
         const double s = block_sum(nrm, sb);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;

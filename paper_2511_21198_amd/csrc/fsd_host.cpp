@@ -109,6 +109,7 @@ void layout_vecs(fsd_problem P, Bump& B, Vecs<T>& v, bool gmres) {
     v.z = B.take<T>(Np);
     v.b = B.take<T>(Np);
     for (int i = 0; i < 4; ++i) v.t[i] = B.take<T>(Np);
+    if (sizeof(T) == 8) v.up = B.take<T>(Np);
     if (gmres) {
         v.V = B.take<T>(Np * (size_t)(P->restart + 1));
         v.w = B.take<T>(Np);
@@ -704,7 +705,7 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
     if (p->precision == FSD_PREC_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
         return fail(FSD_EINVAL, "inner_tol must be in (0, 1)");
     if (p->solver < 0 || p->solver > 2) return fail(FSD_EINVAL, "unknown solver");
-    if (p->x0_mode < 0 || p->x0_mode > 2) return fail(FSD_EINVAL, "unknown x0_mode");
+    if (p->x0_mode < 0 || p->x0_mode > 3) return fail(FSD_EINVAL, "unknown x0_mode");
 
     fsd_problem P = new (std::nothrow) fsd_problem_s();
     if (!P) return fail(FSD_EINVAL, "out of host memory");
@@ -770,6 +771,7 @@ fsd_status fsd_bind(fsd_problem P, void* d_ws, size_t bytes, void* stream) {
     FSD_TRY(upload_all<double>(P, P->t64));
     if (P->mixed) FSD_TRY(upload_all<float>(P, P->t32));
     P->bound = true;
+    P->have_hist = false;
     return FSD_OK;
 }
 
@@ -839,10 +841,21 @@ fsd_status fsd_cn_step(fsd_problem P, const double* d_u_prev, const double* d_F,
     if (P->p.x0_mode == FSD_X0_ZERO) x0_zero = true;
     else if (P->p.x0_mode == FSD_X0_EXTERNAL)
         HIP_TRY(vec_pack<double>(d_guess, v.x, n1, P->P1, P->rows, 1.0, s));
+    else if (P->p.x0_mode == FSD_X0_EXTRAP) {
+        // x = 2 u^{m-1} - u^{m-2}; history <- u^{m-1}
+        HIP_TRY(vec_extrap(v.x, v.up, P->Np, P->have_hist ? 1 : 0, s));
+        P->have_hist = true;
+    }
     fsd_status stt = solve_internal(P, v.x, v.b, x0_zero, st);
     if (stt == FSD_EHIP) return stt;
     HIP_TRY(vec_unpack<double>(v.x, d_u_next, n1, P->P1, P->rows, s));
     return stt;
+}
+
+fsd_status fsd_reset_history(fsd_problem P) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    P->have_hist = false;
+    return FSD_OK;
 }
 
 fsd_status fsd_profile_enable(fsd_problem P, int on) {

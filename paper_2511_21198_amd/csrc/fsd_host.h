@@ -40,6 +40,7 @@ struct Vecs {
     T* z = nullptr;
     T* b = nullptr;
     T* t[4] = {nullptr, nullptr, nullptr, nullptr};
+    T* up = nullptr;  // previous u_prev (time history for extrapolation)
     T* V = nullptr;   // GMRES basis, (restart + 1) vectors
     T* w = nullptr;   // GMRES work vector
 };
@@ -83,6 +84,7 @@ struct fsd_problem_s {
     fsd::Ctrl* h_ctrl = nullptr;   // pinned host mirror of the ctrl header
     int last_iters = 4;
     int last_inner_iters = 4;
+    bool have_hist = false;
 
     bool prof_on = false;
     std::vector<fsd::ProfRec> prof;

@@ -113,6 +113,15 @@ __global__ __launch_bounds__(VT) void k_copy(const T* __restrict__ a, T* __restr
     for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) b[e] = a[e];
 }
 
+__global__ __launch_bounds__(VT) void k_extrap(double* __restrict__ x, double* __restrict__ up, long N,
+                                               int have) {
+    for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) {
+        const double un = x[e];
+        if (have) x[e] = 2.0 * un - up[e];
+        up[e] = un;
+    }
+}
+
 __global__ void k_ctrl_init(Ctrl* c, double tol2, int maxit, int restart) {
     if (threadIdx.x == 0) {
         c->bb = 0; c->rr = 0; c->rz = 0; c->pq = 0; c->alpha = 0; c->beta = 0;
@@ -231,6 +240,10 @@ hipError_t vec_fill(T* x, long N, T v, hipStream_t s) {
 template <typename T>
 hipError_t vec_copy(const T* a, T* b, long N, hipStream_t s) {
     hipLaunchKernelGGL((k_copy<T>), dim3(vgrid(N)), dim3(VT), 0, s, a, b, N);
+    return hipGetLastError();
+}
+hipError_t vec_extrap(double* x, double* up, long N, int have, hipStream_t s) {
+    hipLaunchKernelGGL(k_extrap, dim3(vgrid(N)), dim3(VT), 0, s, x, up, N, have);
     return hipGetLastError();
 }
 hipError_t ctrl_init(Ctrl* c, double tol2, int maxit, int restart, hipStream_t s) {

@@ -28,6 +28,17 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Reciprocal for the Lambda^{-1} scale: v_rcp_f32 (1 ulp) for float;
+// v_rcp_f64 refined by two Newton steps (full double accuracy) for double.
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
 template <typename T, int L>
 struct WGeo {
     static constexpr int G = L / 8;                  // lanes per line
@@ -50,26 +61,146 @@ __device__ inline void dft_sub(T (&xr)[8], T (&xi)[8], int u) {
     for (int r = 0; r < R; ++r) { xr[u + r * S] = ar[r]; xi[u + r * S] = ai[r]; }
 }
 
-// One stage (radix R, span M) on the registers of lane tl; twiddles read
-// from the interleaved global table tw (exp(-2 pi i e / L)).
-template <typename T, int L, int R, int M>
-__device__ inline void wstage(T (&xr)[8], T (&xi)[8], int tl, const T* __restrict__ tw) {
-    constexpr int G = L / 8, S = 8 / R, TWS = L / (M * R);
+// Twiddles of every stage after the first, computed once per kernel into
+// registers.  Stage s (radix R, span M) needs (R-1)(8/R) values per lane:
+// w^{r k} with w = exp(-2 pi i/(M R)), k = (tl + G u) mod M.
+template <int L>
+struct TwPlan {
+    static constexpr Plan P = make_plan(L);
+    static constexpr int count(int upto) {
+        int c = 0, M = 1;
+        for (int s = 0; s < upto && s < P.nst; ++s) {
+            if (s > 0) c += (P.r[s] - 1) * (8 / P.r[s]);
+            M *= P.r[s];
+        }
+        return c;
+    }
+    static constexpr int span(int s) {
+        int M = 1;
+        for (int t = 0; t < s; ++t) M *= P.r[t];
+        return M;
+    }
+    static constexpr int NTW = count(8) > 0 ? count(8) : 1;
+};
+
+template <typename T, int L, int S>
+__device__ inline void tw_fill(T* twr, T* twi, int tl, const T* __restrict__ tw) {
+    using TP = TwPlan<L>;
+    if constexpr (S < TP::P.nst) {
+        constexpr int R = TP::P.r[S], M = TP::span(S), G = L / 8, SB = 8 / R;
+        constexpr int OFF = TP::count(S), TWS = L / (M * R);
 #pragma unroll
-    for (int u = 0; u < S; ++u) {
-        if constexpr (M > 1) {
+        for (int u = 0; u < SB; ++u) {
             const int k = (tl + G * u) % M;
 #pragma unroll
             for (int r = 1; r < R; ++r) {
                 const int t = r * k * TWS;
-                const T wr = tw[2 * t], wi = tw[2 * t + 1];
-                const int q = u + r * S;
+                twr[OFF + u * (R - 1) + r - 1] = tw[2 * t];
+                twi[OFF + u * (R - 1) + r - 1] = tw[2 * t + 1];
+            }
+        }
+        tw_fill<T, L, S + 1>(twr, twi, tl, tw);
+    }
+}
+
+// float keeps the twiddles of all stages in registers (loaded once per
+// kernel, reused by every FFT of the kernel); double reads them from the
+// L1-resident table at the point of use, which keeps the double passes
+// within 128 VGPRs.
+template <typename T, int L, bool REG = (sizeof(T) == 4)>
+struct Twiddles {
+    T r[TwPlan<L>::NTW], i[TwPlan<L>::NTW];
+    __device__ inline void load(int tl, const T* __restrict__ tw) { tw_fill<T, L, 1>(r, i, tl, tw); }
+    template <int S, int R, int M>
+    __device__ inline void get(int u, int rr, T& wr, T& wi) const {
+        constexpr int OFF = TwPlan<L>::count(S);
+        wr = r[OFF + u * (R - 1) + rr - 1];
+        wi = i[OFF + u * (R - 1) + rr - 1];
+    }
+};
+
+template <typename T, int L>
+struct Twiddles<T, L, false> {
+    const T* tab;
+    int tl;
+    __device__ inline void load(int tl_, const T* __restrict__ tw) { tab = tw; tl = tl_; }
+    template <int S, int R, int M>
+    __device__ inline void get(int u, int rr, T& wr, T& wi) const {
+        constexpr int G = L / 8, TWS = L / (M * R);
+        const int k = (tl + G * u) % M;
+        const int t = rr * k * TWS;
+        wr = tab[2 * t];
+        wi = tab[2 * t + 1];
+    }
+};
+
+// Radix-8 DFT on registers 0..7 (even/odd split into two radix-4 DFTs).
+// ZIN: inputs 4..7 are zero, so each radix-4 half reduces to one add/sub
+// pair.  ZOUT: outputs 4..7 are not needed and are left unchanged.
+template <typename T, bool ZIN, bool ZOUT>
+__device__ inline void dft8_pruned(T (&xr)[8], T (&xi)[8]) {
+    const T r2 = T(0.70710678118654752440084436210485);
+    T er[4], ei[4], orr[4], oi[4];
+    if constexpr (ZIN) {
+        // even half {x0, x2, 0, 0}, odd half {x1, x3, 0, 0}
+        er[0] = xr[0] + xr[2]; ei[0] = xi[0] + xi[2];
+        er[2] = xr[0] - xr[2]; ei[2] = xi[0] - xi[2];
+        er[1] = xr[0] + xi[2]; ei[1] = xi[0] - xr[2];
+        er[3] = xr[0] - xi[2]; ei[3] = xi[0] + xr[2];
+        orr[0] = xr[1] + xr[3]; oi[0] = xi[1] + xi[3];
+        orr[2] = xr[1] - xr[3]; oi[2] = xi[1] - xi[3];
+        orr[1] = xr[1] + xi[3]; oi[1] = xi[1] - xr[3];
+        orr[3] = xr[1] - xi[3]; oi[3] = xi[1] + xr[3];
+    } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            er[j] = xr[2 * j];      ei[j] = xi[2 * j];
+            orr[j] = xr[2 * j + 1]; oi[j] = xi[2 * j + 1];
+        }
+        dft4(er, ei);
+        dft4(orr, oi);
+    }
+    // odd half scaled by w8^s, s = 0..3: 1, (1-i)/sqrt2, -i, -(1+i)/sqrt2
+    const T w1r = r2 * (orr[1] + oi[1]), w1i = r2 * (oi[1] - orr[1]);
+    const T w2r = oi[2], w2i = -orr[2];
+    const T w3r = r2 * (oi[3] - orr[3]), w3i = -r2 * (orr[3] + oi[3]);
+    const T wr[4] = {orr[0], w1r, w2r, w3r}, wi[4] = {oi[0], w1i, w2i, w3i};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        xr[s] = er[s] + wr[s];
+        xi[s] = ei[s] + wi[s];
+        if constexpr (!ZOUT) {
+            xr[s + 4] = er[s] - wr[s];
+            xi[s + 4] = ei[s] - wi[s];
+        }
+    }
+}
+
+// One stage (radix R, span M) on the registers of lane tl.  ZIN: registers
+// 4..7 hold zeros (first stage of a zero-padded line; radix 8 only), so the
+// radix-8 DFT skips them.  ZOUT: only outputs 0..3 are needed (last stage,
+// radix 8).
+template <typename T, int L, int R, int M, int S, bool ZIN, bool ZOUT>
+__device__ inline void wstage(T (&xr)[8], T (&xi)[8], const Twiddles<T, L>& tw) {
+    constexpr int SB = 8 / R;
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+        if constexpr (M > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                T wr, wi;
+                tw.template get<S, R, M>(u, r, wr, wi);
+                const int q = u + r * SB;
                 const T a = xr[q], b = xi[q];
                 xr[q] = a * wr - b * wi;
                 xi[q] = a * wi + b * wr;
             }
         }
-        dft_sub<R, T>(xr, xi, u);
+        if constexpr (R == 8 && (ZIN || ZOUT)) {
+            dft8_pruned<T, ZIN, ZOUT>(xr, xi);
+        } else {
+            dft_sub<R, T>(xr, xi, u);
+        }
     }
 }
 
@@ -100,24 +231,28 @@ __device__ inline void wexchange(T (&xr)[8], T (&xi)[8], int tl, T* re, T* im) {
     wave_sync();
 }
 
-template <typename T, int L, int S, int M>
+template <typename T, int L, int S, int M, bool ZIN, bool ZOUT>
 struct WRun {
-    __device__ static inline void run(T (&xr)[8], T (&xi)[8], int tl, const T* tw, T* re, T* im) {
+    __device__ static inline void run(T (&xr)[8], T (&xi)[8], int tl, const Twiddles<T, L>& tw,
+                                      T* re, T* im) {
         constexpr Plan P = make_plan(L);
         if constexpr (S < P.nst) {
             constexpr int R = P.r[S];
-            wstage<T, L, R, M>(xr, xi, tl, tw);
+            constexpr bool zin = ZIN && S == 0 && R == 8;
+            constexpr bool zout = ZOUT && S + 1 == P.nst && R == 8;
+            wstage<T, L, R, M, S, zin, zout>(xr, xi, tw);
             if constexpr (S + 1 < P.nst) wexchange<T, L, R, M>(xr, xi, tl, re, im);
-            WRun<T, L, S + 1, M * R>::run(xr, xi, tl, tw, re, im);
+            WRun<T, L, S + 1, M * R, ZIN, ZOUT>::run(xr, xi, tl, tw, re, im);
         }
     }
 };
 
 // Forward FFT of one line held as points tl + G q; LDS region re/im of
-// length WGeo::LP is private to the lane group.
-template <typename T, int L>
-__device__ inline void wfft(T (&xr)[8], T (&xi)[8], int tl, const T* tw, T* re, T* im) {
-    WRun<T, L, 0, 1>::run(xr, xi, tl, tw, re, im);
+// length WGeo::LP is private to the lane group.  ZIN: points q >= 4 are zero
+// (zero-padded input); ZOUT: only points q < 4 of the result are used.
+template <typename T, int L, bool ZIN = false, bool ZOUT = false>
+__device__ inline void wfft(T (&xr)[8], T (&xi)[8], int tl, const Twiddles<T, L>& tw, T* re, T* im) {
+    WRun<T, L, 0, 1, ZIN, ZOUT>::run(xr, xi, tl, tw, re, im);
 }
 
 // Toeplitz spectrum multiply in registers: Y = conj(C Z).
@@ -226,12 +361,14 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
             wave_sync();
         }
     }
+    Twiddles<T, L> tw;
+    tw.load(tl, a.tw);
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int slot = wave * LW * LPL + g + LW * p;
-        wfft<T, L>(xr[p], xi[p], tl, a.tw, s_re + slot * LP, s_im + slot * LP);
+        wfft<T, L, true, false>(xr[p], xi[p], tl, tw, s_re + slot * LP, s_im + slot * LP);
         wspec<T, L>(xr[p], xi[p], tl, a.spec);
-        wfft<T, L>(xr[p], xi[p], tl, a.tw, s_re + slot * LP, s_im + slot * LP);
+        wfft<T, L, false, true>(xr[p], xi[p], tl, tw, s_re + slot * LP, s_im + slot * LP);
     }
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
@@ -283,10 +420,12 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
             }
         }
     }
+    Twiddles<T, L> tw;
+    tw.load(tl, a.tw);
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int slot = wave * LW * LPL + g + LW * p;
-        wfft<T, L>(xr[p], xi[p], tl, a.tw, s_re + slot * LP, s_im + slot * LP);
+        wfft<T, L, false, true>(xr[p], xi[p], tl, tw, s_re + slot * LP, s_im + slot * LP);
     }
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
@@ -379,14 +518,16 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
         }
     }
     __syncthreads();
+    Twiddles<T, L> tw;
+    tw.load(tl, a.tw);
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int slot = wave * LW * LPL + g + LW * p;
         T* re = s_re + slot * LP;
         T* im = s_im + slot * LP;
-        wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+        wfft<T, L, true, false>(xr[p], xi[p], tl, tw, re, im);
         wspec<T, L>(xr[p], xi[p], tl, a.spec);
-        wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+        wfft<T, L, false, true>(xr[p], xi[p], tl, tw, re, im);
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int e = W::idx(tl + G * q);
@@ -490,13 +631,15 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
         }
     }
     __syncthreads();
+    Twiddles<T, L> tw;
+    tw.load(tl, a.tw);
     double acc = 0.0;
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int slot = wave * LW * LPL + g + LW * p;
         T* re = s_re + slot * LP;
         T* im = s_im + slot * LP;
-        wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+        wfft<T, L, false, !SCALE>(xr[p], xi[p], tl, tw, re, im);
         if constexpr (SCALE) {
             const T P0 = s_P[2 * slot], Q0 = s_Q[2 * slot];
             const T P1v = s_P[2 * slot + 1], Q1v = s_Q[2 * slot + 1];
@@ -507,8 +650,8 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
                 T wr = 0, wi = 0;
                 if (k >= 1 && k <= n) {
                     const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
-                    const T inv0 = P0 != T(0) ? T(1) / (ak * P0 + lk * Q0) : T(0);
-                    const T inv1 = P1v != T(0) ? T(1) / (ak * P1v + lk * Q1v) : T(0);
+                    const T inv0 = P0 != T(0) ? fast_rcp(ak * P0 + lk * Q0) : T(0);
+                    const T inv1 = P1v != T(0) ? fast_rcp(ak * P1v + lk * Q1v) : T(0);
                     const T s1 = -xi[p][q] * a.c;
                     const T s2 = xr[p][q] * a.c;
                     wr = s1 * inv0;
@@ -518,7 +661,7 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
                 xr[p][q] = wr;
                 xi[p][q] = wi;
             }
-            wfft<T, L>(xr[p], xi[p], tl, a.tw, re, im);
+            wfft<T, L, false, true>(xr[p], xi[p], tl, tw, re, im);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {

@@ -54,7 +54,8 @@ class Problem:
         p.precision = {"fp64": nat.PREC_FP64, "mixed": nat.PREC_MIXED}[precision]
         p.inner_tol = float(inner_tol)
         p.max_outer = int(max_outer)
-        p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL}[x0]
+        p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL,
+                     "extrap": nat.X0_EXTRAP}[x0]
         p.allow_delta_zero = int(allow_delta_zero)
         self.params = p
         self.dim = dim
@@ -121,6 +122,10 @@ class Problem:
         if raise_on_error:
             check(s, "fsd_cn_step")
         return out, (st.as_dict() if stats else None)
+
+    def reset_history(self):
+        """Forget the time history used by x0="extrap"."""
+        check(lib.fsd_reset_history(self._h), "fsd_reset_history")
 
     def profile(self, on: bool = True):
         """Record hipEvents around every heavy kernel launch (see
