@@ -95,6 +95,62 @@ def cpu_baseline(w):
                       f"float64 NumPy/SciPy oracle, {dt:.1f} s on {cpu_model()}"}
 
 
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_3d_nonsym_255.json")
+
+
+def counter_traffic(kind):
+    """HBM bytes per launch of a kernel kind from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when there is none or when the
+    kernel sources changed after it was taken."""
+    try:
+        with open(TRAFFIC_JSON) as f:
+            doc = json.load(f)
+    except (OSError, ValueError):
+        return None
+    from paper_2511_21198_amd.rocprof_summary import source_hash
+    if doc.get("source_hash") != source_hash():
+        return None
+    return doc.get("kinds", {}).get(kind, {}).get("hbm_bytes_per_dispatch")
+
+
+def matvec_bench(w, reps=100):
+    """One fsd_apply_A at the workload's size, float64, `reps` calls: wall
+    time per call (hipEvents on the library's stream) and the per-pass
+    figures of the library profiler."""
+    import torch
+    from paper_2511_21198_amd.solver import Problem
+    p = Problem(3, w.n, w.delta, w.kplus, w.kminus, M=w.M, T=w.T, solver="gmres")
+    x = torch.from_numpy(w.F).cuda()
+    y = torch.empty_like(x)
+    for _ in range(5):
+        p.apply_A(x, out=y)
+    st = p.stream
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        p.apply_A(x, out=y)
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    p.profile(True)
+    p.profile_read()
+    for _ in range(reps):
+        p.apply_A(x, out=y)
+    prof = p.profile_read()
+    p.profile(False)
+    N = int(np.prod(w.n))
+    pass_ms = sum(v["total_ms"] for v in prof.values()) / reps
+    pass_bytes = sum(v["bytes"] for v in prof.values()) / reps
+    return {"apply_A_ms": round(ms, 4),
+            "algorithmic_gbps": round(2 * N * 8 / (ms * 1e-3) / 1e9, 1),
+            "passes_ms": round(pass_ms, 4),
+            "pass_level_gbps": round(pass_bytes / (pass_ms * 1e-3) / 1e9, 1),
+            "passes": {k: {"avg_ms": round(v["avg_ms"], 4), "gbps": round(v["gbps"], 1)}
+                       for k, v in prof.items()},
+            "note": "float64, dense ABI layout in and out (pack and unpack kernels "
+                    "included in apply_A_ms), 100 calls"}
+
+
 def secondary_symmetric(a):
     """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
     PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
@@ -223,7 +279,8 @@ def main(argv=None):
                    "n": a.n, "unknowns": a.n ** 3},
         "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": counter_traffic(dom_name) if a.n == 255 else None,
                      "avg_launch_ms": round(dom["avg_ms"], 5),
                      "algorithmic_bytes_per_launch": per_launch},
         "toeplitz_matvec_gbps": toep,
@@ -240,6 +297,7 @@ def main(argv=None):
     if errs:
         out["rel_err_vs_tight_fp64"] = errs
     if not a.no_secondary:
+        out["matvec_fp64"] = matvec_bench(w)
         out["secondary"] = secondary_symmetric(a)
     out["kernels"] = {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
                           "gbps": round(v["gbps"], 1), "total_ms": round(v["total_ms"], 3)}

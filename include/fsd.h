@@ -189,7 +189,10 @@ fsd_status fsd_get_coefficients(fsd_problem prob, int axis, double* q, double* l
  * the stream, aggregates the records per kernel kind into at most `max`
  * entries of `out`, clears them, and returns the number of kinds (or -1 on
  * error).  `bytes` is the algorithmic traffic summed over the launches: the
- * interior values each launch must read and write (padding excluded). */
+ * interior values each launch must read and write (padding excluded).
+ * Launches of a Krylov iteration that was enqueued ahead of the convergence
+ * test and found the solve already stopped (they return without work) are
+ * not counted. */
 typedef struct {
     char name[32];     /* e.g. "toep_z_f32", "dsts_z_f64", "gm_maxpy_f32" */
     long launches;

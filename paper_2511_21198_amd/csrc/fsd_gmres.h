@@ -5,7 +5,7 @@
 
 namespace fsd {
 
-constexpr int kGmGrid = 2048;
+constexpr int kGmGrid = 1024;
 
 enum GmOp : int {
     GM_PBB = 0,    // bb = ||P^{-1} b||^2, thresh = tol^2 bb

@@ -61,87 +61,113 @@ __device__ inline void block_multi_sum(const double (&acc)[NVMAX], int nv, doubl
     }
 }
 
-// partials[i * G + blk] = sum_e V_i[e] w[e], i < nv (nv <= NVMAX).  Each
-// thread takes two elements per iteration so that 2 (nv + 1) independent
-// loads are in flight.
-template <typename T, int NVMAX>
-__global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, int nv,
+// 16-byte vector of T: each lane moves 16 bytes per load (float4 / double2).
+template <typename T> struct Vec16;
+template <> struct Vec16<float> { using type = float4; static constexpr int W = 4; };
+template <> struct Vec16<double> { using type = double2; static constexpr int W = 2; };
+
+template <typename V>
+__device__ inline double vdot(const V& a, const V& b);
+template <>
+__device__ inline double vdot<float4>(const float4& a, const float4& b) {
+    // products of floats are exact in double
+    return ((double)a.x * (double)b.x + (double)a.y * (double)b.y) +
+           ((double)a.z * (double)b.z + (double)a.w * (double)b.w);
+}
+template <>
+__device__ inline double vdot<double2>(const double2& a, const double2& b) {
+    return a.x * b.x + a.y * b.y;
+}
+template <typename T, typename V>
+__device__ inline void vfms(V& o, T h, const V& v) {   // o -= h v
+    o.x -= h * v.x; o.y -= h * v.y;
+    if constexpr (sizeof(V) / sizeof(T) == 4) { o.z -= h * v.z; o.w -= h * v.w; }
+}
+template <typename T, typename V>
+__device__ inline void vfma(V& o, T h, const V& v) {   // o += h v
+    o.x += h * v.x; o.y += h * v.y;
+    if constexpr (sizeof(V) / sizeof(T) == 4) { o.z += h * v.z; o.w += h * v.w; }
+}
+
+// The vector kernels are instantiated for every basis size NV up to
+// kExactNV (EXACT = true: the loops over the basis are fully unrolled with no
+// predicates, so all NV + 1 loads of an iteration are in flight together) and
+// once generically (NV = kMaxRestart + 1, predicated on the runtime count).
+// N is a multiple of the vector width (the padded layout rounds the x extent
+// up to 32) and every vector is 256-byte aligned.
+
+// partials[i * G + blk] = sum_e V_i[e] w[e], i < nv.
+template <typename T, int NV, bool EXACT>
+__global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, int nv_rt,
                                              const T* __restrict__ w, long N,
                                              double* __restrict__ partials, const Ctrl* ctrl) {
-    __shared__ double red[(GT / 64) * NVMAX];
+    using VT = typename Vec16<T>::type;
+    constexpr int VW = Vec16<T>::W;
+    __shared__ double red[(GT / 64) * NV];
     if (ctrl->done) return;
-    double acc[NVMAX];
+    const int nv = EXACT ? NV : nv_rt;
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
-    const long stride = (long)gridDim.x * GT;
-    long e = blockIdx.x * (long)GT + threadIdx.x;
-    for (; e + stride < N; e += 2 * stride) {
-        const long e2 = e + stride;
-        const double w1 = (double)w[e], w2 = (double)w[e2];
-        T v1[NVMAX], v2[NVMAX];
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    const long NW = N / VW, ldw = ld / VW;
+    const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
+    const VT* __restrict__ wv = reinterpret_cast<const VT*>(w);
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < NW; e += (long)gridDim.x * GT) {
+        const VT we = wv[e];
+        VT v[NV];
 #pragma unroll
-        for (int i = 0; i < NVMAX; ++i) {
-            v1[i] = i < nv ? V[i * ld + e] : T(0);
-            v2[i] = i < nv ? V[i * ld + e2] : T(0);
-        }
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) v[i] = Vv[i * ldw + e];
 #pragma unroll
-        for (int i = 0; i < NVMAX; ++i) acc[i] += (double)v1[i] * w1 + (double)v2[i] * w2;
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) acc[i] += vdot(v[i], we);
     }
-    if (e < N) {
-        const double we = (double)w[e];
-#pragma unroll
-        for (int i = 0; i < NVMAX; ++i)
-            if (i < nv) acc[i] += (double)V[i * ld + e] * we;
-    }
-    block_multi_sum<NVMAX>(acc, nv, red, partials);
+    block_multi_sum<NV>(acc, nv, red, partials);
 }
 
 // out = in - sum_i h_i V_i (h from ctrl->gm + hoff); then either partial dots
-// V_i^T out (want_dots) or the partial ||out||^2.  Two elements per thread
-// per iteration.
-template <typename T, int NVMAX>
-__global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, int nv,
+// V_i^T out (want_dots) or the partial ||out||^2.
+template <typename T, int NV, bool EXACT>
+__global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, int nv_rt,
                                               const T* in, T* out, long N, const Ctrl* ctrl,
                                               int hoff, int want_dots, double* __restrict__ partials) {
+    using VT = typename Vec16<T>::type;
+    constexpr int VW = Vec16<T>::W;
     __shared__ double sb[GT / 64];
-    __shared__ double red[(GT / 64) * NVMAX];
+    __shared__ double red[(GT / 64) * NV];
     if (ctrl->done) return;
-    T h[NVMAX];
+    const int nv = EXACT ? NV : nv_rt;
+    T h[NV];
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) h[i] = i < nv ? (T)ctrl->gm[hoff + i] : T(0);
-    double acc[NVMAX];
+    for (int i = 0; i < NV; ++i) h[i] = i < nv ? (T)ctrl->gm[hoff + i] : T(0);
+    double acc[NV];
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) acc[i] = 0.0;
+    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
     double nrm = 0.0;
-    const long stride = (long)gridDim.x * GT;
-    for (long e0 = blockIdx.x * (long)GT + threadIdx.x; e0 < N; e0 += 2 * stride) {
-        const long e1 = e0 + stride;
-        const bool has1 = e1 < N;
-        T va[NVMAX], vb[NVMAX];
-        T oa = in[e0];
-        T ob = has1 ? in[e1] : T(0);
+    const long NW = N / VW, ldw = ld / VW;
+    const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
+    const VT* inv = reinterpret_cast<const VT*>(in);
+    VT* outv = reinterpret_cast<VT*>(out);
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < NW; e += (long)gridDim.x * GT) {
+        VT o = inv[e];
+        VT v[NV];
 #pragma unroll
-        for (int i = 0; i < NVMAX; ++i) {
-            va[i] = i < nv ? V[i * ld + e0] : T(0);
-            vb[i] = (i < nv && has1) ? V[i * ld + e1] : T(0);
-        }
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) v[i] = Vv[i * ldw + e];
 #pragma unroll
-        for (int i = 0; i < NVMAX; ++i) {
-            oa -= h[i] * va[i];
-            ob -= h[i] * vb[i];
-        }
-        out[e0] = oa;
-        if (has1) out[e1] = ob;
+        for (int i = 0; i < NV; ++i)
+            if (i < nv) vfms<T>(o, h[i], v[i]);
+        outv[e] = o;
         if (want_dots) {
 #pragma unroll
-            for (int i = 0; i < NVMAX; ++i)
-                acc[i] += (double)va[i] * (double)oa + (double)vb[i] * (double)ob;
+            for (int i = 0; i < NV; ++i)
+                if (i < nv) acc[i] += vdot(v[i], o);
         } else {
-            nrm += (double)oa * (double)oa + (double)ob * (double)ob;
+            nrm += vdot(o, o);
         }
     }
     if (want_dots) {
-        block_multi_sum<NVMAX>(acc, nv, red, partials);
+        block_multi_sum<NV>(acc, nv, red, partials);
     } else {
         const double s = block_sum(nrm, sb);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
@@ -149,19 +175,37 @@ __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, 
 }
 
 // x += sum_{i < k} y_i V_i with k = ctrl->gm_k and y in ctrl->gm (yoff).
-template <typename T, int NVMAX>
+// The host launches the instance NV = k; any other k (k = 0 after an
+// immediate convergence) takes the predicated loop, which never touches a
+// basis vector beyond k (unwritten memory may hold NaN patterns).
+template <typename T, int NV, bool EXACT>
 __global__ __launch_bounds__(GT) void k_gm_update(T* x, const T* __restrict__ V, long ld, long N,
                                                   const Ctrl* ctrl, int yoff) {
+    using VT = typename Vec16<T>::type;
+    constexpr int VW = Vec16<T>::W;
     const int k = ctrl->gm_k;
-    T y[NVMAX];
+    if (k <= 0) return;
+    T y[NV];
 #pragma unroll
-    for (int i = 0; i < NVMAX; ++i) y[i] = i < k ? (T)ctrl->gm[yoff + i] : T(0);
-    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < N; e += (long)gridDim.x * GT) {
-        T acc = x[e];
+    for (int i = 0; i < NV; ++i) y[i] = i < k ? (T)ctrl->gm[yoff + i] : T(0);
+    const long NW = N / VW, ldw = ld / VW;
+    const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
+    VT* xv = reinterpret_cast<VT*>(x);
+    const bool full = EXACT && k == NV;
+    for (long e = blockIdx.x * (long)GT + threadIdx.x; e < NW; e += (long)gridDim.x * GT) {
+        VT acc = xv[e];
+        VT v[NV];
+        if (full) {
 #pragma unroll
-        for (int i = 0; i < NVMAX; ++i)
-            if (i < k) acc += y[i] * V[i * ld + e];
-        x[e] = acc;
+            for (int i = 0; i < NV; ++i) v[i] = Vv[i * ldw + e];
+#pragma unroll
+            for (int i = 0; i < NV; ++i) vfma<T>(acc, y[i], v[i]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i)
+                if (i < k) vfma<T>(acc, y[i], Vv[i * ldw + e]);
+        }
+        xv[e] = acc;
     }
 }
 
@@ -181,9 +225,12 @@ __device__ inline bool gm_isfinite(double v) { return __builtin_isfinite(v); }
 // Scalar GMRES steps (one workgroup; thread 0 updates the state).
 // Layout of ctrl->gm for restart m: H (m+1) x m column-major at 0,
 // cs at GM_CS, sn at GM_SN, g at GM_G (m+1), y at GM_Y (m), h2 at GM_T (m+1).
-__global__ __launch_bounds__(GT) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
+// The nv sums of the partials are spread over the wavefronts (one value per
+// wavefront at a time, a fixed summation order per value).
+constexpr int ST = 1024;
+__global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
                                                   int nparts, int nv, int j, int op) {
-    __shared__ double sb[GT / 64];
+    __shared__ double sums[kMaxRestart + 1];
     const int m = c->gm_m;
     const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m, oY = oG + m + 1, oT = oY + m;
     double* gm = c->gm;
@@ -200,21 +247,26 @@ __global__ __launch_bounds__(GT) void k_gm_scalar(Ctrl* c, const double* __restr
         return;
     }
     if (c->done) return;
-    for (int i = 0; i < nv; ++i) {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int i = wv; i < nv; i += ST / 64) {
         double acc = 0.0;
-        for (int t = threadIdx.x; t < nparts; t += GT) acc += partials[(long)i * nparts + t];
-        const double S = block_sum(acc, sb);
-        if (threadIdx.x == 0) {
-            if (op == GM_H1) gm[oH + i + (m + 1) * j] = S;
-            else if (op == GM_H2) { gm[oT + i] = S; gm[oH + i + (m + 1) * j] += S; }
-            else gm[oT + i] = S;   // GM_PBB, GM_BETA, GM_STEP: a single norm
-        }
+        for (int t = lane; t < nparts; t += 64) acc += partials[(long)i * nparts + t];
+        acc = wave_sum(acc);
+        if (lane == 0) sums[i] = acc;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < nv; ++i) {
+        const double S = sums[i];
+        if (op == GM_H1) gm[oH + i + (m + 1) * j] = S;
+        else if (op == GM_H2) { gm[oT + i] = S; gm[oH + i + (m + 1) * j] += S; }
+        else gm[oT + i] = S;   // GM_PBB, GM_BETA, GM_STEP: a single norm
     }
     if (threadIdx.x != 0) return;
     if (op == GM_PBB) {
         const double S = gm[oT];
         c->bb = S;
-        c->thresh = c->tol2 * S;
+        c->thresh = fmax(c->tol2 * S, c->abs2);
         if (!gm_isfinite(S)) { c->status = 4; c->done = 1; }
         else if (S == 0.0) { c->rr = 0.0; c->done = 1; }
     } else if (op == GM_BETA) {
@@ -268,6 +320,10 @@ __global__ void k_gm_restart(Ctrl* c) {
     if (threadIdx.x == 0 && c->done == 2) c->done = 0;
 }
 
+// The vector kernels move 16 bytes per lane: lengths and strides must be
+// multiples of 4 elements (true for the padded layout).
+inline bool vec_ok(long N, long ld) { return N % 4 == 0 && ld % 4 == 0; }
+
 inline int ggrid(long N) {
     long g = (N + GT * 4 - 1) / (GT * 4);
     if (g > kGmGrid) g = kGmGrid;
@@ -279,16 +335,47 @@ inline int ggrid(long N) {
 
 int gm_grid(long N) { return ggrid(N); }
 
+// Basis sizes with a fully unrolled kernel instance (restart <= 23).
+constexpr int kExactNV = 24;
+
+#define FSD_NV_CASE(KER, T, NV, ...)                                                         \
+    case NV: hipLaunchKernelGGL((KER<T, NV, true>), __VA_ARGS__); break;
 #define FSD_NV_DISPATCH(KER, T, nv, ...)                                                     \
     do {                                                                                     \
-        if ((nv) <= 8) hipLaunchKernelGGL((KER<T, 8>), __VA_ARGS__);                         \
-        else if ((nv) <= 24) hipLaunchKernelGGL((KER<T, 24>), __VA_ARGS__);                  \
-        else hipLaunchKernelGGL((KER<T, kMaxRestart + 1>), __VA_ARGS__);                     \
+        switch (nv) {                                                                        \
+        FSD_NV_CASE(KER, T, 1, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 2, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 3, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 4, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 5, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 6, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 7, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 8, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 9, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 10, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 11, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 12, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 13, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 14, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 15, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 16, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 17, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 18, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 19, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 20, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 21, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 22, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 23, __VA_ARGS__)                                                 \
+        FSD_NV_CASE(KER, T, 24, __VA_ARGS__)                                                 \
+        default: hipLaunchKernelGGL((KER<T, kMaxRestart + 1, false>), __VA_ARGS__);          \
+        }                                                                                    \
     } while (0)
+static_assert(kExactNV == 24, "FSD_NV_DISPATCH lists the exact cases 1..24");
 
 template <typename T>
 hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* partials,
                    const Ctrl* ctrl, int* nparts, hipStream_t s) {
+    if (!vec_ok(N, ld)) return hipErrorInvalidValue;
     const int g = ggrid(N);
     *nparts = g;
     FSD_NV_DISPATCH(k_mdot, T, nv, dim3(g), dim3(GT), 0, s, V, ld, nv, w, N, partials, ctrl);
@@ -298,6 +385,7 @@ hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* part
 template <typename T>
 hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, const Ctrl* ctrl,
                     int hoff, int want_dots, double* partials, int* nparts, hipStream_t s) {
+    if (!vec_ok(N, ld)) return hipErrorInvalidValue;
     const int g = ggrid(N);
     *nparts = g;
     FSD_NV_DISPATCH(k_maxpy, T, nv, dim3(g), dim3(GT), 0, s, V, ld, nv, in, out, N, ctrl, hoff,
@@ -308,6 +396,7 @@ hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, co
 template <typename T>
 hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ctrl, int yoff,
                      hipStream_t s) {
+    if (!vec_ok(N, ld)) return hipErrorInvalidValue;
     const int g = ggrid(N);
     FSD_NV_DISPATCH(k_gm_update, T, kmax, dim3(g), dim3(GT), 0, s, x, V, ld, N, ctrl, yoff);
     return hipGetLastError();
@@ -321,7 +410,7 @@ hipError_t gm_scale(const T* in, T* out, long N, const Ctrl* ctrl, hipStream_t s
 
 hipError_t gm_scalar(Ctrl* c, const double* partials, int nparts, int nv, int j, int op,
                      hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_scalar, dim3(1), dim3(GT), 0, s, c, partials, nparts, nv, j, op);
+    hipLaunchKernelGGL(k_gm_scalar, dim3(1), dim3(ST), 0, s, c, partials, nparts, nv, j, op);
     return hipGetLastError();
 }
 

@@ -67,9 +67,18 @@ struct ProfScope {
     ~ProfScope() {
         if (!a) return;
         (void)hipEventRecord(b, P->stream);
-        P->prof.push_back(ProfRec{kind, a, b, bytes});
+        P->prof.push_back(ProfRec{kind, a, b, bytes, P->prof_tag, false});
     }
 };
+
+// Marks the records from index `from` whose iteration tag is >= executed:
+// those launches were enqueued ahead of the convergence test and returned
+// without work.
+void prof_drop_skipped(fsd_problem P, size_t from, int executed) {
+    for (size_t i = from; i < P->prof.size(); ++i)
+        if (P->prof[i].tag >= executed) P->prof[i].skip = true;
+    P->prof_tag = -1;
+}
 
 template <typename T>
 constexpr bool is_f32() { return sizeof(T) == 4; }
@@ -345,6 +354,7 @@ long default_maxit(fsd_problem P) {
 struct SolveOut {
     long iters = 0;
     double relres = 0.0;   // solver's own stopping quantity
+    double bnorm = 0.0;    // ||b|| (PCG) or ||P^{-1} b|| (left GMRES) of this solve
     int status = FSD_OK;
 };
 
@@ -356,12 +366,14 @@ struct SolveOut {
 // 3 or 5 preconditioner passes ((r, z) by Parseval in the middle one) and
 // three one-workgroup scalar kernels.
 template <typename T>
-fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit, SolveOut& out) {
+fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit, double abs_tol,
+               SolveOut& out) {
     Vecs<T>& v = vecs<T>(P);
     hipStream_t s = P->stream;
     const long Np = P->Np;
     int np = 0;
-    HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), P->restart, s));
+    HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), P->restart, s,
+                      abs_tol * abs_tol));
     HIP_TRY(vec_dot<T>(b, b, Np, P->partials, P->ctrl, &np, s));
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_BB, s));
     if (x0_zero) {
@@ -377,10 +389,14 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
     FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_RZ0, s));
 
-    int chunk = std::max(2, P->last_iters);
+    // First chunk: the previous solve's count less one (counts fall slowly
+    // over the time steps); then two iterations per host check.
+    int chunk = std::max(2, P->last_iters - 1);
     long enq = 0;
+    const size_t rec0 = P->prof.size();
     for (;;) {
         for (int c = 0; c < chunk && enq < maxit; ++c, ++enq) {
+            P->prof_tag = (int)enq;
             MatvecOpts o;
             o.epi = EPI_DOT_P;
             o.pro = PRO_PUPDATE;
@@ -391,6 +407,7 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
                 HIP_TRY(vec_update_xr<T>(x, v.r, v.p, v.q, Np, P->ctrl, P->partials, &np, s));
             }
             HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_CHECK, s));
+            P->prof_tag = (int)enq + 1;   // z for the next direction
             FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
             HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_BETA, s));
         }
@@ -399,8 +416,10 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
         chunk = 2;
     }
     const Ctrl& c = *P->h_ctrl;
+    prof_drop_skipped(P, rec0, c.iters);
     out.iters = c.iters;
     out.relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
+    out.bnorm = std::sqrt(c.bb);
     out.status = c.status;
     if (c.bb == 0.0) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
     if (!c.done && out.status == FSD_OK) out.status = FSD_ENOTCONV;
@@ -413,13 +432,14 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
 // stop when ||P^{-1}(b - A x_k)||_2 <= tol ||P^{-1} b||_2.
 template <typename T>
 fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
-                 SolveOut& out) {
+                 double abs_tol, SolveOut& out) {
     Vecs<T>& v = vecs<T>(P);
     hipStream_t s = P->stream;
     const long Np = P->Np;
     const int m = P->restart;
     int np = 0;
-    HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), m, s));
+    HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), m, s,
+                      abs_tol * abs_tol));
     // ||P^{-1} b||
     FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr));
     HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
@@ -438,10 +458,12 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         }
         HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
-        int chunk = std::max(2, P->last_iters);
+        int chunk = std::max(2, P->last_iters - 1);
         int j = 0;
+        const size_t rec0 = P->prof.size();
         for (;;) {
             for (int c = 0; c < chunk && j < m; ++c, ++j) {
+                P->prof_tag = j;
                 T* vj = v.V + (long)j * Np;
                 // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
                 MatvecOpts o;
@@ -474,6 +496,7 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             chunk = 2;
         }
         const Ctrl& c = *P->h_ctrl;
+        prof_drop_skipped(P, rec0, c.gm_k);
         // x += V y over the columns of this cycle
         HIP_TRY(gm_scalar(P->ctrl, P->partials, 0, 0, 0, GM_SOLVE, s));
         {
@@ -492,6 +515,7 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     const Ctrl& c = *P->h_ctrl;
     out.iters = c.iters;
     out.relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
+    out.bnorm = std::sqrt(c.bb);
     if (c.bb == 0.0) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
     if (out.status == FSD_OK && c.status != 0) out.status = c.status;
     P->last_iters = std::max(1, (int)c.iters);
@@ -499,10 +523,14 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     return FSD_OK;
 }
 
+// Stops when the solver's residual norm is <= max(tol * (norm at the start),
+// abs_tol): ||r|| vs ||b|| for PCG, ||P^{-1} r|| vs ||P^{-1} b|| for GMRES.
 template <typename T>
-fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit, SolveOut& o) {
-    if (P->solver == FSD_SOLVER_PGMRES) return gmres<T>(P, x, b, x0_zero, tol, maxit, o);
-    return pcg<T>(P, x, b, x0_zero, tol, maxit, o);
+fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
+                  SolveOut& o, double abs_tol = 0.0) {
+    P->prof_tag = -1;
+    if (P->solver == FSD_SOLVER_PGMRES) return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
+    return pcg<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
 }
 
 // True residual r = b - A x in float64; *rnorm = ||r||_2.
@@ -546,29 +574,55 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         S.converged = o.status == FSD_OK;
     } else {
         // Defect correction: r = b - A x (float64); solve A d = r in float32
-        // to inner_tol; x += d; stop when ||b - A x|| <= tol ||b||.
+        // to inner_tol; x += d.  The stopping test is the float64 solver's:
+        // ||b - A x|| <= tol ||b|| for PCG, ||P^{-1}(b - A x)|| <= tol ||P^{-1} b||
+        // for left GMRES.  The inner solve also stops once the outer test
+        // is met (absolute floor abs_tol), so the last correction is no more
+        // accurate than needed; for GMRES its first step, ||P^{-1} r||, is
+        // the outer test of the current iterate.
         Vecs<float>& f = P->v32;
         double* r = P->v64.r;
+        const bool left = P->solver == FSD_SOLVER_PGMRES;
         if (x0_zero) HIP_TRY(vec_fill<double>(x, P->Np, 0.0, P->stream));
         long iters = 0;
         int outer = 0;
         int status = FSD_ENOTCONV;
-        double relres = 0.0, bnorm = 0.0;
+        double relres = 0.0, bnorm = 0.0, pbnorm = 0.0, prec_rel = 0.0;
         FSD_TRY(norm2(P, b, &bnorm));
+        if (left) {
+            FSD_TRY(op_precond<double>(P, b, P->v64.z, nullptr, nullptr, nullptr));
+            FSD_TRY(norm2(P, P->v64.z, &pbnorm));
+        }
         for (;;) {
             double rnorm = 0.0;
             FSD_TRY(true_residual(P, x, b, r, &rnorm));
             relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
             if (!std::isfinite(relres)) { status = FSD_ENONFINITE; break; }
-            if (relres <= tol || rnorm == 0.0) { status = FSD_OK; break; }
-            if (outer >= P->p.max_outer || iters >= maxit) break;
+            if (rnorm == 0.0 || (!left && relres <= tol)) { status = FSD_OK; break; }
+            if (outer >= P->p.max_outer || iters >= maxit) {
+                if (left) {
+                    double pr = 0.0;
+                    FSD_TRY(op_precond<double>(P, r, P->v64.z, nullptr, nullptr, nullptr));
+                    FSD_TRY(norm2(P, P->v64.z, &pr));
+                    prec_rel = pbnorm > 0.0 ? pr / pbnorm : pr;
+                    if (prec_rel <= tol) status = FSD_OK;
+                }
+                break;
+            }
             HIP_TRY((vec_cast<double, float>(r, f.b, P->Np, 1.0 / rnorm, P->stream)));
+            const double ref = left ? pbnorm : bnorm;
             SolveOut o;
             const int saved = P->last_iters;
-            P->last_iters = P->last_inner_iters;
-            FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o));
-            P->last_inner_iters = P->last_iters;
+            const int slot = std::min(outer, 3);
+            P->last_iters = P->last_inner_iters[slot];
+            FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o,
+                                  tol * ref / rnorm));
+            P->last_inner_iters[slot] = P->last_iters;
             P->last_iters = saved;
+            if (left) {
+                prec_rel = pbnorm > 0.0 ? o.bnorm * rnorm / pbnorm : 0.0;
+                if (prec_rel <= tol) { status = FSD_OK; break; }   // x already passes
+            }
             iters += o.iters;
             ++outer;
             if (o.status == FSD_ENONFINITE || o.status == FSD_EBREAKDOWN) { status = o.status; break; }
@@ -577,7 +631,7 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         S.iters = iters;
         S.outer_iters = outer;
         S.relres = relres;
-        S.solver_relres = relres;
+        S.solver_relres = left ? prec_rel : relres;
         S.status = status;
         S.converged = status == FSD_OK;
     }
@@ -873,6 +927,7 @@ int fsd_profile_read(fsd_problem P, fsd_profile_entry* out, int max) {
     long cnt[2 * K_NKINDS] = {0};
     double ms[2 * K_NKINDS] = {0}, by[2 * K_NKINDS] = {0};
     for (const ProfRec& r : P->prof) {
+        if (r.skip) continue;
         float t = 0.f;
         if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) continue;
         cnt[r.kind] += 1;

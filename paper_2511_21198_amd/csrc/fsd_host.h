@@ -50,10 +50,14 @@ struct Vecs {
 namespace fsd {
 // One profiled launch: hipEvents recorded on the problem's stream around a
 // kernel, with the algorithmic bytes that launch moves.
+// tag: Krylov iteration the launch belongs to (-1: none); skip: the launch
+// returned at once because the solve had already stopped (not counted).
 struct ProfRec {
     int kind;
     hipEvent_t a, b;
     double bytes;
+    int tag;
+    bool skip;
 };
 }  // namespace fsd
 
@@ -83,11 +87,12 @@ struct fsd_problem_s {
     fsd::Vecs<float> v32;
     fsd::Ctrl* h_ctrl = nullptr;   // pinned host mirror of the ctrl header
     int last_iters = 4;
-    int last_inner_iters = 4;
+    int last_inner_iters[4] = {4, 4, 4, 4};   // per defect-correction pass (capped at 3)
     bool have_hist = false;
 
     bool prof_on = false;
     std::vector<fsd::ProfRec> prof;
     std::vector<hipEvent_t> prof_pool;
     size_t prof_next = 0;
+    int prof_tag = -1;
 };

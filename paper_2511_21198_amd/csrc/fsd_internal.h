@@ -31,7 +31,8 @@ struct Ctrl {
     double gm_beta;   // GMRES: ||r0|| of the current cycle
     double gm_hnext;  // GMRES: norm of the new basis vector before scaling
     double gm_scale;  // GMRES: 1 / gm_hnext
-    double pad_[4];
+    double abs2;      // absolute floor of thresh (0: purely relative test)
+    double pad_[3];
     // GMRES small dense state: H is (m+1) x m column-major, then cs, sn, g, y, h
     double gm[1];
 };

@@ -1,0 +1,193 @@
+"""Summarise rocprofv3 output of a solver run per kernel kind.
+
+    python -m paper_2511_21198_amd.rocprof_summary --trace DIR [--fetch DIR]
+        [--write DIR] --np NP [--json OUT.json] [--md OUT.md] [--cmd "..."]
+
+DIR is a rocprofv3 ``-d`` directory written with ``-f csv``: ``--trace`` one
+of ``--kernel-trace --stats``, ``--fetch`` / ``--write`` one of
+``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` (KiB per dispatch).
+
+Kernel dispatches are mapped to the kinds the library's own hipEvent
+profiler reports (toep_x_f32, dst_y_f64, gm_maxpy_f32, ...).  The strided
+Toeplitz kernel serves the y and the z pass of a matvec; a dispatch is the
+y pass when the previous Toeplitz dispatch was an x pass.  Dispatches that
+returned at once because the solve had already stopped (Krylov iterations
+are enqueued ahead of the convergence test) are left out: in the trace
+those shorter than ``--skip-us`` microseconds, in the counter runs those
+that fetched less than 1 MiB.
+
+HBM bytes: FETCH_SIZE and WRITE_SIZE are scaled by the factors that make
+the float64 -> float32 cast kernel (k_cast, NP elements: reads 8 NP bytes,
+writes 4 NP bytes) read and write exactly its own size.  NP is the padded
+vector length of the run (n3 * n2 * round_up(n1, 32)).
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def source_hash() -> str:
+    """Hash of the device-code sources of the library (kernels and the
+    structures they read), to detect counters taken on other kernels."""
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if p.endswith((".hip", ".hpp")) or os.path.basename(p) == "fsd_internal.h":
+            h.update(os.path.basename(p).encode())
+            with open(p, "rb") as f:
+                h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+_KINDS = [
+    (re.compile(r"k2?_toep_x\b"), "toep_x"),
+    (re.compile(r"k2?_toep_s\b"), "toep_s"),
+    (re.compile(r"k2?_dst_x\b"), "dst_x"),
+    (re.compile(r"k_dsts_s\b"), "dsts"),
+    (re.compile(r"k2_dst_s\b.*(true|, ?1)\s*>"), "dsts"),
+    (re.compile(r"k2?_dst_s\b"), "dst_y"),
+    (re.compile(r"k_mdot\b"), "gm_mdot"),
+    (re.compile(r"k_maxpy\b"), "gm_maxpy"),
+    (re.compile(r"k_gm_update\b"), "gm_update"),
+    (re.compile(r"k_update_xr\b"), "pcg_update"),
+    (re.compile(r"k_cast\b"), "cast"),
+]
+
+
+def _dtype(name: str) -> str:
+    m = re.search(r"<\s*(float|double)", name)
+    if not m:
+        return ""
+    return "f32" if m.group(1) == "float" else "f64"
+
+
+def classify(rows, dim=3):
+    """rows: dispatches in submission order with 'Kernel_Name'.  Returns the
+    kind of each (None for kernels outside the table)."""
+    out = []
+    last_toep = None
+    for r in rows:
+        name = r["Kernel_Name"]
+        kind = None
+        for rx, k in _KINDS:
+            if rx.search(name):
+                kind = k
+                break
+        if kind is None:
+            out.append(None)
+            continue
+        if kind == "toep_s":
+            kind = "toep_y" if (last_toep == "toep_x" or dim == 2) else "toep_z"
+        if kind == "dsts":
+            kind = "dsts_z" if dim == 3 else "dsts_y"
+        if kind.startswith("toep"):
+            last_toep = kind
+        dt = _dtype(name)
+        out.append(f"{kind}_{dt}" if dt and kind != "cast" else kind)
+    return out
+
+
+def _read(path_dir, pattern):
+    files = glob.glob(os.path.join(path_dir, "**", pattern), recursive=True)
+    if not files:
+        raise FileNotFoundError(f"no {pattern} under {path_dir}")
+    rows = list(csv.DictReader(open(files[0])))
+    key = "Dispatch_Id" if "Dispatch_Id" in rows[0] else "Correlation_Id"
+    rows.sort(key=lambda r: int(r[key]))
+    return rows
+
+
+def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.0, dim=3):
+    tr = _read(trace_dir, "*kernel_trace.csv")
+    kinds = classify(tr, dim)
+    dur = collections.defaultdict(list)
+    skipped = collections.Counter()
+    for r, k in zip(tr, kinds):
+        if k is None:
+            continue
+        us = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3
+        if us < skip_us:
+            skipped[k] += 1
+        else:
+            dur[k].append(us)
+    res = {k: {"dispatches": len(v), "skipped": skipped[k], "avg_us": sum(v) / len(v),
+               "total_ms": sum(v) / 1e3} for k, v in dur.items()}
+    factors = {}
+    for label, d, cname in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        if not d:
+            continue
+        rows = [r for r in _read(d, "*counter_collection.csv") if r["Counter_Name"] == cname]
+        ks = classify(rows, dim)
+        per = collections.defaultdict(list)
+        for r, k in zip(rows, ks):
+            v = float(r["Counter_Value"]) * 1024.0
+            if k is None or (k != "cast" and label == "fetch" and v < 1 << 20):
+                continue
+            per[k].append(v)
+        if "cast" in per and np_len:
+            expect = (8.0 if label == "fetch" else 4.0) * np_len
+            factors[label] = expect / (sum(per["cast"]) / len(per["cast"]))
+        f = factors.get(label, 1.0)
+        for k, v in per.items():
+            if k in res:
+                res[k][f"{label}_bytes_per_dispatch"] = f * sum(v) / len(v)
+    for k, e in res.items():
+        if "fetch_bytes_per_dispatch" in e and "write_bytes_per_dispatch" in e:
+            e["hbm_bytes_per_dispatch"] = e["fetch_bytes_per_dispatch"] + e["write_bytes_per_dispatch"]
+            e["hbm_gbps"] = e["hbm_bytes_per_dispatch"] / (e["avg_us"] * 1e-6) / 1e9
+    return res, factors
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch")
+    ap.add_argument("--write")
+    ap.add_argument("--np", type=int, help="padded vector length of the run")
+    ap.add_argument("--dim", type=int, default=3)
+    ap.add_argument("--skip-us", type=float, default=8.0)
+    ap.add_argument("--json")
+    ap.add_argument("--md")
+    ap.add_argument("--cmd", default="", help="the profiled command, recorded in the outputs")
+    ap.add_argument("--title", default="")
+    a = ap.parse_args(argv)
+    res, factors = summarise(a.trace, a.fetch, a.write, a.np, a.skip_us, a.dim)
+    doc = {"command": a.cmd, "source_hash": source_hash(), "np": a.np,
+           "counter_scale": factors, "kinds": res}
+    if a.json:
+        with open(a.json, "w") as f:
+            json.dump(doc, f, indent=1, sort_keys=True)
+    lines = []
+    if a.title:
+        lines += [f"# {a.title}", ""]
+    lines += ["Command:", "", "```", a.cmd, "```", "",
+              f"Library source hash: `{doc['source_hash']}`.  Counter scale factors "
+              f"(k_cast calibration, {a.np} elements): "
+              + ", ".join(f"{k} x{v:.4f}" for k, v in factors.items()), "",
+              f"Dispatches shorter than {a.skip_us:g} us (enqueued after the solve had "
+              "stopped; they return at once) are listed as skipped and excluded.", "",
+              "| kind | dispatches | skipped | avg us | total ms | HBM MB/dispatch | HBM GB/s |",
+              "|---|---:|---:|---:|---:|---:|---:|"]
+    for k, e in sorted(res.items(), key=lambda kv: -kv[1]["total_ms"]):
+        hb = e.get("hbm_bytes_per_dispatch")
+        lines.append(f"| {k} | {e['dispatches']} | {e['skipped']} | {e['avg_us']:.2f} | "
+                     f"{e['total_ms']:.3f} | {hb / 1e6:.2f} | {e['hbm_gbps']:.0f} |" if hb else
+                     f"| {k} | {e['dispatches']} | {e['skipped']} | {e['avg_us']:.2f} | "
+                     f"{e['total_ms']:.3f} | - | - |")
+    text = "\n".join(lines) + "\n"
+    if a.md:
+        with open(a.md, "w") as f:
+            f.write(text)
+    print(text)
+
+
+if __name__ == "__main__":
+    main()
