@@ -143,3 +143,36 @@ def config_learned(seed: int, n: int = 255, M: int = 200) -> Workload:
 def random_grid(shape, seed: int):
     """Standard-normal test vector of the given grid shape."""
     return np.random.default_rng(seed).standard_normal(shape)
+
+
+def nn_initial_params(seed: int, layers) -> np.ndarray:
+    """He-uniform initial weights for a stack of 3x3x3 convolutions, biases
+    zero; the last layer is scaled by 0.1 so that the initial prediction is
+    close to the previous iterate.  layers: sequence of (c_in, c_out).
+    Flat float32 vector, per layer W[o, i, 3, 3, 3] (C order) then b[o]."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for k, (ci, co) in enumerate(layers):
+        lim = np.sqrt(6.0 / (ci * 27))
+        if k == len(layers) - 1:
+            lim *= 0.1
+        parts.append(rng.uniform(-lim, lim, co * ci * 27))
+        parts.append(np.zeros(co))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def bumps_source_torch(n, centres, width, device):
+    """bumps_source evaluated with torch on `device` (float64): the same
+    separable outer products, for sources generated per time step on the
+    GPU."""
+    import torch
+    d = len(n)
+    ax = [torch.arange(1, k + 1, dtype=torch.float64, device=device) / (k + 1) for k in n]
+    out = torch.zeros(tuple(reversed(n)), dtype=torch.float64, device=device)
+    for c in centres:
+        g = None
+        for i in reversed(range(d)):
+            e = torch.exp(-((ax[i] - float(c[i])) ** 2) / (2.0 * width * width))
+            g = e if g is None else torch.einsum("...,k->...k", g, e)
+        out += g
+    return out
