@@ -78,10 +78,14 @@ typedef enum {
     FSD_X0_ZERO = 1,       /* initial guess 0 (the setting that reproduces the
                               paper's iteration counts) */
     FSD_X0_EXTERNAL = 2,   /* initial guess passed to fsd_cn_step */
-    FSD_X0_EXTRAP = 3      /* 2 u^{m-1} - u^{m-2}: linear extrapolation in time
+    FSD_X0_EXTRAP = 3,     /* 2 u^{m-1} - u^{m-2}: linear extrapolation in time
                               from the previous call's u_prev (the history is
                               kept in the workspace; u^{m-1} on the first call
                               after fsd_bind or fsd_reset_history) */
+    FSD_X0_GUARDED = 4     /* d_guess (e.g. the network of fsd_nn.h) unless its
+                              float64 residual ||b - A guess|| exceeds that of
+                              u^{m-1}; then u^{m-1} (fsd_stats.x0_fallback = 1).
+                              Costs two extra float64 matvecs. */
 } fsd_x0_mode;
 
 /* Problem parameters.  Fill with fsd_default_params() first. */
@@ -114,6 +118,7 @@ typedef struct {
     double relres;         /* final ||b - A x||_2 / ||b||_2 in float64 */
     double solver_relres;  /* the solver's own stopping quantity at exit */
     int status;            /* fsd_status of the solve */
+    int x0_fallback;       /* FSD_X0_GUARDED: 1 if u^{m-1} replaced the guess */
 } fsd_stats;
 
 typedef struct fsd_problem_s* fsd_problem;
@@ -167,7 +172,8 @@ fsd_status fsd_solve(fsd_problem prob, const double* d_b, double* d_x, fsd_stats
 /* One Crank-Nicolson step (Section 2, ``CN`` / ``linear_sys``):
  * b = (A_N - K) u_prev + dt F, then solve A u_next = b from the initial
  * guess selected by x0_mode (u_prev, 0 or d_guess).  d_F may be NULL
- * (f = 0); d_guess is read only in FSD_X0_EXTERNAL mode.  d_u_prev may
+ * (f = 0); d_guess is read only in FSD_X0_EXTERNAL and FSD_X0_GUARDED
+ * modes.  d_u_prev may
  * equal d_u_next.  st may be NULL. */
 fsd_status fsd_cn_step(fsd_problem prob, const double* d_u_prev, const double* d_F,
                        const double* d_guess, double* d_u_next, fsd_stats* st);

@@ -22,7 +22,7 @@ SOLVER_AUTO, SOLVER_PCG, SOLVER_PGMRES = 0, 1, 2
 # fsd_precision
 PREC_FP64, PREC_MIXED = 0, 1
 # fsd_x0_mode
-X0_PREV, X0_ZERO, X0_EXTERNAL, X0_EXTRAP = 0, 1, 2, 3
+X0_PREV, X0_ZERO, X0_EXTERNAL, X0_EXTRAP, X0_GUARDED = 0, 1, 2, 3, 4
 
 
 class Params(C.Structure):
@@ -56,6 +56,7 @@ class Stats(C.Structure):
         ("relres", C.c_double),
         ("solver_relres", C.c_double),
         ("status", C.c_int),
+        ("x0_fallback", C.c_int),
     ]
 
     def as_dict(self):
@@ -71,7 +72,8 @@ class ProfileEntry(C.Structure):
     ]
 
 
-# Every symbol declared in include/fsd.h, with (restype, argtypes).
+# Every symbol declared in include/fsd.h and include/fsd_nn.h, with
+# (restype, argtypes).
 _VP = C.c_void_p
 SIGNATURES = {
     "fsd_default_params": (C.c_int, [C.POINTER(Params)]),
@@ -92,6 +94,22 @@ SIGNATURES = {
     "fsd_status_string": (C.c_char_p, [C.c_int]),
     "fsd_last_error": (C.c_char_p, []),
     "fsd_version": (C.c_char_p, []),
+    # fsd_nn.h
+    "fsd_nn_param_count": (C.c_long, []),
+    "fsd_nn_layer": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "fsd_nn_create": (C.c_int, [C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(_VP)]),
+    "fsd_nn_destroy": (None, [_VP]),
+    "fsd_nn_workspace_bytes": (C.c_size_t, [_VP]),
+    "fsd_nn_bind": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
+    "fsd_nn_features": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double, C.POINTER(C.c_double), _VP, _VP,
+                                  _VP]),
+    "fsd_nn_crop": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
+                              C.c_int, C.c_int, C.c_int, _VP, _VP]),
+    "fsd_nn_forward": (C.c_int, [_VP, _VP, _VP, _VP]),
+    "fsd_nn_loss_grad": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),
+    "fsd_nn_adam": (C.c_int, [C.c_long, _VP, _VP, _VP, _VP, C.c_int, C.c_double, C.c_double,
+                              C.c_double, C.c_double, _VP]),
+    "fsd_nn_predict": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double, C.POINTER(C.c_double), _VP]),
 }
 
 

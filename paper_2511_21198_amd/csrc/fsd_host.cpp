@@ -759,7 +759,7 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
     if (p->precision == FSD_PREC_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
         return fail(FSD_EINVAL, "inner_tol must be in (0, 1)");
     if (p->solver < 0 || p->solver > 2) return fail(FSD_EINVAL, "unknown solver");
-    if (p->x0_mode < 0 || p->x0_mode > 3) return fail(FSD_EINVAL, "unknown x0_mode");
+    if (p->x0_mode < 0 || p->x0_mode > FSD_X0_GUARDED) return fail(FSD_EINVAL, "unknown x0_mode");
 
     fsd_problem P = new (std::nothrow) fsd_problem_s();
     if (!P) return fail(FSD_EINVAL, "out of host memory");
@@ -880,7 +880,8 @@ fsd_status fsd_cn_step(fsd_problem P, const double* d_u_prev, const double* d_F,
                        double* d_u_next, fsd_stats* st) {
     FSD_TRY(check_bound(P));
     if (!d_u_prev || !d_u_next) return fail(FSD_EINVAL, "null vector");
-    if (P->p.x0_mode == FSD_X0_EXTERNAL && !d_guess) return fail(FSD_EINVAL, "x0_mode EXTERNAL needs a guess");
+    if ((P->p.x0_mode == FSD_X0_EXTERNAL || P->p.x0_mode == FSD_X0_GUARDED) && !d_guess)
+        return fail(FSD_EINVAL, "x0_mode EXTERNAL / GUARDED needs a guess");
     Vecs<double>& v = P->v64;
     hipStream_t s = P->stream;
     const int n1 = P->ax[0].n;
@@ -900,7 +901,17 @@ fsd_status fsd_cn_step(fsd_problem P, const double* d_u_prev, const double* d_F,
         HIP_TRY(vec_extrap(v.x, v.up, P->Np, P->have_hist ? 1 : 0, s));
         P->have_hist = true;
     }
+    int fallback = 0;
+    if (P->p.x0_mode == FSD_X0_GUARDED) {
+        double rp = 0.0, rg = 0.0;
+        FSD_TRY(true_residual(P, v.x, v.b, v.r, &rp));
+        HIP_TRY(vec_pack<double>(d_guess, v.p, n1, P->P1, P->rows, 1.0, s));
+        FSD_TRY(true_residual(P, v.p, v.b, v.r, &rg));
+        if (std::isfinite(rg) && rg <= rp) HIP_TRY(vec_copy<double>(v.p, v.x, P->Np, s));
+        else fallback = 1;
+    }
     fsd_status stt = solve_internal(P, v.x, v.b, x0_zero, st);
+    if (st) st->x0_fallback = fallback;
     if (stt == FSD_EHIP) return stt;
     HIP_TRY(vec_unpack<double>(v.x, d_u_next, n1, P->P1, P->rows, s));
     return stt;
@@ -963,3 +974,7 @@ fsd_status fsd_get_coefficients(fsd_problem P, int axis, double* q, double* lam,
 }
 
 }  // extern "C"
+
+namespace fsd {
+fsd_status set_error(fsd_status s, const std::string& msg) { return fail(s, msg); }
+}  // namespace fsd

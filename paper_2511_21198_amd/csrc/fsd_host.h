@@ -18,6 +18,9 @@ struct Axis {
     std::vector<double> tw;            // twiddles exp(-2 pi i e/L), interleaved
 };
 
+// Records msg as the thread's last error (fsd_last_error) and returns s.
+fsd_status set_error(fsd_status s, const std::string& msg);
+
 void q_coefficients(double delta, int n, std::vector<long double>& q);
 void axis_setup(Axis& ax, int n, double a, double b, double delta, double kp, double km, double dt);
 void axis_spectra(Axis& ax, int axis_index);

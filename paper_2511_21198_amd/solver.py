@@ -55,7 +55,7 @@ class Problem:
         p.inner_tol = float(inner_tol)
         p.max_outer = int(max_outer)
         p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL,
-                     "extrap": nat.X0_EXTRAP}[x0]
+                     "extrap": nat.X0_EXTRAP, "guarded": nat.X0_GUARDED}[x0]
         p.allow_delta_zero = int(allow_delta_zero)
         self.params = p
         self.dim = dim

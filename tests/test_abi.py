@@ -1,4 +1,4 @@
-"""The C-ABI library: it loads, exports every symbol include/fsd.h declares,
+"""The C-ABI library: it loads, exports every symbol include/*.h declares,
 validates parameters, and its host-side coefficients match the oracle.
 CPU only: no call here touches a GPU (fsd_init_problem and
 fsd_get_coefficients are host-only)."""
@@ -10,13 +10,19 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "fsd.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("fsd.h", "fsd_nn.h")]
 
 
 def header_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fsd_[A-Za-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(fsd_[A-Za-z_0-9]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_headers_listed():
+    assert sorted(os.listdir(os.path.join(ROOT, "include"))) == sorted(os.path.basename(h) for h in HEADERS)
 
 
 @pytest.fixture(scope="module")

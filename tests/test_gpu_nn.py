@@ -1,0 +1,200 @@
+"""Parity of the warm-start network kernels (through the C ABI of
+include/fsd_nn.h) with the float64 reference network of oracle/nn.py.
+
+Tolerances.  The kernels store activations and input gradients in bfloat16
+(8-bit significand, unit roundoff u = 2^-9) and accumulate in float32; the
+oracle is float64 and is fed the same bf16-rounded parameters and inputs.
+Each of the 7 layers rounds its output once, so the forward output carries a
+relative error of a few u (measured about 3e-3; bound used 2e-2).  The
+backward pass rounds 13 more tensors and its per-layer gradients are sums
+over many voxels of products of rounded values: each layer's gradient is
+checked to a relative 2-norm error of 6e-2 and a cosine of at least 0.998.
+Features, crop and Adam are float32 element-wise maps: 1e-6 relative.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import cn, nn as onn, operators as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ws():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2511_21198_amd import warmstart
+    return warmstart
+
+
+def bf16_round(a):
+    """float32 -> nearest bfloat16 (ties to even), returned as float64."""
+    f = np.ascontiguousarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def relerr(a, b):
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def _params(seed, jitter=0.05):
+    rng = np.random.default_rng(seed + 100)
+    p = workloads.nn_initial_params(seed, [(ci, co) for _, ci, co, _, _ in onn.LAYERS])
+    return (p + jitter * rng.standard_normal(p.size) * np.abs(p).mean()).astype(np.float32) + \
+        np.float32(0.01) * (np.arange(p.size) % 7 == 0)
+
+
+def _x(batch, dims, seed):
+    rng = np.random.default_rng(seed)
+    x = rng.standard_normal((batch, 5) + dims).astype(np.float32)
+    x[:, 2:] = rng.uniform(-0.5, 1.0, (batch, 3, 1, 1, 1))
+    return x
+
+
+def dev32(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+@pytest.mark.parametrize("dims,batch", [((9, 12, 19), 2), ((5, 7, 33), 1), ((16, 16, 16), 1),
+                                        ((1, 3, 2), 1)])
+def test_forward_parity(ws, dims, batch):
+    p = _params(1)
+    x = _x(batch, dims, 2)
+    net = ws.Net(dims[2], dims[1], dims[0], batch=batch)
+    y = net.forward(dev32(p), dev32(x)).cpu().numpy()
+    pr = onn.unflatten(bf16_round(p))
+    for b in range(batch):
+        yo, _ = onn.forward(pr, bf16_round(x[b]))
+        assert relerr(y[b].astype(np.float64), yo) <= 2e-2, b
+
+
+def test_loss_grad_parity(ws):
+    dims, batch, margin = (10, 12, 14), 2, 1
+    p = _params(3)
+    x = _x(batch, dims, 4)
+    rng = np.random.default_rng(5)
+    t = rng.standard_normal((batch,) + dims).astype(np.float32)
+    net = ws.Net(dims[2], dims[1], dims[0], batch=batch, training=True)
+    loss, g = net.loss_grad(dev32(p), dev32(x), dev32(t), margin)
+    loss = float(loss.cpu()[0])
+    g = g.cpu().numpy().astype(np.float64)
+    pr = onn.unflatten(bf16_round(p))
+    # oracle: the batch loss is the mean over both grids of the interior squares
+    Ls, gs = [], []
+    for b in range(batch):
+        L, gb = onn.loss_and_grad(pr, bf16_round(x[b]), t[b].astype(np.float64), margin)
+        Ls.append(L)
+        gs.append(gb)
+    Lo = float(np.mean(Ls))
+    go = np.mean(gs, axis=0)
+    assert abs(loss - Lo) <= 2e-2 * Lo
+    k = 0
+    for name, ci, co, _, _ in onn.LAYERS:
+        n = co * ci * 27 + co
+        a, b = g[k:k + n], go[k:k + n]
+        cos = float(a @ b / (np.linalg.norm(a) * np.linalg.norm(b)))
+        assert relerr(a, b) <= 6e-2 and cos >= 0.998, (name, relerr(a, b), cos)
+        k += n
+
+
+def test_adam_parity(ws):
+    rng = np.random.default_rng(6)
+    n = 1000
+    p, g = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    m, v = (0.1 * rng.standard_normal(n)).astype(np.float32), rng.uniform(0, 1, n).astype(np.float32)
+    tp, tg, tm, tv = dev32(p), dev32(g), dev32(m), dev32(v)
+    ws.adam(tp, tg, tm, tv, 3, 1e-2)
+    po, mo, vo = onn.adam(p.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                          v.astype(np.float64), 3, 1e-2)
+    assert np.allclose(tp.cpu().numpy(), po, rtol=1e-6, atol=1e-7)
+    assert np.allclose(tm.cpu().numpy(), mo, rtol=1e-6, atol=1e-7)
+    assert np.allclose(tv.cpu().numpy(), vo, rtol=1e-6, atol=1e-7)
+
+
+def test_features_crop_predict(ws):
+    dims = (11, 13, 17)
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal(dims)
+    F = rng.standard_normal(dims)
+    un = u + 0.01 * rng.standard_normal(dims)
+    dt, eta = 0.02, [3.0, 7.5, 0.4]
+    net = ws.Net(dims[2], dims[1], dims[0])
+    tu, tF, tun = (torch.from_numpy(a).cuda() for a in (u, F, un))
+    x, t, s = net.features(tu, tF, dt, eta, unext=tun)
+    xo, so = onn.features(u, F, dt, eta)
+    assert np.isclose(float(s.cpu()[0]), so, rtol=1e-13)
+    assert np.allclose(x.cpu().numpy(), xo, rtol=1e-6, atol=1e-7)
+    assert np.allclose(t.cpu().numpy(), (un - u) / so, rtol=1e-6, atol=1e-7)
+    c = ws.crop(x, (2, 3, 4), (5, 6, 7)).cpu().numpy()
+    assert np.array_equal(c, x.cpu().numpy()[:, 2:7, 3:9, 4:11])
+    p = _params(8)
+    guess = net.predict(dev32(p), tu, tF, dt, eta).cpu().numpy()
+    _, yo = None, onn.forward(onn.unflatten(bf16_round(p)), bf16_round(xo))[0]
+    assert relerr((guess - u) / so, yo) <= 2e-2
+
+
+def _solver_pairs(n, steps, seed):
+    """(u^{m-1}, F^{m-1/2}, u^m) triples from the float64 oracle CN run."""
+    w = workloads.config_learned(seed, n=n, M=steps)
+    prob = op.Problem(3, w.n, w.delta, w.kplus, w.kminus, T=w.T, M=w.M)
+    out = []
+    u = w.u0
+    for m in range(1, steps + 1):
+        F = workloads.moving_bumps_source(w.n, w.bumps, (m - 0.5) * prob.dt)
+        un, _ = cn.run(prob, u, lambda _m: F, tol=1e-12, steps=1)
+        out.append((u, F, un))
+        u = un
+    return prob, out
+
+
+def test_training_reduces_loss(ws):
+    """A short Adam run on solver-generated pairs lowers the training loss."""
+    n = 15
+    prob, pairs = _solver_pairs(n, 6, seed=11)
+    eta = list(prob.eta)
+    full = ws.Net(n, n, n)
+    xs, ts = [], []
+    for u, F, un in pairs[1:]:
+        x, t, _ = full.features(*(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (u, F)),
+                                prob.dt, eta, unext=torch.from_numpy(un).cuda())
+        xs.append(x)
+        ts.append(t)
+    X = torch.stack(xs).contiguous()
+    T = torch.stack(ts).contiguous()
+    net = ws.Net(n, n, n, batch=X.shape[0], training=True)
+    p = dev32(workloads.nn_initial_params(0, [(ci, co) for _, ci, co, _, _ in onn.LAYERS]))
+    m, v = torch.zeros_like(p), torch.zeros_like(p)
+    losses = []
+    for it in range(1, 121):
+        loss, g = net.loss_grad(p, X, T, 1)
+        losses.append(float(loss.cpu()[0]))
+        ws.adam(p, g, m, v, it, 2e-3)
+    assert np.isfinite(losses).all()
+    assert min(losses[-10:]) < 0.5 * losses[0], (losses[0], losses[-10:])
+
+
+def test_guarded_initial_guess():
+    from paper_2511_21198_amd.solver import Problem
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    n = [15, 11, 23]
+    kw = dict(dim=3, n=n, delta=[0.3, 0.5, 0.7], kplus=[1, 1, 1], kminus=[1, 1, 1], M=4, T=1.0,
+              tol=1e-10)
+    rng = np.random.default_rng(12)
+    u0 = torch.from_numpy(rng.standard_normal(tuple(reversed(n)))).cuda()
+    F = torch.from_numpy(workloads.random_grid(tuple(reversed(n)), 13)).cuda()
+    ref, st_ref = Problem(**kw, x0="prev").cn_step(u0, F)
+    exact, _ = Problem(**{**kw, "tol": 1e-13}, x0="prev").cn_step(u0, F)
+    g = Problem(**kw, x0="guarded")
+    good, st_good = g.cn_step(u0, F, guess=exact)
+    assert st_good["x0_fallback"] == 0 and st_good["iters"] <= 1
+    assert torch.allclose(good, exact, rtol=0, atol=1e-9 * float(exact.abs().max()))
+    bad_guess = exact + 1e3 * torch.from_numpy(rng.standard_normal(tuple(reversed(n)))).cuda()
+    bad, st_bad = g.cn_step(u0, F, guess=bad_guess)
+    assert st_bad["x0_fallback"] == 1
+    assert st_bad["iters"] == st_ref["iters"]
+    assert torch.equal(bad, ref)
