@@ -151,6 +151,85 @@ def matvec_bench(w, reps=100):
                     "included in apply_A_ms), 100 calls"}
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2511_21198_amd", "weights", "warmstart_3d_sym.npy")
+
+
+def learned_workload(a, seed=10001, n=255, M=200):
+    """Learned warm start workload (3D symmetric, orders drawn for the
+    evaluation seed, moving bumps, M steps to T = 1, tol 1e-8): plain float64
+    PCG from u^{m-1} against the same solver from the network's guess (with
+    the residual guard), float64 and mixed precision, and linear
+    extrapolation in time (the network's base guess).  All sources F^{m-1/2} are generated on the GPU
+    before timing; a step includes the network inference when it is used."""
+    import torch
+    import workloads
+    from paper_2511_21198_amd.solver import Problem
+    w = workloads.config_learned(seed, n=n, M=M)
+    dev = torch.device("cuda:0")
+    dt = w.T / w.M
+    Fs = [workloads.bumps_source_torch([n] * 3, w.bumps["c0"] + w.bumps["v"] * ((m - 0.5) * dt),
+                                       w.bumps["width"], dev) for m in range(1, M + 1)]
+    u0 = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    common = dict(dim=3, n=[n] * 3, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
+                  solver="pcg", tol=w.tol)
+    params = None
+    net = None
+    if os.path.exists(WEIGHTS):
+        from paper_2511_21198_amd import warmstart
+        params = torch.from_numpy(np.load(WEIGHTS)).to(dev)
+        net = warmstart.Net(n, n, n)
+    out = {"workload": f"3D symmetric {n}^3, (alpha,beta,gamma)={np.round(w.delta, 3).tolist()} "
+                       f"(seed {seed}), k=1, {M} CN steps to T=1, 8 moving seeded bumps, u0=0, "
+                       "PCG, tol 1e-8",
+           "weights": os.path.relpath(WEIGHTS, ROOT) if net else None}
+    variants = [("fp64_prev", "fp64", "prev"), ("fp64_extrap", "fp64", "extrap"),
+                ("mixed_prev", "mixed", "prev"), ("mixed_extrap", "mixed", "extrap")]
+    if net:
+        variants += [("fp64_net", "fp64", "guarded"), ("mixed_net", "mixed", "guarded")]
+    finals = {}
+    for name, prec, x0 in variants:
+        p = Problem(**common, precision=prec, inner_tol=1e-4, x0=x0)
+        eta = [p.coefficients(i)[2] for i in range(3)]
+        u = u0.clone()
+        un = torch.empty_like(u)
+        up = torch.empty_like(u)
+        guess = torch.empty_like(u) if x0 == "guarded" else None
+        its, fb = [], 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for m in range(M):
+            if m == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if guess is not None:
+                net.predict(params, u, Fs[m], dt, eta, u_prev=up if m > 0 else None,
+                            F_prev=Fs[m - 1] if m > 0 else None, out=guess)
+            un, st = p.cn_step(u, Fs[m], guess=guess, out=un)
+            its.append(st["iters"])
+            fb += st["x0_fallback"]
+            up, u, un = u, un, up
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        finals[name] = u.clone()
+        out[name] = {"steps_per_s": round((M - 1) / t, 2), "mean_iters": round(float(np.mean(its)), 3),
+                     "iters_first10": its[:10]}
+        if x0 == "guarded":
+            out[name]["fallbacks"] = fb
+        log(f"learned {name}: {out[name]}")
+        del p
+    pref = Problem(**{**common, "tol": 1e-12}, precision="fp64", x0="prev")
+    u = u0.clone()
+    for m in range(M):
+        u, _ = pref.cn_step(u, Fs[m])
+    nrm = torch.linalg.vector_norm(u)
+    for name in finals:
+        out[name]["rel_err_vs_tight_fp64"] = float(torch.linalg.vector_norm(finals[name] - u) / nrm)
+    base = out["fp64_prev"]["steps_per_s"]
+    for name in finals:
+        out[name]["speedup_vs_fp64_prev"] = round(out[name]["steps_per_s"] / base, 3)
+    return out
+
+
 def secondary_symmetric(a):
     """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
     PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
@@ -197,6 +276,10 @@ def main(argv=None):
                     help="skip the tight float64 reference run used for the error figures")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 127^3 symmetric PCG comparison")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned warm start workload (255^3, 200 steps)")
+    ap.add_argument("--only-learned", action="store_true",
+                    help="run only the learned warm start workload and print its JSON")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not "
@@ -209,6 +292,9 @@ def main(argv=None):
     import workloads
     from paper_2511_21198_amd.solver import Problem
 
+    if a.only_learned:
+        print(json.dumps(learned_workload(a)), flush=True)
+        return 0
     w = workloads.config_3d_nonsymmetric(seed=0, n=a.n, M=16)
     dev = torch.device("cuda:0")
     F = torch.from_numpy(w.F).to(dev)
@@ -299,6 +385,8 @@ def main(argv=None):
     if not a.no_secondary:
         out["matvec_fp64"] = matvec_bench(w)
         out["secondary"] = secondary_symmetric(a)
+    if not a.no_learned:
+        out["learned"] = learned_workload(a)
     out["kernels"] = {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
                           "gbps": round(v["gbps"], 1), "total_ms": round(v["total_ms"], 3)}
                       for k, v in prof.items()}

@@ -1,16 +1,20 @@
 /* Learned warm start for the Crank-Nicolson solves (extension; not part of
- * arXiv 2511.21198).  A four-level 3D convolution network predicts u^m from
- * (u^{m-1}, F^{m-1/2}) so that PCG / PGMRES (Section 3) start closer to the
- * solution; the solver's plain initial guess u^{m-1} remains the fallback
- * (FSD_X0_GUARDED in fsd.h).
+ * arXiv 2511.21198).  A four-level 3D convolution network corrects the
+ * linear extrapolation in time 2 u^{m-1} - u^{m-2} of the next iterate, so
+ * that PCG / PGMRES (Section 3) start closer to the solution; the solver's
+ * plain initial guess u^{m-1} remains the fallback (FSD_X0_GUARDED in
+ * fsd.h).  The Crank-Nicolson matrices do not depend on m, so the
+ * extrapolation error is a linear map of du = u^{m-1} - u^{m-2} and
+ * dF = F^{m-1/2} - F^{m-3/2}; these are the network's inputs.
  *
  * Network (all convolutions 3x3x3, zero padding, stride 1, with bias):
- *   features x = [u/s, dt F/s, log(eta_1)/4, log(eta_2)/4, log(eta_3)/4],
- *            s = rms(u) + rms(dt F) + 1e-30;
+ *   features x = [du/s, dt dF/s, log(eta_1)/4, log(eta_2)/4, log(eta_3)/4],
+ *            s = rms(du) + rms(dt dF) + 1e-30 (no history: du = 0,
+ *            dF = F^{m-1/2});
  *   e0 = relu(conv 5->16)  e1 = relu(conv(pool e0) 16->32)
  *   e2 = relu(conv(pool e1) 32->64)  e3 = relu(conv(pool e2) 64->64)
  *   d2 = relu(conv(up e3 + e2) 64->32)  d1 = relu(conv(up d2 + e1) 32->16)
- *   y  = conv(up d1 + e0) 16->1;  guess = u + s y.
+ *   y  = conv(up d1 + e0) 16->1;  guess = u^{m-1} + du + s y.
  * pool: 2x2x2 average, stride 2, size ceil(n/2) (absent inputs count as
  * zero); up: nearest neighbour.  Activations are bfloat16, convolutions run
  * on bf16 MFMA with float32 accumulation; parameters, gradients and Adam
@@ -53,11 +57,15 @@ size_t fsd_nn_workspace_bytes(fsd_nn nn);
  * 256-byte aligned) and a stream. */
 fsd_status fsd_nn_bind(fsd_nn nn, void* d_ws, size_t bytes, void* stream);
 
-/* Features of one grid (batch index 0; nx, ny, nz of the instance):
- * d_x (float32 [5][nz][ny][nx]); optional d_t = (d_unext - d_u) / s and
- * d_s (device double).  d_F and d_unext may be NULL. */
-fsd_status fsd_nn_features(fsd_nn nn, const double* d_u, const double* d_F, const double* d_unext,
-                           double dt, const double eta[3], float* d_x, float* d_t, double* d_s);
+/* Features of one grid at step m (batch index 0; nx, ny, nz of the
+ * instance): d_u = u^{m-1}, d_uprev = u^{m-2}, d_F = F^{m-1/2},
+ * d_Fprev = F^{m-3/2}; d_x receives float32 [5][nz][ny][nx]; optional
+ * training target d_t = (d_unext - 2 d_u + d_uprev) / s (d_unext = u^m) and
+ * d_s (device double).  d_uprev, d_F, d_Fprev and d_unext may be NULL
+ * (no history: du = 0 and the target uses u_prev = u; zero sources). */
+fsd_status fsd_nn_features(fsd_nn nn, const double* d_u, const double* d_uprev, const double* d_F,
+                           const double* d_Fprev, const double* d_unext, double dt,
+                           const double eta[3], float* d_x, float* d_t, double* d_s);
 
 /* Copies the box [x0, x0+cx) x [y0, y0+cy) x [z0, z0+cz) of each of the
  * c channels of d_src (float32 [c][nz][ny][nx]) to d_dst ([c][cz][cy][cx]). */
@@ -80,8 +88,10 @@ fsd_status fsd_nn_loss_grad(fsd_nn nn, const float* d_params, const float* d_x, 
 fsd_status fsd_nn_adam(long count, float* d_p, const float* d_g, float* d_m, float* d_v, int t,
                        double lr, double b1, double b2, double eps, void* stream);
 
-/* guess = u + s * network(features(u, F)) on one full grid (batch index 0). */
-fsd_status fsd_nn_predict(fsd_nn nn, const float* d_params, const double* d_u, const double* d_F,
+/* guess = u + (u - u_prev) + s * network(features) on one full grid
+ * (batch index 0); the arguments as in fsd_nn_features. */
+fsd_status fsd_nn_predict(fsd_nn nn, const float* d_params, const double* d_u,
+                          const double* d_uprev, const double* d_F, const double* d_Fprev,
                           double dt, const double eta[3], double* d_guess);
 
 #ifdef __cplusplus

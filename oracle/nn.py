@@ -3,12 +3,19 @@
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
 The warm start is not part of the paper: it is an extension that predicts
-the next Crank-Nicolson iterate u^{m} from (u^{m-1}, F^{m-1/2}) so that the
-Krylov solve of Section 3 starts closer to its solution.  This module is the
-plain definition of that network, written out in NumPy:
+the next Crank-Nicolson iterate u^{m} so that the Krylov solve of Section 3
+starts closer to its solution.  It corrects the linear extrapolation
+2 u^{m-1} - u^{m-2}.  The Crank-Nicolson matrices do not change with m, so
+the extrapolation error u^m - 2 u^{m-1} + u^{m-2} is A^{-1} applied to
+dt (F^{m-1/2} - F^{m-3/2}) - 2 K (u^{m-1} - u^{m-2}): a linear map of the
+last increment and the last change of the source, which is what the
+network sees.  This module is the plain definition of that network,
+written out in NumPy:
 
-* features: x = [u / s, dt F / s, log(eta_1)/4, log(eta_2)/4, log(eta_3)/4],
-  s = rms(u) + rms(dt F) (+1e-30), on the n_3 x n_2 x n_1 grid;
+* features: x = [du / s, dt dF / s, log(eta_1)/4, log(eta_2)/4,
+  log(eta_3)/4] with du = u^{m-1} - u^{m-2}, dF = F^{m-1/2} - F^{m-3/2}
+  and s = rms(du) + rms(dt dF) (+1e-30), on the n_3 x n_2 x n_1 grid; the
+  first step has no history (du = 0, dF = F);
 * a four-level U-shaped network (levels 0..3, each level half the size of
   the previous one, rounded up):
 
@@ -24,11 +31,12 @@ plain definition of that network, written out in NumPy:
       out[o, z, y, x] = b[o] + sum_{i, a, c, d} W[o, i, a, c, d] in[i, z+a-1, y+c-1, x+d-1];
   pool: 2x2x2 average with stride 2, out size ceil(n/2), absent inputs zero;
   up:   nearest-neighbour, out[j] = in[j // 2], cropped to the finer size;
-* prediction: guess = u + s * y.
+* prediction: guess = u + (u - u_prev) + s * y, the linear extrapolation in
+  time corrected by the network.
 
 Training minimises the mean squared error between y and the scaled
-increment t = (u^{m} - u^{m-1}) / s over an interior region, with Adam
-(Kingma and Ba, 2015).
+extrapolation error t = (u^{m} - 2 u^{m-1} + u^{m-2}) / s over an interior
+region, with Adam (Kingma and Ba, 2015).
 
 Pins (tests/test_oracle_nn.py): conv against a brute-force loop; pool and
 up against their adjoint identities and brute force; the backward pass
@@ -156,14 +164,19 @@ def relu(x):
 
 # ------------------------------------------------------------------ network
 
-def features(u, F, dt, eta):
-    """Network input and scale s for one grid function u (n3, n2, n1)."""
+def features(u, F, dt, eta, u_prev=None, F_prev=None):
+    """Network input and scale s at step m: u = u^{m-1}, u_prev = u^{m-2},
+    F = F^{m-1/2}, F_prev = F^{m-3/2} (None: no history / zero source)."""
     u = np.asarray(u, dtype=np.float64)
-    f = dt * (np.zeros_like(u) if F is None else np.asarray(F, dtype=np.float64))
-    s = np.sqrt(np.mean(u * u)) + np.sqrt(np.mean(f * f)) + 1e-30
+    z = np.zeros_like(u)
+    du = z if u_prev is None else u - np.asarray(u_prev, dtype=np.float64)
+    f = z if F is None else np.asarray(F, dtype=np.float64)
+    fp = z if F_prev is None else np.asarray(F_prev, dtype=np.float64)
+    df = dt * (f - fp)
+    s = np.sqrt(np.mean(du * du)) + np.sqrt(np.mean(df * df)) + 1e-30
     x = np.empty((N_IN,) + u.shape)
-    x[0] = u / s
-    x[1] = f / s
+    x[0] = du / s
+    x[1] = df / s
     for i in range(3):
         x[2 + i] = np.log(eta[i]) / 4.0
     return x, s
@@ -240,11 +253,18 @@ def loss_and_grad(params, x, t, margin=0):
     return L, flatten(g)
 
 
-def predict(params, u, F, dt, eta):
-    """guess = u + s * y."""
-    x, s = features(u, F, dt, eta)
+def target(u, u_prev, u_next, s):
+    """Scaled extrapolation error (u_next - 2 u + u_prev) / s."""
+    up = u if u_prev is None else u_prev
+    return (u_next - 2.0 * u + up) / s
+
+
+def predict(params, u, F, dt, eta, u_prev=None, F_prev=None):
+    """guess = u + (u - u_prev) + s * y."""
+    x, s = features(u, F, dt, eta, u_prev, F_prev)
     y, _ = forward(params, x)
-    return u + s * y
+    du = 0.0 if u_prev is None else u - u_prev
+    return u + du + s * y
 
 
 def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -101,15 +101,16 @@ SIGNATURES = {
     "fsd_nn_destroy": (None, [_VP]),
     "fsd_nn_workspace_bytes": (C.c_size_t, [_VP]),
     "fsd_nn_bind": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
-    "fsd_nn_features": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double, C.POINTER(C.c_double), _VP, _VP,
-                                  _VP]),
+    "fsd_nn_features": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double, C.POINTER(C.c_double),
+                                  _VP, _VP, _VP]),
     "fsd_nn_crop": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int, C.c_int,
                               C.c_int, C.c_int, C.c_int, _VP, _VP]),
     "fsd_nn_forward": (C.c_int, [_VP, _VP, _VP, _VP]),
     "fsd_nn_loss_grad": (C.c_int, [_VP, _VP, _VP, _VP, C.c_int, _VP, _VP]),
     "fsd_nn_adam": (C.c_int, [C.c_long, _VP, _VP, _VP, _VP, C.c_int, C.c_double, C.c_double,
                               C.c_double, C.c_double, _VP]),
-    "fsd_nn_predict": (C.c_int, [_VP, _VP, _VP, _VP, C.c_double, C.POINTER(C.c_double), _VP]),
+    "fsd_nn_predict": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double,
+                                 C.POINTER(C.c_double), _VP]),
 }
 
 

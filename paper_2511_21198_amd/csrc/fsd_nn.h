@@ -49,6 +49,8 @@ struct NnConvArgs {
     int cout_p;
     float* out32;        // channel 0 as float32 [voxel] (may be null)
     int relu;
+    const bf16_t* up;    // optional: input is in[v] + up[v / 2] (pitch cin_p)
+    NnDims upd;          // dimensions of `up`
 };
 
 // A operands of a layer.  transposed = 0: rows o < cout, K = (tap, i < cin)
@@ -86,15 +88,19 @@ struct NnWgradArgs {
 long nn_wgrad_partials(const NnDims& d, int cin_p, int cout, int vchunk);
 hipError_t nn_wgrad(const NnWgradArgs& a, hipStream_t s);
 
-// Features on the full grid (dense float64, x fastest), with the scale
-// s = rms(u) + rms(dt F) + 1e-30 reduced on the device into *s_out.
-hipError_t nn_scale(const double* u, const double* F, double dt, long N, double* partials,
-                    double* s_out, hipStream_t st);
-hipError_t nn_feat_bf16(const double* u, const double* F, double dt, const double* s, float l0,
-                        float l1, float l2, long N, bf16_t* x, hipStream_t st);
-hipError_t nn_feat_f32(const double* u, const double* F, const double* unext, double dt,
-                       const double* s, float l0, float l1, float l2, long N, float* x, float* t,
-                       hipStream_t st);
+// Features on the full grid (dense float64, x fastest): du = u - uprev,
+// df = dt (F - Fprev), channels [du, df, l0, l1, l2] / s (the last three
+// constant) with s = rms(du) + rms(df) + 1e-30 reduced on the device into
+// *s_out.  Null uprev: du = 0; null F or Fprev: zero source.
+hipError_t nn_scale(const double* u, const double* uprev, const double* F, const double* Fprev,
+                    double dt, long N, double* partials, double* s_out, hipStream_t st);
+hipError_t nn_feat_bf16(const double* u, const double* uprev, const double* F, const double* Fprev,
+                        double dt, const double* s, float l0, float l1, float l2, long N, bf16_t* x,
+                        hipStream_t st);
+// float32 channels-first; t = (unext - 2 u + uprev) / s when unext is given.
+hipError_t nn_feat_f32(const double* u, const double* uprev, const double* F, const double* Fprev,
+                       const double* unext, double dt, const double* s, float l0, float l1,
+                       float l2, long N, float* x, float* t, hipStream_t st);
 // float32 [B][5][D][H][W] -> bf16 [B][D][H][W][8]
 hipError_t nn_pack_x(const float* x, bf16_t* out, NnDims d, hipStream_t st);
 hipError_t nn_crop(const float* src, int c, int nx, int ny, int nz, int x0, int y0, int z0, int cx,
@@ -102,9 +108,9 @@ hipError_t nn_crop(const float* src, int c, int nx, int ny, int nz, int x0, int 
 // loss = mean over the interior of (y - t)^2; gy[v][0] = 2 (y - t) / count there, 0 elsewhere.
 hipError_t nn_loss(const float* y, const float* t, NnDims d, int margin, bf16_t* gy,
                    double* partials, double* loss, hipStream_t st);
-// guess = u + s * y
-hipError_t nn_head(const double* u, const float* y, const double* s, long N, double* guess,
-                   hipStream_t st);
+// guess = u + (u - uprev) + s * y  (uprev == null: guess = u + s * y)
+hipError_t nn_head(const double* u, const double* uprev, const float* y, const double* s, long N,
+                   double* guess, hipStream_t st);
 hipError_t nn_adam(long n, float* p, const float* g, float* m, float* v, float lr, float b1,
                    float b2, float eps, float c1, float c2, hipStream_t st);
 

@@ -82,66 +82,157 @@ __global__ void k_nn_frag(const float* __restrict__ W, int cin, int cout, int tr
 
 // ---------------------------------------------------------------- conv
 
-// One wavefront computes 16 consecutive x positions of one (b, z, y) row for
-// all output channels (MB blocks of 16).  Per K-step each lane loads the 4
-// channels (one 8-byte word) of one tap of its voxel and its A fragments.
-template <int MB>
+// Workgroup tile: 16 x positions x 4 y rows x R z planes of output voxels,
+// all output channels (MB blocks of 16).  The input block with a one-voxel
+// halo, 18 x 6 x (R + 2) voxels of CP channels, is staged once in LDS
+// (voxel pitch CP + 4 halfwords against bank conflicts); wavefront w
+// computes the row y0 + w of the R planes.  Per K-step (16 values of
+// K = (tap, channel)) each lane reads its 4 channels of one tap from LDS
+// and the MB A fragments from global memory (shared by the R rows).
+// With a.up set, the staged input is in[v] + up[v / 2] (the decoder's
+// upsample-and-add, rounded to bf16 as the separate kernel does).
+constexpr int kConvTY = 4;
+
+// LDS offset (halfwords) of tap t = 9 dz + 3 dy + dx in the staged block.
+template <int TYH, int TX, int P>
+__device__ constexpr int tap_off(int t) {
+    return (((t / 9) * TYH + (t / 3) % 3) * TX + t % 3) * P;
+}
+
+template <int CP, int MB, int R>
 __global__ __launch_bounds__(256) void k_nn_conv(NnConvArgs a) {
-    const int lane = threadIdx.x & 63;
-    const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int nxb = (a.d.W + 15) >> 4;
-    const long nwaves = (long)a.d.B * a.d.D * a.d.H * nxb;
-    if (wave >= nwaves) return;
-    const int xb = (int)(wave % nxb);
-    long t = wave / nxb;
-    const int y = (int)(t % a.d.H);
-    t /= a.d.H;
-    const int z = (int)(t % a.d.D);
-    const int b = (int)(t / a.d.D);
-    const int n = lane & 15, g = lane >> 4;
-    const int x = xb * 16 + n;
-    nn_f4 acc[MB];
-#pragma unroll
-    for (int m = 0; m < MB; ++m) acc[m] = nn_f4{0.f, 0.f, 0.f, 0.f};
+    extern __shared__ bf16_t tile[];
+    constexpr int P = CP + 4, Q4 = CP / 4, TX = 18, TYH = kConvTY + 2, TZH = R + 2;
+    constexpr int KS = (27 * CP + 15) / 16;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int nxb = (a.d.W + 15) >> 4, nyb = (a.d.H + kConvTY - 1) / kConvTY;
+    const int nzb = (a.d.D + R - 1) / R;
+    long bid = blockIdx.x;
+    const int xb = (int)(bid % nxb);
+    bid /= nxb;
+    const int yb = (int)(bid % nyb);
+    bid /= nyb;
+    const int zb = (int)(bid % nzb);
+    const int b = (int)(bid / nzb);
+    const int x0 = xb * 16, y0 = yb * kConvTY, z0 = zb * R;
     const long plane = (long)a.d.H * a.d.W;
-    const bf16_t* inb = a.in + (long)b * a.d.D * plane * a.cin_p;
-    const int cmask = a.cin_p - 1;
-    for (int s = 0; s < a.ks; ++s) {
-        const int kb = 16 * s + 4 * g;
-        const int tap = kb >> a.cin_shift, ci = kb & cmask;
-        nn_s4 bv = {0, 0, 0, 0};
-        if (tap < 27) {
-            const int zz = z + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-            if (zz >= 0 && zz < a.d.D && yy >= 0 && yy < a.d.H && xx >= 0 && xx < a.d.W)
-                bv = *reinterpret_cast<const nn_s4*>(
-                    inb + ((long)zz * plane + (long)yy * a.d.W + xx) * a.cin_p + ci);
-        }
+    const bf16_t* inb = a.in + (long)b * a.d.D * plane * CP;
+    const long uplane = (long)a.upd.H * a.upd.W;
+    const bf16_t* upb = a.up ? a.up + (long)b * a.upd.D * uplane * CP : nullptr;
+    // stage the input block: 8-byte words, zero outside the grid.  All loads
+    // of a thread are issued before the first LDS store (the loop is
+    // unrolled), so the block costs one memory latency, not one per word.
+    constexpr int NWORDS = TX * TYH * TZH * Q4;
+    constexpr int NIT = (NWORDS + 255) / 256;
+    uint2 val[NIT], upv[NIT];
 #pragma unroll
-        for (int m = 0; m < MB; ++m) {
-            const nn_s4 av = a.frag[((long)s * MB + m) * 64 + lane];
-            acc[m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[m], 0, 0, 0);
+    for (int it = 0; it < NIT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        const int q = i % Q4;
+        const int vx = (i / Q4) % TX;
+        const int vy = (i / (Q4 * TX)) % TYH;
+        const int vz = i / (Q4 * TX * TYH);
+        const int zz = z0 + vz - 1, yy = y0 + vy - 1, xx = x0 + vx - 1;
+        val[it] = make_uint2(0u, 0u);
+        upv[it] = make_uint2(0u, 0u);
+        if (i < NWORDS && zz >= 0 && zz < a.d.D && yy >= 0 && yy < a.d.H && xx >= 0 &&
+            xx < a.d.W) {
+            val[it] = *reinterpret_cast<const uint2*>(
+                inb + ((long)zz * plane + (long)yy * a.d.W + xx) * CP + 4 * q);
+            if (upb)
+                upv[it] = *reinterpret_cast<const uint2*>(
+                    upb + ((long)(zz >> 1) * uplane + (long)(yy >> 1) * a.upd.W + (xx >> 1)) * CP +
+                    4 * q);
         }
     }
-    if (x >= a.d.W) return;
-    const long vox = (((long)b * a.d.D + z) * a.d.H + y) * a.d.W + x;
 #pragma unroll
-    for (int m = 0; m < MB; ++m) {
-        const int co0 = m * 16 + 4 * g;
-        float v[4];
+    for (int it = 0; it < NIT; ++it) {
+        const int i = threadIdx.x + it * 256;
+        if (i < NWORDS) {
+            const int q = i % Q4;
+            const int vx = (i / Q4) % TX;
+            const int vy = (i / (Q4 * TX)) % TYH;
+            const int vz = i / (Q4 * TX * TYH);
+            uint2 v = val[it];
+            if (upb) {
+                const U4 k = ld4(reinterpret_cast<const bf16_t*>(&val[it]));
+                const U4 c = ld4(reinterpret_cast<const bf16_t*>(&upv[it]));
+                float f[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = co0 + r;
-            float w = acc[m][r];
-            if (co < a.cout) {
-                if (a.bias) w += a.bias[co];
-                if (a.relu) w = fmaxf(w, 0.f);
-            } else {
-                w = 0.f;
+                for (int e = 0; e < 4; ++e) f[e] = bf2f(c.v[e]) + bf2f(k.v[e]);
+                st4(reinterpret_cast<bf16_t*>(&v), f);
             }
-            v[r] = w;
+            *reinterpret_cast<uint2*>(tile + ((vz * TYH + vy) * TX + vx) * P + 4 * q) = v;
         }
-        if (a.out && co0 < a.cout_p) st4(a.out + vox * a.cout_p + co0, v);
-        if (a.out32 && co0 == 0) a.out32[vox] = v[0];
+    }
+    __syncthreads();
+    const int n = lane & 15, g = lane >> 4;
+    nn_f4 acc[R][MB];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int m = 0; m < MB; ++m) acc[r][m] = nn_f4{0.f, 0.f, 0.f, 0.f};
+    // K index k = 16 s + 4 g + e = tap * CP + channel.  The loop over the KS
+    // K-steps is fully unrolled, so the tap of each step (and its LDS
+    // offset) is a constant: for CP >= 16 one tap per step and the lane
+    // group only picks the channels; for CP = 8 (4) a step spans 2 (4)
+    // taps, selected by the lane group.
+    const nn_s4* fr = a.frag + lane;
+    const bf16_t* tw = tile + (w * TX + n) * P + (CP >= 16 ? 4 * g : CP == 8 ? 4 * (g & 1) : 0);
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+        nn_s4 av[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) av[m] = fr[(s * MB + m) * 64];
+        int off;
+        bool tv = true;
+        if constexpr (CP >= 16) {
+            off = tap_off<TYH, TX, P>((16 * s) / CP) + (16 * s) % CP;
+        } else if constexpr (CP == 8) {
+            const int t0 = 2 * s, t1 = 2 * s + 1;
+            off = (g >> 1) ? tap_off<TYH, TX, P>(t1) : tap_off<TYH, TX, P>(t0);
+            if (t1 >= 27) tv = (g >> 1) == 0;
+        } else {
+            const int t = 4 * s;
+            off = g == 0 ? tap_off<TYH, TX, P>(t) : g == 1 ? tap_off<TYH, TX, P>(t + 1)
+                : g == 2 ? tap_off<TYH, TX, P>(t + 2) : tap_off<TYH, TX, P>(t + 3);
+            if (t + 3 >= 27) tv = t + g < 27;
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            nn_s4 bv = {0, 0, 0, 0};
+            if (tv) bv = *reinterpret_cast<const nn_s4*>(tw + off + r * (TYH * TX * P));
+#pragma unroll
+            for (int m = 0; m < MB; ++m)
+                acc[r][m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[m], bv, acc[r][m], 0, 0, 0);
+        }
+    }
+    const int x = x0 + n, y = y0 + w;
+    if (x >= a.d.W || y >= a.d.H) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int z = z0 + r;
+        if (z >= a.d.D) break;
+        const long vox = (((long)b * a.d.D + z) * a.d.H + y) * a.d.W + x;
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            const int co0 = m * 16 + 4 * g;
+            float v[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int co = co0 + e;
+                float t = acc[r][m][e];
+                if (co < a.cout) {
+                    if (a.bias) t += a.bias[co];
+                    if (a.relu) t = fmaxf(t, 0.f);
+                } else {
+                    t = 0.f;
+                }
+                v[e] = t;
+            }
+            if (a.out && co0 < a.cout_p) st4(a.out + vox * a.cout_p + co0, v);
+            if (a.out32 && co0 == 0) a.out32[vox] = v[0];
+        }
     }
 }
 
@@ -330,18 +421,25 @@ __global__ void k_nn_wgrad_reduce(NnWgradArgs a, int mbn, int kn, long nchunks) 
 
 // ---------------------------------------------------------------- features
 
+// du = u - uprev and df = dt (F - Fprev) at element e (absent arrays: zero).
+__device__ inline void nn_incr(const double* u, const double* up, const double* F,
+                               const double* Fp, double dt, long e, double& du, double& df) {
+    du = up ? u[e] - up[e] : 0.0;
+    df = dt * ((F ? F[e] : 0.0) - (Fp ? Fp[e] : 0.0));
+}
+
 __global__ __launch_bounds__(256) void k_nn_sumsq(const double* __restrict__ u,
-                                                  const double* __restrict__ F, double dt, long N,
+                                                  const double* __restrict__ up,
+                                                  const double* __restrict__ F,
+                                                  const double* __restrict__ Fp, double dt, long N,
                                                   double* __restrict__ partials) {
     __shared__ double sb[4];
     double su = 0.0, sf = 0.0;
     for (long e = (long)blockIdx.x * 256 + threadIdx.x; e < N; e += (long)gridDim.x * 256) {
-        const double a = u[e];
-        su += a * a;
-        if (F) {
-            const double f = dt * F[e];
-            sf += f * f;
-        }
+        double du, df;
+        nn_incr(u, up, F, Fp, dt, e, du, df);
+        su += du * du;
+        sf += df * df;
     }
     const double S1 = nn_block_sum(su, sb);
     __syncthreads();
@@ -366,31 +464,40 @@ __global__ __launch_bounds__(256) void k_nn_scale_fin(const double* __restrict__
     if (threadIdx.x == 0) *s_out = sqrt(S1 / (double)N) + sqrt(S2 / (double)N) + 1e-30;
 }
 
-__global__ void k_nn_feat_bf16(const double* __restrict__ u, const double* __restrict__ F, double dt,
+__global__ void k_nn_feat_bf16(const double* __restrict__ u, const double* __restrict__ up,
+                               const double* __restrict__ F, const double* __restrict__ Fp, double dt,
                                const double* __restrict__ s, float l0, float l1, float l2, long N,
                                bf16_t* __restrict__ x) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= N) return;
     const double inv = 1.0 / *s;
-    const float v0[4] = {(float)(u[e] * inv), F ? (float)(dt * F[e] * inv) : 0.f, l0, l1};
+    double du, df;
+    nn_incr(u, up, F, Fp, dt, e, du, df);
+    const float v0[4] = {(float)(du * inv), (float)(df * inv), l0, l1};
     const float v1[4] = {l2, 0.f, 0.f, 0.f};
     st4(x + e * 8, v0);
     st4(x + e * 8 + 4, v1);
 }
 
-__global__ void k_nn_feat_f32(const double* __restrict__ u, const double* __restrict__ F,
+__global__ void k_nn_feat_f32(const double* __restrict__ u, const double* __restrict__ up,
+                              const double* __restrict__ F, const double* __restrict__ Fp,
                               const double* __restrict__ un, double dt, const double* __restrict__ s,
                               float l0, float l1, float l2, long N, float* __restrict__ x,
                               float* __restrict__ t) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= N) return;
     const double inv = 1.0 / *s;
-    x[e] = (float)(u[e] * inv);
-    x[N + e] = F ? (float)(dt * F[e] * inv) : 0.f;
+    double du, df;
+    nn_incr(u, up, F, Fp, dt, e, du, df);
+    x[e] = (float)(du * inv);
+    x[N + e] = (float)(df * inv);
     x[2 * N + e] = l0;
     x[3 * N + e] = l1;
     x[4 * N + e] = l2;
-    if (t && un) t[e] = (float)((un[e] - u[e]) * inv);
+    if (t && un) {
+        const double ue = u[e], pe = up ? up[e] : ue;
+        t[e] = (float)((un[e] - 2.0 * ue + pe) * inv);
+    }
 }
 
 __global__ void k_nn_pack_x(const float* __restrict__ x, bf16_t* __restrict__ out, NnDims d) {
@@ -451,11 +558,13 @@ __global__ __launch_bounds__(256) void k_nn_loss_fin(const double* __restrict__ 
     if (threadIdx.x == 0) *loss = S * inv_cnt;
 }
 
-__global__ void k_nn_head(const double* __restrict__ u, const float* __restrict__ y,
-                          const double* __restrict__ s, long N, double* __restrict__ guess) {
+__global__ void k_nn_head(const double* __restrict__ u, const double* __restrict__ up,
+                          const float* __restrict__ y, const double* __restrict__ s, long N,
+                          double* __restrict__ guess) {
     const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= N) return;
-    guess[e] = u[e] + *s * (double)y[e];
+    const double ue = u[e];
+    guess[e] = ue + (up ? ue - up[e] : 0.0) + *s * (double)y[e];
 }
 
 __global__ void k_nn_adam(long n, float* __restrict__ p, const float* __restrict__ g,
@@ -484,15 +593,29 @@ hipError_t nn_frag(const float* W, int cin, int cout, int transposed, nn_s4* fra
 }
 
 hipError_t nn_conv(const NnConvArgs& a, int mb, hipStream_t s) {
-    const long nw = (long)a.d.B * a.d.D * a.d.H * ((a.d.W + 15) / 16);
-    const dim3 g(blocks(nw, 4));
-    switch (mb) {
-        case 1: hipLaunchKernelGGL(k_nn_conv<1>, g, dim3(256), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(k_nn_conv<2>, g, dim3(256), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(k_nn_conv<4>, g, dim3(256), 0, s, a); break;
-        default: return hipErrorInvalidValue;
+    // z planes per workgroup: 4 for up to 32 input channels, 2 for 64 (LDS)
+    const int R = a.cin_p <= 32 ? 4 : 2;
+    const long nblk = (long)a.d.B * ((a.d.W + 15) / 16) * ((a.d.H + kConvTY - 1) / kConvTY) *
+                      ((a.d.D + R - 1) / R);
+    const size_t lds = (size_t)18 * (kConvTY + 2) * (R + 2) * (a.cin_p + 4) * sizeof(bf16_t);
+    const dim3 g((unsigned)nblk);
+#define NN_CONV_CASE(CP_, MB_, R_)                                                              \
+    if (a.cin_p == CP_ && mb == MB_ && R == R_) {                                               \
+        hipLaunchKernelGGL((k_nn_conv<CP_, MB_, R_>), g, dim3(256), lds, s, a);                  \
+        return hipGetLastError();                                                               \
     }
-    return hipGetLastError();
+    // the (input pitch, output blocks) pairs of the network's forward and
+    // input-gradient convolutions
+    NN_CONV_CASE(8, 1, 4)
+    NN_CONV_CASE(16, 2, 4)
+    NN_CONV_CASE(32, 4, 4)
+    NN_CONV_CASE(64, 4, 2)
+    NN_CONV_CASE(64, 2, 2)
+    NN_CONV_CASE(32, 1, 4)
+    NN_CONV_CASE(16, 1, 4)
+    NN_CONV_CASE(4, 1, 4)
+#undef NN_CONV_CASE
+    return hipErrorInvalidValue;
 }
 
 hipError_t nn_pool(const bf16_t* in, bf16_t* out, NnDims fine, NnDims coarse, int cp, hipStream_t s) {
@@ -539,27 +662,29 @@ hipError_t nn_wgrad(const NnWgradArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t nn_scale(const double* u, const double* F, double dt, long N, double* partials,
-                    double* s_out, hipStream_t st) {
+hipError_t nn_scale(const double* u, const double* uprev, const double* F, const double* Fprev,
+                    double dt, long N, double* partials, double* s_out, hipStream_t st) {
     long g = (N + 255) / 256;
     if (g > kNnGrid) g = kNnGrid;
-    hipLaunchKernelGGL(k_nn_sumsq, dim3((unsigned)g), dim3(256), 0, st, u, F, dt, N, partials);
+    hipLaunchKernelGGL(k_nn_sumsq, dim3((unsigned)g), dim3(256), 0, st, u, uprev, F, Fprev, dt, N,
+                       partials);
     hipLaunchKernelGGL(k_nn_scale_fin, dim3(1), dim3(256), 0, st, partials, (int)g, N, s_out);
     return hipGetLastError();
 }
 
-hipError_t nn_feat_bf16(const double* u, const double* F, double dt, const double* s, float l0,
-                        float l1, float l2, long N, bf16_t* x, hipStream_t st) {
-    hipLaunchKernelGGL(k_nn_feat_bf16, dim3(blocks(N)), dim3(256), 0, st, u, F, dt, s, l0, l1, l2, N,
-                       x);
+hipError_t nn_feat_bf16(const double* u, const double* uprev, const double* F, const double* Fprev,
+                        double dt, const double* s, float l0, float l1, float l2, long N, bf16_t* x,
+                        hipStream_t st) {
+    hipLaunchKernelGGL(k_nn_feat_bf16, dim3(blocks(N)), dim3(256), 0, st, u, uprev, F, Fprev, dt, s,
+                       l0, l1, l2, N, x);
     return hipGetLastError();
 }
 
-hipError_t nn_feat_f32(const double* u, const double* F, const double* unext, double dt,
-                       const double* s, float l0, float l1, float l2, long N, float* x, float* t,
-                       hipStream_t st) {
-    hipLaunchKernelGGL(k_nn_feat_f32, dim3(blocks(N)), dim3(256), 0, st, u, F, unext, dt, s, l0, l1,
-                       l2, N, x, t);
+hipError_t nn_feat_f32(const double* u, const double* uprev, const double* F, const double* Fprev,
+                       const double* unext, double dt, const double* s, float l0, float l1,
+                       float l2, long N, float* x, float* t, hipStream_t st) {
+    hipLaunchKernelGGL(k_nn_feat_f32, dim3(blocks(N)), dim3(256), 0, st, u, uprev, F, Fprev, unext,
+                       dt, s, l0, l1, l2, N, x, t);
     return hipGetLastError();
 }
 
@@ -589,9 +714,9 @@ hipError_t nn_loss(const float* y, const float* t, NnDims d, int margin, bf16_t*
     return hipGetLastError();
 }
 
-hipError_t nn_head(const double* u, const float* y, const double* s, long N, double* guess,
-                   hipStream_t st) {
-    hipLaunchKernelGGL(k_nn_head, dim3(blocks(N)), dim3(256), 0, st, u, y, s, N, guess);
+hipError_t nn_head(const double* u, const double* uprev, const float* y, const double* s, long N,
+                   double* guess, hipStream_t st) {
+    hipLaunchKernelGGL(k_nn_head, dim3(blocks(N)), dim3(256), 0, st, u, uprev, y, s, N, guess);
     return hipGetLastError();
 }
 

@@ -146,10 +146,12 @@ fsd_status build_frags(fsd_nn nn, const float* params, bool transposed) {
 }
 
 fsd_status conv(fsd_nn nn, int k, const bf16_t* in, bf16_t* out, float* out32,
-                const float* params) {
+                const float* params, const bf16_t* up = nullptr) {
     const LayerPlan& l = nn->L[k];
     NnConvArgs a{};
     a.in = in;
+    a.up = up;
+    if (up) a.upd = nn->lv[l.level + 1];
     a.cin_p = l.cin_p;
     a.cin_shift = nn_log2(l.cin_p);
     a.d = nn->lv[l.level];
@@ -211,10 +213,13 @@ fsd_status wgrad(fsd_nn nn, int k, const bf16_t* in, const bf16_t* gout, float* 
         if (s_ != FSD_OK) return s_;    \
     } while (0)
 
-// Forward pass from nn->x; leaves every activation in the workspace.
+// Forward pass from nn->x.  A training instance materialises every
+// activation (the backward pass reads them); an inference instance fuses
+// each decoder upsample-and-add into the staging of the next convolution.
 fsd_status forward(fsd_nn nn, const float* params) {
     hipStream_t s = nn->stream;
     const NnDims* v = nn->lv;
+    const bool keep = nn->training;
     NN_TRY(conv(nn, 0, nn->x, nn->e0, nullptr, params));
     NN_HIP(nn_pool(nn->e0, nn->p1, v[0], v[1], 16, s));
     NN_TRY(conv(nn, 1, nn->p1, nn->e1, nullptr, params));
@@ -222,12 +227,18 @@ fsd_status forward(fsd_nn nn, const float* params) {
     NN_TRY(conv(nn, 2, nn->p2, nn->e2, nullptr, params));
     NN_HIP(nn_pool(nn->e2, nn->p3, v[2], v[3], 64, s));
     NN_TRY(conv(nn, 3, nn->p3, nn->e3, nullptr, params));
-    NN_HIP(nn_upadd(nn->e3, nn->e2, nn->s2, v[2], v[3], 64, s));
-    NN_TRY(conv(nn, 4, nn->s2, nn->d2, nullptr, params));
-    NN_HIP(nn_upadd(nn->d2, nn->e1, nn->s1, v[1], v[2], 32, s));
-    NN_TRY(conv(nn, 5, nn->s1, nn->d1, nullptr, params));
-    NN_HIP(nn_upadd(nn->d1, nn->e0, nn->s0, v[0], v[1], 16, s));
-    NN_TRY(conv(nn, 6, nn->s0, nullptr, nn->y32, params));
+    if (keep) {
+        NN_HIP(nn_upadd(nn->e3, nn->e2, nn->s2, v[2], v[3], 64, s));
+        NN_TRY(conv(nn, 4, nn->s2, nn->d2, nullptr, params));
+        NN_HIP(nn_upadd(nn->d2, nn->e1, nn->s1, v[1], v[2], 32, s));
+        NN_TRY(conv(nn, 5, nn->s1, nn->d1, nullptr, params));
+        NN_HIP(nn_upadd(nn->d1, nn->e0, nn->s0, v[0], v[1], 16, s));
+        NN_TRY(conv(nn, 6, nn->s0, nullptr, nn->y32, params));
+    } else {
+        NN_TRY(conv(nn, 4, nn->e2, nn->d2, nullptr, params, nn->e3));
+        NN_TRY(conv(nn, 5, nn->e1, nn->d1, nullptr, params, nn->d2));
+        NN_TRY(conv(nn, 6, nn->e0, nullptr, nn->y32, params, nn->d1));
+    }
     return FSD_OK;
 }
 
@@ -337,17 +348,18 @@ fsd_status fsd_nn_bind(fsd_nn nn, void* d_ws, size_t bytes, void* stream) {
     return FSD_OK;
 }
 
-fsd_status fsd_nn_features(fsd_nn nn, const double* d_u, const double* d_F, const double* d_unext,
-                           double dt, const double eta[3], float* d_x, float* d_t, double* d_s) {
+fsd_status fsd_nn_features(fsd_nn nn, const double* d_u, const double* d_uprev, const double* d_F,
+                           const double* d_Fprev, const double* d_unext, double dt,
+                           const double eta[3], float* d_x, float* d_t, double* d_s) {
     NN_TRY(check(nn));
     if (!d_u || !d_x || !eta) return set_error(FSD_EINVAL, "null argument");
     for (int i = 0; i < 3; ++i)
         if (!(eta[i] > 0.0)) return set_error(FSD_EINVAL, "eta must be positive");
     const long N = (long)nn->nx * nn->ny * nn->nz;
-    NN_HIP(nn_scale(d_u, d_F, dt, N, nn->partials, nn->scal, nn->stream));
-    NN_HIP(nn_feat_f32(d_u, d_F, d_unext, dt, nn->scal, (float)(std::log(eta[0]) / 4),
-                       (float)(std::log(eta[1]) / 4), (float)(std::log(eta[2]) / 4), N, d_x, d_t,
-                       nn->stream));
+    NN_HIP(nn_scale(d_u, d_uprev, d_F, d_Fprev, dt, N, nn->partials, nn->scal, nn->stream));
+    NN_HIP(nn_feat_f32(d_u, d_uprev, d_F, d_Fprev, d_unext, dt, nn->scal,
+                       (float)(std::log(eta[0]) / 4), (float)(std::log(eta[1]) / 4),
+                       (float)(std::log(eta[2]) / 4), N, d_x, d_t, nn->stream));
     if (d_s) NN_HIP(hipMemcpyAsync(d_s, nn->scal, sizeof(double), hipMemcpyDeviceToDevice, nn->stream));
     return FSD_OK;
 }
@@ -400,7 +412,8 @@ fsd_status fsd_nn_adam(long count, float* d_p, const float* d_g, float* d_m, flo
     return FSD_OK;
 }
 
-fsd_status fsd_nn_predict(fsd_nn nn, const float* d_params, const double* d_u, const double* d_F,
+fsd_status fsd_nn_predict(fsd_nn nn, const float* d_params, const double* d_u,
+                          const double* d_uprev, const double* d_F, const double* d_Fprev,
                           double dt, const double eta[3], double* d_guess) {
     NN_TRY(check(nn));
     if (!d_params || !d_u || !d_guess || !eta) return set_error(FSD_EINVAL, "null argument");
@@ -410,11 +423,11 @@ fsd_status fsd_nn_predict(fsd_nn nn, const float* d_params, const double* d_u, c
     const long N = (long)nn->nx * nn->ny * nn->nz;
     hipStream_t s = nn->stream;
     NN_TRY(build_frags(nn, d_params, false));
-    NN_HIP(nn_scale(d_u, d_F, dt, N, nn->partials, nn->scal, s));
-    NN_HIP(nn_feat_bf16(d_u, d_F, dt, nn->scal, (float)(std::log(eta[0]) / 4),
+    NN_HIP(nn_scale(d_u, d_uprev, d_F, d_Fprev, dt, N, nn->partials, nn->scal, s));
+    NN_HIP(nn_feat_bf16(d_u, d_uprev, d_F, d_Fprev, dt, nn->scal, (float)(std::log(eta[0]) / 4),
                         (float)(std::log(eta[1]) / 4), (float)(std::log(eta[2]) / 4), N, nn->x, s));
     NN_TRY(forward(nn, d_params));
-    NN_HIP(nn_head(d_u, nn->y32, nn->scal, N, d_guess, s));
+    NN_HIP(nn_head(d_u, d_uprev, nn->y32, nn->scal, N, d_guess, s));
     return FSD_OK;
 }
 

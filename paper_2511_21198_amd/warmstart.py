@@ -4,7 +4,7 @@ Argument marshalling only: features, network, loss, gradients and Adam all
 run in libfsd.so.  PyTorch provides device memory and the stream.
 
     net = Net(nx, ny, nz)                       # inference instance
-    guess = net.predict(params, u, F, dt, eta)  # float64 grids
+    guess = net.predict(params, u, F, dt, eta, u_prev, F_prev)  # float64 grids
     prob = Problem(..., x0="guarded"); prob.cn_step(u, F, guess=guess)
 """
 from __future__ import annotations
@@ -69,12 +69,13 @@ class Net:
             lib.fsd_nn_destroy(h)
             self._h = None
 
-    def features(self, u, F, dt, eta, unext=None):
+    def features(self, u, F, dt, eta, unext=None, u_prev=None, F_prev=None):
         """(x float32 [5, nz, ny, nx], t float32 [nz, ny, nx] or None, s)."""
         x = torch.empty((5,) + self.dims, dtype=torch.float32, device=self.device)
         t = torch.empty(self.dims, dtype=torch.float32, device=self.device) if unext is not None else None
         s = torch.empty(1, dtype=torch.float64, device=self.device)
-        check(lib.fsd_nn_features(self._h, _p(u, torch.float64), _p(F, torch.float64),
+        check(lib.fsd_nn_features(self._h, _p(u, torch.float64), _p(u_prev, torch.float64),
+                                  _p(F, torch.float64), _p(F_prev, torch.float64),
                                   _p(unext, torch.float64), float(dt), _eta(eta),
                                   _p(x, torch.float32), _p(t, torch.float32),
                                   _p(s, torch.float64)), "fsd_nn_features")
@@ -96,10 +97,12 @@ class Net:
                                    _p(loss, torch.float64)), "fsd_nn_loss_grad")
         return loss, grad
 
-    def predict(self, params, u, F, dt, eta, out: Optional[torch.Tensor] = None):
+    def predict(self, params, u, F, dt, eta, u_prev=None, F_prev=None,
+                out: Optional[torch.Tensor] = None):
         out = out if out is not None else torch.empty_like(u)
         check(lib.fsd_nn_predict(self._h, _p(params, torch.float32), _p(u, torch.float64),
-                                 _p(F, torch.float64), float(dt), _eta(eta),
+                                 _p(u_prev, torch.float64), _p(F, torch.float64),
+                                 _p(F_prev, torch.float64), float(dt), _eta(eta),
                                  _p(out, torch.float64)), "fsd_nn_predict")
         return out
 

@@ -42,6 +42,8 @@ def relerr(a, b):
 
 
 def _params(seed, jitter=0.05):
+    # initial weights (the last layer starts at zero) plus a perturbation of
+    # every parameter, so that each layer and bias takes part
     rng = np.random.default_rng(seed + 100)
     p = workloads.nn_initial_params(seed, [(ci, co) for _, ci, co, _, _ in onn.LAYERS])
     return (p + jitter * rng.standard_normal(p.size) * np.abs(p).mean()).astype(np.float32) + \
@@ -119,22 +121,28 @@ def test_features_crop_predict(ws):
     dims = (11, 13, 17)
     rng = np.random.default_rng(7)
     u = rng.standard_normal(dims)
+    up = u - 0.02 * rng.standard_normal(dims)
     F = rng.standard_normal(dims)
+    Fp = F + 0.1 * rng.standard_normal(dims)
     un = u + 0.01 * rng.standard_normal(dims)
     dt, eta = 0.02, [3.0, 7.5, 0.4]
     net = ws.Net(dims[2], dims[1], dims[0])
-    tu, tF, tun = (torch.from_numpy(a).cuda() for a in (u, F, un))
-    x, t, s = net.features(tu, tF, dt, eta, unext=tun)
-    xo, so = onn.features(u, F, dt, eta)
-    assert np.isclose(float(s.cpu()[0]), so, rtol=1e-13)
-    assert np.allclose(x.cpu().numpy(), xo, rtol=1e-6, atol=1e-7)
-    assert np.allclose(t.cpu().numpy(), (un - u) / so, rtol=1e-6, atol=1e-7)
+    tu, tup, tF, tFp, tun = (torch.from_numpy(a).cuda() for a in (u, up, F, Fp, un))
+    for hist in (True, False):
+        x, t, s = net.features(tu, tF, dt, eta, unext=tun, u_prev=tup if hist else None,
+                               F_prev=tFp if hist else None)
+        xo, so = onn.features(u, F, dt, eta, up if hist else None, Fp if hist else None)
+        assert np.isclose(float(s.cpu()[0]), so, rtol=1e-13)
+        assert np.allclose(x.cpu().numpy(), xo, rtol=1e-6, atol=1e-6)
+        assert np.allclose(t.cpu().numpy(), onn.target(u, up if hist else None, un, so),
+                           rtol=1e-6, atol=1e-5)
     c = ws.crop(x, (2, 3, 4), (5, 6, 7)).cpu().numpy()
     assert np.array_equal(c, x.cpu().numpy()[:, 2:7, 3:9, 4:11])
     p = _params(8)
-    guess = net.predict(dev32(p), tu, tF, dt, eta).cpu().numpy()
-    _, yo = None, onn.forward(onn.unflatten(bf16_round(p)), bf16_round(xo))[0]
-    assert relerr((guess - u) / so, yo) <= 2e-2
+    xo, so = onn.features(u, F, dt, eta, up, Fp)
+    guess = net.predict(dev32(p), tu, tF, dt, eta, u_prev=tup, F_prev=tFp).cpu().numpy()
+    yo = onn.forward(onn.unflatten(bf16_round(p)), bf16_round(xo))[0]
+    assert relerr((guess - (2 * u - up)) / so, yo) <= 2e-2
 
 
 def _solver_pairs(n, steps, seed):
@@ -158,9 +166,10 @@ def test_training_reduces_loss(ws):
     eta = list(prob.eta)
     full = ws.Net(n, n, n)
     xs, ts = [], []
-    for u, F, un in pairs[1:]:
-        x, t, _ = full.features(*(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (u, F)),
-                                prob.dt, eta, unext=torch.from_numpy(un).cuda())
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    for (up, Fp, _), (u, F, un) in zip(pairs[:-1], pairs[1:]):
+        x, t, _ = full.features(dev(u), dev(F), prob.dt, eta, unext=dev(un), u_prev=dev(up),
+                                F_prev=dev(Fp))
         xs.append(x)
         ts.append(t)
     X = torch.stack(xs).contiguous()

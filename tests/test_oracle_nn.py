@@ -96,6 +96,7 @@ def test_param_count_and_layout():
     assert flat.size == nn.param_count() == 251649
     d = nn.unflatten(flat)
     assert d["e0"][0].shape == (16, 5, 3, 3, 3) and d["d0"][1].shape == (1,)
+    assert not d["d0"][0].any() and not d["d0"][1].any()
     assert np.array_equal(nn.flatten(d), flat.astype(np.float64))
 
 
@@ -127,15 +128,31 @@ def test_network_gradient_finite_difference():
         k += n
 
 
-def test_features_scale_invariance():
+def test_features_scale_and_shift_invariance():
     rng = np.random.default_rng(5)
-    u = rng.standard_normal((4, 5, 6))
-    F = rng.standard_normal((4, 5, 6))
-    x1, s1 = nn.features(u, F, 0.01, [2.0, 3.0, 4.0])
-    x2, s2 = nn.features(7.0 * u, 7.0 * F, 0.01, [2.0, 3.0, 4.0])
-    assert np.allclose(x1, x2, rtol=1e-14, atol=1e-15)
+    u, up, F, Fp = (rng.standard_normal((4, 5, 6)) for _ in range(4))
+    x1, s1 = nn.features(u, F, 0.01, [2.0, 3.0, 4.0], up, Fp)
+    x2, s2 = nn.features(7.0 * u, 7.0 * F, 0.01, [2.0, 3.0, 4.0], 7.0 * up, 7.0 * Fp)
+    assert np.allclose(x1, x2, rtol=1e-13, atol=1e-14)
     assert np.isclose(s2, 7.0 * s1, rtol=1e-14)
+    # adding the same field to both time levels changes nothing
+    c = rng.standard_normal((4, 5, 6))
+    x3, s3 = nn.features(u + c, F + c, 0.01, [2.0, 3.0, 4.0], up + c, Fp + c)
+    assert np.allclose(x1, x3, rtol=1e-12, atol=1e-12) and np.isclose(s1, s3, rtol=1e-12)
     assert np.allclose(x1[3], np.log(3.0) / 4.0)
+    assert np.allclose(x1[0] * s1, u - up)
+    assert np.allclose(x1[1] * s1, 0.01 * (F - Fp))
+
+
+def test_zero_network_is_linear_extrapolation():
+    # with the initial (zero) last layer the prediction is 2 u - u_prev
+    rng = np.random.default_rng(9)
+    u, up, F = (rng.standard_normal((5, 4, 6)) for _ in range(3))
+    p = nn.unflatten(_params(3))
+    g = nn.predict(p, u, F, 0.02, [1.5, 2.5, 3.5], up, 0.5 * F)
+    assert np.allclose(g, 2 * u - up, rtol=0, atol=1e-14)
+    t = nn.target(u, up, 2 * u - up, 1.0)
+    assert np.allclose(t, 0.0, atol=1e-14)
 
 
 def test_adam_first_step_closed_form():

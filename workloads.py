@@ -147,16 +147,17 @@ def random_grid(shape, seed: int):
 
 def nn_initial_params(seed: int, layers) -> np.ndarray:
     """He-uniform initial weights for a stack of 3x3x3 convolutions, biases
-    zero; the last layer is scaled by 0.1 so that the initial prediction is
-    close to the previous iterate.  layers: sequence of (c_in, c_out).
-    Flat float32 vector, per layer W[o, i, 3, 3, 3] (C order) then b[o]."""
+    zero; the last layer starts at zero (the initial prediction is the
+    network's residual base).  layers: sequence of (c_in, c_out).  Flat
+    float32 vector, per layer W[o, i, 3, 3, 3] (C order) then b[o]."""
     rng = np.random.default_rng(seed)
     parts = []
     for k, (ci, co) in enumerate(layers):
         lim = np.sqrt(6.0 / (ci * 27))
+        wk = rng.uniform(-lim, lim, co * ci * 27)
         if k == len(layers) - 1:
-            lim *= 0.1
-        parts.append(rng.uniform(-lim, lim, co * ci * 27))
+            wk[:] = 0.0
+        parts.append(wk)
         parts.append(np.zeros(co))
     return np.concatenate(parts).astype(np.float32)
 
