@@ -230,6 +230,55 @@ def learned_workload(a, seed=10001, n=255, M=200):
     return out
 
 
+def batched_workload(a, streams=8, steps=8):
+    """64 independent instances (32 2D with n per axis in {127, 255, 511,
+    1023}, 32 3D with n in {63, 95, 127}; orders U(0.1, 0.9), k+- U(0.5, 2),
+    k+ = k- (PCG) for even instances, PGMRES otherwise; 8 bumps; u0 = 0;
+    mixed precision, tol 1e-8), `steps` CN steps each, through the batched
+    executor: one lane (problems one after the other on one stream) against
+    the autotuned lane count."""
+    import torch
+    import workloads
+    from paper_2511_21198_amd.batch import Batch
+    ws = workloads.config_batched()
+    probs = [dict(dim=w.dim, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
+                  solver=w.solver, precision="mixed", inner_tol=1e-4, tol=w.tol, x0="prev")
+             for w in ws]
+    Fs = [torch.from_numpy(w.F).cuda() for w in ws]
+    u0 = [torch.zeros_like(F) for F in Fs]
+    unknowns = sum(int(np.prod(w.n)) for w in ws)
+    b = Batch(probs, streams=streams)
+    out = {"workload": f"{len(ws)} instances (32 2D n in {{127,255,511,1023}}^2, 32 3D n in "
+                       f"{{63,95,127}}^3, half PCG / half PGMRES), {steps} CN steps each, mixed "
+                       "precision, tol 1e-8", "unknowns": unknowns, "streams": streams}
+
+    def run(label):
+        u = [x.clone() for x in u0]
+        its = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            u, st = b.cn_step(u, Fs)
+            its.append(sum(x["iters"] for x in st))
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[label] = {"lanes": b.lanes, "instance_steps_per_s": round(len(ws) * steps / t, 1),
+                      "unknown_steps_per_s": float(f"{unknowns * steps / t:.4g}"),
+                      "ms_per_batch_step": round(1e3 * t / steps, 2),
+                      "total_iters_per_step": its}
+        log(f"batched {label}: {out[label]}")
+        return u
+
+    b.set_lanes(1)
+    run("one_lane")
+    lanes, ms = b.autotune(u0, Fs)
+    out["autotune_ms_per_lanes"] = {str(k): round(v, 2) for k, v in ms.items()}
+    run("autotuned")
+    out["speedup_vs_one_lane"] = round(out["autotuned"]["instance_steps_per_s"] /
+                                       out["one_lane"]["instance_steps_per_s"], 3)
+    return out
+
+
 def secondary_symmetric(a):
     """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
     PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
@@ -280,6 +329,10 @@ def main(argv=None):
                     help="skip the learned warm start workload (255^3, 200 steps)")
     ap.add_argument("--only-learned", action="store_true",
                     help="run only the learned warm start workload and print its JSON")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 64-instance batched workload")
+    ap.add_argument("--only-batched", action="store_true",
+                    help="run only the batched workload and print its JSON")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not "
@@ -294,6 +347,9 @@ def main(argv=None):
 
     if a.only_learned:
         print(json.dumps(learned_workload(a)), flush=True)
+        return 0
+    if a.only_batched:
+        print(json.dumps(batched_workload(a)), flush=True)
         return 0
     w = workloads.config_3d_nonsymmetric(seed=0, n=a.n, M=16)
     dev = torch.device("cuda:0")
@@ -387,6 +443,8 @@ def main(argv=None):
         out["secondary"] = secondary_symmetric(a)
     if not a.no_learned:
         out["learned"] = learned_workload(a)
+    if not a.no_batched:
+        out["batched"] = batched_workload(a)
     out["kernels"] = {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
                           "gbps": round(v["gbps"], 1), "total_ms": round(v["total_ms"], 3)}
                       for k, v in prof.items()}

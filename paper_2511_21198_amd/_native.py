@@ -72,8 +72,8 @@ class ProfileEntry(C.Structure):
     ]
 
 
-# Every symbol declared in include/fsd.h and include/fsd_nn.h, with
-# (restype, argtypes).
+# Every symbol declared in include/fsd.h, include/fsd_nn.h and
+# include/fsd_batch.h, with (restype, argtypes).
 _VP = C.c_void_p
 SIGNATURES = {
     "fsd_default_params": (C.c_int, [C.POINTER(Params)]),
@@ -111,6 +111,19 @@ SIGNATURES = {
                               C.c_double, C.c_double, _VP]),
     "fsd_nn_predict": (C.c_int, [_VP, _VP, _VP, _VP, _VP, _VP, C.c_double,
                                  C.POINTER(C.c_double), _VP]),
+    # fsd_batch.h
+    "fsd_batch_create": (C.c_int, [C.POINTER(Params), C.c_int, C.POINTER(_VP)]),
+    "fsd_batch_destroy": (None, [_VP]),
+    "fsd_batch_workspace_bytes": (C.c_size_t, [_VP]),
+    "fsd_batch_offset": (C.c_size_t, [_VP, C.c_int]),
+    "fsd_batch_bind": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(_VP), C.c_int]),
+    "fsd_batch_set_lanes": (C.c_int, [_VP, C.c_int]),
+    "fsd_batch_lanes": (C.c_int, [_VP]),
+    "fsd_batch_cn_step": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP),
+                                    C.POINTER(_VP), C.POINTER(Stats)]),
+    "fsd_batch_autotune": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP),
+                                     C.POINTER(C.c_double)]),
+    "fsd_batch_problem": (_VP, [_VP, C.c_int]),
 }
 
 

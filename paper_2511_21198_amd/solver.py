@@ -25,6 +25,38 @@ def _ptr(t: Optional[torch.Tensor]):
     return C.c_void_p(t.data_ptr())
 
 
+def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Sequence[float],
+                kminus: Sequence[float], M: int = 1, T: float = 1.0, solver: str = "auto",
+                restart: int = 20, tol: float = 1e-9, maxit: int = 0, precision: str = "fp64",
+                inner_tol: float = 1e-5, max_outer: int = 8, x0: str = "prev", domain=None,
+                allow_delta_zero: bool = False) -> nat.Params:
+    """fsd_params from keyword arguments (defaults from fsd_default_params)."""
+    p = nat.Params()
+    check(lib.fsd_default_params(C.byref(p)), "fsd_default_params")
+    p.dim = dim
+    for i in range(dim):
+        p.n[i] = int(n[i])
+        p.delta[i] = float(delta[i])
+        p.kplus[i] = float(kplus[i])
+        p.kminus[i] = float(kminus[i])
+        if domain is not None:
+            p.a[i], p.b[i] = float(domain[i][0]), float(domain[i][1])
+    p.M = int(M)
+    p.T = float(T)
+    p.solver = {"auto": nat.SOLVER_AUTO, "pcg": nat.SOLVER_PCG, "gmres": nat.SOLVER_PGMRES,
+                "pgmres": nat.SOLVER_PGMRES}[solver]
+    p.restart = int(restart)
+    p.tol = float(tol)
+    p.maxit = int(maxit)
+    p.precision = {"fp64": nat.PREC_FP64, "mixed": nat.PREC_MIXED}[precision]
+    p.inner_tol = float(inner_tol)
+    p.max_outer = int(max_outer)
+    p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL,
+                 "extrap": nat.X0_EXTRAP, "guarded": nat.X0_GUARDED}[x0]
+    p.allow_delta_zero = int(allow_delta_zero)
+    return p
+
+
 class Problem:
     """One CN-FV problem bound to a caller-owned device workspace."""
 
@@ -34,29 +66,8 @@ class Problem:
                  precision: str = "fp64", inner_tol: float = 1e-5, max_outer: int = 8,
                  x0: str = "prev", domain=None, allow_delta_zero: bool = False,
                  device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
-        p = nat.Params()
-        check(lib.fsd_default_params(C.byref(p)), "fsd_default_params")
-        p.dim = dim
-        for i in range(dim):
-            p.n[i] = int(n[i])
-            p.delta[i] = float(delta[i])
-            p.kplus[i] = float(kplus[i])
-            p.kminus[i] = float(kminus[i])
-            if domain is not None:
-                p.a[i], p.b[i] = float(domain[i][0]), float(domain[i][1])
-        p.M = int(M)
-        p.T = float(T)
-        p.solver = {"auto": nat.SOLVER_AUTO, "pcg": nat.SOLVER_PCG, "gmres": nat.SOLVER_PGMRES,
-                    "pgmres": nat.SOLVER_PGMRES}[solver]
-        p.restart = int(restart)
-        p.tol = float(tol)
-        p.maxit = int(maxit)
-        p.precision = {"fp64": nat.PREC_FP64, "mixed": nat.PREC_MIXED}[precision]
-        p.inner_tol = float(inner_tol)
-        p.max_outer = int(max_outer)
-        p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL,
-                     "extrap": nat.X0_EXTRAP, "guarded": nat.X0_GUARDED}[x0]
-        p.allow_delta_zero = int(allow_delta_zero)
+        p = make_params(dim, n, delta, kplus, kminus, M, T, solver, restart, tol, maxit, precision,
+                        inner_tol, max_outer, x0, domain, allow_delta_zero)
         self.params = p
         self.dim = dim
         self.n = tuple(int(v) for v in n[:dim])

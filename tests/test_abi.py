@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("fsd.h", "fsd_nn.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("fsd.h", "fsd_nn.h", "fsd_batch.h")]
 
 
 def header_functions():
