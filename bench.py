@@ -108,9 +108,10 @@ def counter_traffic(kind):
     except (OSError, ValueError):
         return None
     from paper_2511_21198_amd.rocprof_summary import source_hash
-    if doc.get("source_hash") != source_hash():
+    e = doc.get("kinds", {}).get(kind, {})
+    if e.get("source_hash") != source_hash(kind):
         return None
-    return doc.get("kinds", {}).get(kind, {}).get("hbm_bytes_per_dispatch")
+    return e.get("hbm_bytes_per_dispatch")
 
 
 def matvec_bench(w, reps=100):

@@ -35,15 +35,27 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def source_hash() -> str:
-    """Hash of the device-code sources of the library (kernels and the
-    structures they read), to detect counters taken on other kernels."""
+# Device sources behind each kernel kind (the structures they read included).
+_LINE_SRC = ["fsd_internal.h", "fsd_lines.hpp", "fsd_wave.hpp", "fsd_lines_f32.hip",
+             "fsd_lines_f64.hip"]
+_SOURCES = {"toep": _LINE_SRC, "dst": _LINE_SRC, "dsts": _LINE_SRC,
+            "gm": ["fsd_internal.h", "fsd_gmres.h", "fsd_gmres.hip"],
+            "pcg": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
+            "cast": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"]}
+
+
+def source_hash(kind: str | None = None) -> str:
+    """Hash of the device sources of a kernel kind (all device sources when
+    kind is None), to detect counters taken on other kernels."""
+    if kind is None:
+        names = sorted({n for v in _SOURCES.values() for n in v})
+    else:
+        names = _SOURCES[kind.split("_")[0]]
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
-        if p.endswith((".hip", ".hpp")) or os.path.basename(p) == "fsd_internal.h":
-            h.update(os.path.basename(p).encode())
-            with open(p, "rb") as f:
-                h.update(f.read())
+    for n in names:
+        h.update(n.encode())
+        with open(os.path.join(HERE, "csrc", n), "rb") as f:
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
@@ -140,6 +152,7 @@ def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.
             if k in res:
                 res[k][f"{label}_bytes_per_dispatch"] = f * sum(v) / len(v)
     for k, e in res.items():
+        e["source_hash"] = source_hash(k)
         if "fetch_bytes_per_dispatch" in e and "write_bytes_per_dispatch" in e:
             e["hbm_bytes_per_dispatch"] = e["fetch_bytes_per_dispatch"] + e["write_bytes_per_dispatch"]
             e["hbm_gbps"] = e["hbm_bytes_per_dispatch"] / (e["avg_us"] * 1e-6) / 1e9
