@@ -7,11 +7,15 @@ namespace fsd {
 
 constexpr int kGmGrid = 1024;
 
+// k_maxpy modes
+enum MaxpyMode : int { MX_NORM = 0, MX_DOTS = 1, MX_REORTH = 2 };
+
 enum GmOp : int {
     GM_PBB = 0,    // bb = ||P^{-1} b||^2, thresh = tol^2 bb
     GM_BETA = 1,   // beta = ||r0||, g = beta e1, scale = 1/beta (done if small)
-    GM_H1 = 2,     // H[0..j, j] = first Gram-Schmidt coefficients
-    GM_H2 = 3,     // second pass coefficients added to H[0..j, j] and kept in h2
+    GM_H1 = 2,     // H[0..j, j] = first Gram-Schmidt coefficients; ||w||^2
+    GM_H2 = 3,     // reorthogonalisation test; if taken, second pass coefficients
+                   // added to H[0..j, j] and kept in h2
     GM_STEP = 4,   // H[j+1, j] = ||w||, Givens rotations, residual test
     GM_SOLVE = 5,  // y = R^{-1} g for the k columns of the cycle
 };
@@ -27,7 +31,7 @@ hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* part
                    const Ctrl* ctrl, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, const Ctrl* ctrl,
-                    int hoff, int want_dots, double* partials, int* nparts, hipStream_t s);
+                    int hoff, int mode, double* partials, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ctrl, int yoff,
                      hipStream_t s);

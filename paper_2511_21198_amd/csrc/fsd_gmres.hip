@@ -89,6 +89,30 @@ __device__ inline void vfma(V& o, T h, const V& v) {   // o += h v
     if constexpr (sizeof(V) / sizeof(T) == 4) { o.z += h * v.z; o.w += h * v.w; }
 }
 
+// Like block_multi_sum for nv + 1 values: acc[0..nv-1] to rows 0..nv-1 and
+// the extra accumulator acc[NVMAX] to row nv.
+template <int NVMAX>
+__device__ inline void block_multi_sum_ext(const double (&acc)[NVMAX + 1], int nv, double* red,
+                                           double* __restrict__ partials) {
+    constexpr int NR = NVMAX + 1;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+        if (i < nv || i == NVMAX) {
+            const double v = wave_sum(acc[i]);
+            if (lane == 0) red[w * NR + i] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x <= nv) {
+        const int src = threadIdx.x < nv ? threadIdx.x : NVMAX;
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < GT / 64; ++k) s += red[k * NR + src];
+        partials[(long)threadIdx.x * gridDim.x + blockIdx.x] = s;
+    }
+}
+
 // The vector kernels are instantiated for every basis size NV up to
 // kExactNV (EXACT = true: the loops over the basis are fully unrolled with no
 // predicates, so all NV + 1 loads of an iteration are in flight together) and
@@ -96,19 +120,20 @@ __device__ inline void vfma(V& o, T h, const V& v) {   // o += h v
 // N is a multiple of the vector width (the padded layout rounds the x extent
 // up to 32) and every vector is 256-byte aligned.
 
-// partials[i * G + blk] = sum_e V_i[e] w[e], i < nv.
+// partials[i * G + blk] = sum_e V_i[e] w[e] for i < nv, and row nv the
+// partial ||w||^2 (the reference of the reorthogonalisation test).
 template <typename T, int NV, bool EXACT>
 __global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, int nv_rt,
                                              const T* __restrict__ w, long N,
                                              double* __restrict__ partials, const Ctrl* ctrl) {
     using VT = typename Vec16<T>::type;
     constexpr int VW = Vec16<T>::W;
-    __shared__ double red[(GT / 64) * NV];
+    __shared__ double red[(GT / 64) * (NV + 1)];
     if (ctrl->done) return;
     const int nv = EXACT ? NV : nv_rt;
-    double acc[NV];
+    double acc[NV + 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     const long NW = N / VW, ldw = ld / VW;
     const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
     const VT* __restrict__ wv = reinterpret_cast<const VT*>(w);
@@ -121,29 +146,34 @@ __global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, i
 #pragma unroll
         for (int i = 0; i < NV; ++i)
             if (i < nv) acc[i] += vdot(v[i], we);
+        acc[NV] += vdot(we, we);
     }
-    block_multi_sum<NV>(acc, nv, red, partials);
+    block_multi_sum_ext<NV>(acc, nv, red, partials);
 }
 
-// out = in - sum_i h_i V_i (h from ctrl->gm + hoff); then either partial dots
-// V_i^T out (want_dots) or the partial ||out||^2.
+// out = in - sum_i h_i V_i (h from ctrl->gm + hoff), then
+//   mode MX_DOTS:   partial dots V_i^T out (rows < nv) and ||out||^2 (row nv);
+//   mode MX_NORM:   partial ||out||^2;
+//   mode MX_REORTH: as MX_NORM, but only when ctrl->gm_reorth is set (the
+//                   second Gram-Schmidt pass); otherwise nothing.
 template <typename T, int NV, bool EXACT>
 __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, int nv_rt,
                                               const T* in, T* out, long N, const Ctrl* ctrl,
-                                              int hoff, int want_dots, double* __restrict__ partials) {
+                                              int hoff, int mode, double* __restrict__ partials) {
     using VT = typename Vec16<T>::type;
     constexpr int VW = Vec16<T>::W;
     __shared__ double sb[GT / 64];
-    __shared__ double red[(GT / 64) * NV];
+    __shared__ double red[(GT / 64) * (NV + 1)];
     if (ctrl->done) return;
+    if (mode == MX_REORTH && !ctrl->gm_reorth) return;
+    const bool dots = mode == MX_DOTS;
     const int nv = EXACT ? NV : nv_rt;
     T h[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) h[i] = i < nv ? (T)ctrl->gm[hoff + i] : T(0);
-    double acc[NV];
+    double acc[NV + 1];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) acc[i] = 0.0;
-    double nrm = 0.0;
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     const long NW = N / VW, ldw = ld / VW;
     const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
     const VT* inv = reinterpret_cast<const VT*>(in);
@@ -158,18 +188,17 @@ __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, 
         for (int i = 0; i < NV; ++i)
             if (i < nv) vfms<T>(o, h[i], v[i]);
         outv[e] = o;
-        if (want_dots) {
+        if (dots) {
 #pragma unroll
             for (int i = 0; i < NV; ++i)
                 if (i < nv) acc[i] += vdot(v[i], o);
-        } else {
-            nrm += vdot(o, o);
         }
+        acc[NV] += vdot(o, o);
     }
-    if (want_dots) {
-        block_multi_sum<NV>(acc, nv, red, partials);
+    if (dots) {
+        block_multi_sum_ext<NV>(acc, nv, red, partials);
     } else {
-        const double s = block_sum(nrm, sb);
+        const double s = block_sum(acc[NV], sb);
         if (threadIdx.x == 0) partials[blockIdx.x] = s;
     }
 }
@@ -230,7 +259,7 @@ __device__ inline bool gm_isfinite(double v) { return __builtin_isfinite(v); }
 constexpr int ST = 1024;
 __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
                                                   int nparts, int nv, int j, int op) {
-    __shared__ double sums[kMaxRestart + 1];
+    __shared__ double sums[kMaxRestart + 2];
     const int m = c->gm_m;
     const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m, oY = oG + m + 1, oT = oY + m;
     double* gm = c->gm;
@@ -248,7 +277,10 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
     }
     if (c->done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int i = wv; i < nv; i += ST / 64) {
+    // GM_H1 / GM_H2 carry one more row: ||w||^2 / ||w'||^2.  GM_STEP reads
+    // a norm from the partials only after a second Gram-Schmidt pass.
+    const int rows = (op == GM_H1 || op == GM_H2) ? nv + 1 : (op == GM_STEP && !c->gm_reorth) ? 0 : nv;
+    for (int i = wv; i < rows; i += ST / 64) {
         double acc = 0.0;
         for (int t = lane; t < nparts; t += 64) acc += partials[(long)i * nparts + t];
         acc = wave_sum(acc);
@@ -256,11 +288,27 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
-    for (int i = 0; i < nv; ++i) {
-        const double S = sums[i];
-        if (op == GM_H1) gm[oH + i + (m + 1) * j] = S;
-        else if (op == GM_H2) { gm[oT + i] = S; gm[oH + i + (m + 1) * j] += S; }
-        else gm[oT + i] = S;   // GM_PBB, GM_BETA, GM_STEP: a single norm
+    if (op == GM_H1) {
+        for (int i = 0; i < nv; ++i) gm[oH + i + (m + 1) * j] = sums[i];
+        c->gm_w2 = sums[nv];
+    } else if (op == GM_H2) {
+        // Daniel-Gragg-Kaufman-Stewart test: keep w' when the first pass
+        // removed less than half of ||w||^2; otherwise take the second pass
+        // (its coefficients h2 are added to the Hessenberg column).
+        const double wp2 = sums[nv];
+        c->gm_wp2 = wp2;
+        const int re = !(wp2 > 0.5 * c->gm_w2);
+        c->gm_reorth = re;
+        c->gm_rflag[j] = re;
+        c->gm_nreorth += re;
+        for (int i = 0; i < nv; ++i) {
+            gm[oT + i] = re ? sums[i] : 0.0;
+            if (re) gm[oH + i + (m + 1) * j] += sums[i];
+        }
+    } else if (op == GM_STEP) {
+        gm[oT] = c->gm_reorth ? sums[0] : c->gm_wp2;
+    } else {
+        for (int i = 0; i < nv; ++i) gm[oT + i] = sums[i];   // GM_PBB, GM_BETA: a single norm
     }
     if (threadIdx.x != 0) return;
     if (op == GM_PBB) {
@@ -384,12 +432,12 @@ hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* part
 
 template <typename T>
 hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, const Ctrl* ctrl,
-                    int hoff, int want_dots, double* partials, int* nparts, hipStream_t s) {
+                    int hoff, int mode, double* partials, int* nparts, hipStream_t s) {
     if (!vec_ok(N, ld)) return hipErrorInvalidValue;
     const int g = ggrid(N);
     *nparts = g;
     FSD_NV_DISPATCH(k_maxpy, T, nv, dim3(g), dim3(GT), 0, s, V, ld, nv, in, out, N, ctrl, hoff,
-                    want_dots, partials);
+                    mode, partials);
     return hipGetLastError();
 }
 

@@ -35,11 +35,11 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 enum Kind : int {
     K_TOEP_X, K_TOEP_Y, K_TOEP_Z, K_DST_X, K_DST_Y, K_DSTS_Y, K_DSTS_Z,
-    K_GM_MDOT, K_GM_MAXPY, K_GM_UPDATE, K_PCG_UPDATE, K_NKINDS
+    K_GM_MDOT, K_GM_MAXPY, K_GM_REORTH, K_GM_UPDATE, K_PCG_UPDATE, K_NKINDS
 };
 const char* const kKindNames[K_NKINDS] = {"toep_x", "toep_y", "toep_z", "dst_x", "dst_y",
                                           "dsts_y", "dsts_z", "gm_mdot", "gm_maxpy",
-                                          "gm_update", "pcg_update"};
+                                          "gm_reorth", "gm_update", "pcg_update"};
 
 hipEvent_t prof_event(fsd_problem P) {
     if (P->prof_next < P->prof_pool.size()) return P->prof_pool[P->prof_next++];
@@ -477,16 +477,20 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
                     HIP_TRY(gm_mdot<T>(v.V, Np, j + 1, v.w, Np, P->partials, P->ctrl, &np, s));
                 }
                 HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H1, s));
+                // first Gram-Schmidt pass: v_{j+1} = w - V h1, with V^T v_{j+1}
+                // and ||v_{j+1}||^2 for the reorthogonalisation test
+                T* vn = v.V + (long)(j + 1) * Np;
                 {
                     ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (j + 3));
-                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, v.w, Np, P->ctrl, j * (m + 1), 1,
+                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, vn, Np, P->ctrl, j * (m + 1), MX_DOTS,
                                         P->partials, &np, s));
                 }
                 HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H2, s));
+                // second pass, in place, only when the test asks for it
                 {
-                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (j + 3));
-                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, v.V + (long)(j + 1) * Np, Np,
-                                        P->ctrl, h2off, 0, P->partials, &np, s));
+                    ProfScope ps(P, K_GM_REORTH, is_f32<T>(), vb * (j + 3));
+                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, vn, vn, Np, P->ctrl, h2off, MX_REORTH,
+                                        P->partials, &np, s));
                 }
                 HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, j, GM_STEP, s));
                 ++total_enq;
@@ -497,6 +501,11 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         }
         const Ctrl& c = *P->h_ctrl;
         prof_drop_skipped(P, rec0, c.gm_k);
+        for (size_t r = rec0; r < P->prof.size(); ++r) {   // second passes not taken
+            ProfRec& pr = P->prof[r];
+            if (pr.kind / 2 == K_GM_REORTH && pr.tag >= 0 && pr.tag < c.gm_k && !c.gm_rflag[pr.tag])
+                pr.skip = true;
+        }
         // x += V y over the columns of this cycle
         HIP_TRY(gm_scalar(P->ctrl, P->partials, 0, 0, 0, GM_SOLVE, s));
         {

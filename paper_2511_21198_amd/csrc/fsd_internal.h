@@ -8,6 +8,8 @@
 
 namespace fsd {
 
+constexpr int kMaxRestartHdr = 64;   // = kMaxRestart (declared before Ctrl)
+
 // Device-resident solver state.  Written only by the single-workgroup scalar
 // kernels (thread 0, vector stores); read by every kernel of a Krylov loop,
 // which returns at once when `done` is set so that iterations enqueued after
@@ -32,13 +34,17 @@ struct Ctrl {
     double gm_hnext;  // GMRES: norm of the new basis vector before scaling
     double gm_scale;  // GMRES: 1 / gm_hnext
     double abs2;      // absolute floor of thresh (0: purely relative test)
-    double pad_[3];
+    double gm_w2;     // GMRES: ||w||^2 before Gram-Schmidt
+    double gm_wp2;    // GMRES: ||w'||^2 after the first Gram-Schmidt pass
+    int gm_reorth;    // GMRES: the current step takes the second pass
+    int gm_nreorth;   // GMRES: second passes taken in this solve
+    int gm_rflag[kMaxRestartHdr];   // GMRES: second pass taken at column j (this cycle)
     // GMRES small dense state: H is (m+1) x m column-major, then cs, sn, g, y, h
     double gm[1];
 };
 
-constexpr int kMaxRestart = 64;
-constexpr size_t kCtrlBytes = 256 + sizeof(double) * ((kMaxRestart + 1) * kMaxRestart
+constexpr int kMaxRestart = kMaxRestartHdr;
+constexpr size_t kCtrlBytes = sizeof(Ctrl) + sizeof(double) * ((kMaxRestart + 1) * kMaxRestart
                                                         + 6 * (kMaxRestart + 1) + 64);
 
 // Epilogue of the last matvec pass.

@@ -128,6 +128,8 @@ __global__ void k_ctrl_init(Ctrl* c, double tol2, int maxit, int restart, double
         c->thresh = 0; c->tol2 = tol2; c->iters = 0; c->maxit = maxit; c->done = 0;
         c->status = 0; c->first = 1; c->gm_j = 0; c->gm_m = restart; c->gm_k = 0;
         c->gm_beta = 0; c->gm_hnext = 0; c->gm_scale = 0; c->abs2 = abs2;
+        c->gm_w2 = 0; c->gm_wp2 = 0; c->gm_reorth = 0; c->gm_nreorth = 0;
+        for (int j = 0; j < kMaxRestart; ++j) c->gm_rflag[j] = 0;
     }
 }
 
