@@ -108,6 +108,10 @@ typedef struct {
     int max_outer;         /* max defect-correction steps (default 8) */
     int x0_mode;           /* fsd_x0_mode */
     int allow_delta_zero;  /* test builds: accept delta = 0 (classical limit) */
+    int dst_mfma;          /* mixed precision: the float32 preconditioner applies
+                              DST-I as a bf16 matrix-core product on axes with
+                              n <= 256 (1) or by FFT (0, default: faster as
+                              measured at 255^3) */
 } fsd_params;
 
 /* Per-solve statistics. */
@@ -125,7 +129,7 @@ typedef struct fsd_problem_s* fsd_problem;
 
 /* Fill p with defaults: dim 3, n = 63, domain (0,1), delta 0.5, k = 1,
  * M = 1, T = 1, AUTO solver, restart 20, tol 1e-9, maxit 0, FP64,
- * inner_tol 1e-5, max_outer 8, x0 PREV. */
+ * inner_tol 1e-5, max_outer 8, x0 PREV, dst_mfma 0. */
 fsd_status fsd_default_params(fsd_params* p);
 
 /* Validate p and build the host-side plan (Section 2 coefficients s_k, q_k,
@@ -162,6 +166,12 @@ fsd_status fsd_apply_rhs(fsd_problem prob, const double* d_u, const double* d_F,
 
 /* z = P^{-1} r = S_N Lambda^{-1} S_N r  (Section 3, ``diag_tau_pre``). */
 fsd_status fsd_apply_Pinv(fsd_problem prob, const double* d_r, double* d_z);
+
+/* z = P^{-1} r as the float32 inner solve of a FSD_PREC_MIXED problem
+ * applies it: r rounded to float32, the float32 passes (DST-I by FFT, or by
+ * the bf16 matrix-core product on axes with n <= 256 when dst_mfma is set),
+ * z widened to float64.  Errors: FSD_EINVAL for a float64-only problem. */
+fsd_status fsd_apply_Pinv32(fsd_problem prob, const double* d_r, double* d_z);
 
 /* Solve A x = b with the configured solver and precision.  d_x holds the
  * initial guess on entry and the solution on exit.  st may be NULL.

@@ -45,6 +45,7 @@ class Params(C.Structure):
         ("max_outer", C.c_int),
         ("x0_mode", C.c_int),
         ("allow_delta_zero", C.c_int),
+        ("dst_mfma", C.c_int),
     ]
 
 
@@ -84,6 +85,7 @@ SIGNATURES = {
     "fsd_apply_A": (C.c_int, [_VP, _VP, _VP]),
     "fsd_apply_rhs": (C.c_int, [_VP, _VP, _VP, _VP]),
     "fsd_apply_Pinv": (C.c_int, [_VP, _VP, _VP]),
+    "fsd_apply_Pinv32": (C.c_int, [_VP, _VP, _VP]),
     "fsd_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     "fsd_cn_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)]),
     "fsd_get_coefficients": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_double),

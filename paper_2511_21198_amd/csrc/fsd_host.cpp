@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 
 #include "fsd_gmres.h"
 #include "fsd_host.h"
@@ -27,6 +28,12 @@ fsd_status fail(fsd_status s, const std::string& msg) {
         hipError_t e_ = (expr);                                                        \
         if (e_ != hipSuccess)                                                          \
             return fail(FSD_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+#define FSD_TRY(expr)                          \
+    do {                                       \
+        fsd_status s_ = (expr);                \
+        if (s_ != FSD_OK) return s_;           \
     } while (0)
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -105,6 +112,10 @@ void layout_tables(fsd_problem P, Bump& B, Tables<T>& t) {
         t.specR[i] = B.take<T>(2 * (size_t)L);
         t.a[i] = B.take<T>((size_t)n);
         t.lc[i] = B.take<T>((size_t)n);
+        if (sizeof(T) == 4 && P->gdst[i]) {
+            const size_t nt = (size_t)(n + 15) / 16;
+            t.sfrag[i] = B.take<uint64_t>(nt * nt * 64);
+        }
     }
 }
 
@@ -294,51 +305,84 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
         D.dim = P->dim;
         return D;
     };
-    // forward x
-    const double nb = 2.0 * (double)P->N * sizeof(T);
-    DstArgs<T> X1 = mk(0, geo_x(P), in, v.t[0]);
-    {
+    // MFMA products for the float32 passes of axes with n <= 256
+    auto mfma = [&](int axis) { return std::is_same<T, float>::value && P->gdst[axis]; };
+    auto mg = [&](int axis, PassGeo g, const T* u, T* o) {
+        GdstArgs G{};
+        G.g = g;
+        G.u = reinterpret_cast<const float*>(u);
+        G.o = reinterpret_cast<float*>(o);
+        G.frag = tabs<float>(P).sfrag[axis];
+        G.ctrl = ctrl;
+        G.dim = P->dim;
+        return G;
+    };
+    auto x_pass = [&](const T* u, T* o) -> fsd_status {
+        const double nb = 2.0 * (double)P->N * sizeof(T);
         ProfScope ps(P, K_DST_X, is_f32<T>(), nb);
-        HIP_TRY(launch_dst_x<T>(P->ax[0].L, X1, nullptr, P->stream));
-    }
+        if (mfma(0)) {
+            HIP_TRY(launch_gdst_row(mg(0, geo_x(P), u, o), P->stream));
+        } else {
+            HIP_TRY(launch_dst_x<T>(P->ax[0].L, mk(0, geo_x(P), u, o), nullptr, P->stream));
+        }
+        return FSD_OK;
+    };
+    auto y_pass = [&](const T* u, T* o) -> fsd_status {
+        const double nb = 2.0 * (double)P->N * sizeof(T);
+        ProfScope ps(P, K_DST_Y, is_f32<T>(), nb);
+        if (mfma(1)) {
+            HIP_TRY(launch_gdst_col(mg(1, geo_y(P), u, o), false, nullptr, P->stream));
+        } else {
+            HIP_TRY(launch_dst_s<T>(P->ax[1].L, mk(1, geo_y(P), u, o), nullptr, P->stream));
+        }
+        return FSD_OK;
+    };
+    // forward x (and y for 3D)
+    FSD_TRY(x_pass(in, v.t[0]));
     const T* cur = v.t[0];
     T* mid = v.t[1];
     if (P->dim == 3) {
-        DstArgs<T> Y1 = mk(1, geo_y(P), cur, v.t[1]);
-        ProfScope ps(P, K_DST_Y, is_f32<T>(), nb);
-        HIP_TRY(launch_dst_s<T>(P->ax[1].L, Y1, nullptr, P->stream));
+        FSD_TRY(y_pass(cur, v.t[1]));
         cur = v.t[1];
         mid = v.t[2];
     }
-    DstArgs<T> S = mk(last, last == 1 ? geo_y(P) : geo_z(P), cur, mid);
-    S.a_last = tb.a[last];
-    S.lc_last = tb.lc[last];
-    S.a1 = tb.a[0];
-    S.lc1 = tb.lc[0];
-    if (P->dim == 3) { S.a2 = tb.a[1]; S.lc2 = tb.lc[1]; }
-    S.partials = partials;
+    // last axis: S, Lambda^{-1}, S with the Parseval partials of (r, P^{-1} r)
     {
+        const PassGeo gl = last == 1 ? geo_y(P) : geo_z(P);
+        const double nb = 2.0 * (double)P->N * sizeof(T);
         ProfScope ps(P, last == 1 ? K_DSTS_Y : K_DSTS_Z, is_f32<T>(), nb);
-        HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream));
+        if (mfma(last)) {
+            GdstArgs G = mg(last, gl, cur, mid);
+            G.a_last = reinterpret_cast<const float*>(tb.a[last]);
+            G.lc_last = reinterpret_cast<const float*>(tb.lc[last]);
+            G.a1 = reinterpret_cast<const float*>(tb.a[0]);
+            G.lc1 = reinterpret_cast<const float*>(tb.lc[0]);
+            if (P->dim == 3) {
+                G.a2 = reinterpret_cast<const float*>(tb.a[1]);
+                G.lc2 = reinterpret_cast<const float*>(tb.lc[1]);
+            }
+            G.partials = partials;
+            HIP_TRY(launch_gdst_col(G, true, nparts, P->stream));
+        } else {
+            DstArgs<T> S = mk(last, gl, cur, mid);
+            S.a_last = tb.a[last];
+            S.lc_last = tb.lc[last];
+            S.a1 = tb.a[0];
+            S.lc1 = tb.lc[0];
+            if (P->dim == 3) { S.a2 = tb.a[1]; S.lc2 = tb.lc[1]; }
+            S.partials = partials;
+            HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream));
+        }
     }
     cur = mid;
     if (P->dim == 3) {
-        DstArgs<T> Y2 = mk(1, geo_y(P), cur, v.t[3]);
-        ProfScope ps(P, K_DST_Y, is_f32<T>(), nb);
-        HIP_TRY(launch_dst_s<T>(P->ax[1].L, Y2, nullptr, P->stream));
+        FSD_TRY(y_pass(cur, v.t[3]));
         cur = v.t[3];
     }
-    DstArgs<T> X2 = mk(0, geo_x(P), cur, out);
-    ProfScope ps(P, K_DST_X, is_f32<T>(), nb);
-    HIP_TRY(launch_dst_x<T>(P->ax[0].L, X2, nullptr, P->stream));
+    FSD_TRY(x_pass(cur, out));
     return FSD_OK;
 }
 
-#define FSD_TRY(expr)                          \
-    do {                                       \
-        fsd_status s_ = (expr);                \
-        if (s_ != FSD_OK) return s_;           \
-    } while (0)
 
 fsd_status read_ctrl(fsd_problem P) {
     HIP_TRY(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
@@ -670,6 +714,35 @@ fsd_status upload_vec(fsd_problem P, T* dst, const std::vector<double>& src) {
     return FSD_OK;
 }
 
+// bf16 (round to nearest even) of a float32 value.
+uint16_t host_bf16(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// MFMA fragments of the orthonormal DST-I matrix S of order n (Section 3),
+// stored K step major: fragment (s, t), lane l, element e =
+// S[16 t + l % 16][16 s + 4 (l / 16) + e] in bf16, zero outside n x n.
+fsd_status upload_sfrag(fsd_problem P, void* dst, int n) {
+    const int nt = (n + 15) / 16;
+    std::vector<uint16_t> f((size_t)nt * nt * 64 * 4, 0);
+    const long double c = std::sqrt(2.0L / (n + 1)), pi = 3.141592653589793238462643383279503L;
+    for (int t = 0; t < nt; ++t)
+        for (int s = 0; s < nt; ++s)
+            for (int l = 0; l < 64; ++l)
+                for (int e = 0; e < 4; ++e) {
+                    const int k = 16 * t + l % 16, j = 16 * s + 4 * (l / 16) + e;
+                    float v = 0.f;
+                    if (k < n && j < n) v = (float)(c * std::sin(pi * (j + 1) * (k + 1) / (n + 1)));
+                    f[(((size_t)s * nt + t) * 64 + l) * 4 + e] = host_bf16(v);
+                }
+    HIP_TRY(hipMemcpyAsync(dst, f.data(), f.size() * 2, hipMemcpyHostToDevice, P->stream));
+    HIP_TRY(hipStreamSynchronize(P->stream));
+    return FSD_OK;
+}
+
 template <typename T>
 fsd_status upload_all(fsd_problem P, Tables<T>& t) {
     for (int i = 0; i < P->dim; ++i) {
@@ -682,6 +755,7 @@ fsd_status upload_all(fsd_problem P, Tables<T>& t) {
         const double ci = ax.eta * (ax.kp + ax.km);
         for (int k = 0; k < ax.n; ++k) lc[k] = ci * ax.lam[k];
         FSD_TRY(upload_vec<T>(P, t.lc[i], lc));
+        if (t.sfrag[i]) FSD_TRY(upload_sfrag(P, t.sfrag[i], ax.n));
     }
     return FSD_OK;
 }
@@ -730,6 +804,7 @@ fsd_status fsd_default_params(fsd_params* p) {
     p->tol = 1e-9;
     p->maxit = 0;
     p->precision = FSD_PREC_FP64;
+    p->dst_mfma = 0;
     p->inner_tol = 1e-5;
     p->max_outer = 8;
     p->x0_mode = FSD_X0_PREV;
@@ -786,6 +861,8 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
     P->solver = p->solver == FSD_SOLVER_AUTO ? (P->symmetric ? FSD_SOLVER_PCG : FSD_SOLVER_PGMRES)
                                              : p->solver;
     P->mixed = p->precision == FSD_PREC_MIXED;
+    for (int i = 0; i < p->dim; ++i)
+        P->gdst[i] = P->mixed && p->dst_mfma != 0 && p->n[i] <= 256 && gdst_supported(p->n[i]);
     P->restart = p->restart;
     P->P1 = (p->n[0] + 31) / 32 * 32;
     P->rows = (long)p->n[1] * (P->dim == 3 ? p->n[2] : 1);
@@ -800,6 +877,7 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
             const int tx = 2 * lines_per_block(L, f64 != 0);
             mp = std::max<long>(mp, (long)(P->P1 / tx) * outer);
         }
+        mp = std::max<long>(mp, ((long)(P->P1 / 16) * outer + 3) / 4);   // MFMA DST passes
     }
     P->maxparts = mp;
     P->ws_bytes = layout(P, nullptr);
@@ -870,6 +948,17 @@ fsd_status fsd_apply_Pinv(fsd_problem P, const double* d_r, double* d_z) {
     HIP_TRY(vec_pack<double>(d_r, v.p, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
     FSD_TRY(op_precond<double>(P, v.p, v.q, nullptr, nullptr, nullptr));
     HIP_TRY(vec_unpack<double>(v.q, d_z, P->ax[0].n, P->P1, P->rows, P->stream));
+    return FSD_OK;
+}
+
+fsd_status fsd_apply_Pinv32(fsd_problem P, const double* d_r, double* d_z) {
+    FSD_TRY(check_bound(P));
+    if (!d_r || !d_z) return fail(FSD_EINVAL, "null vector");
+    if (!P->mixed) return fail(FSD_EINVAL, "float32 operators exist for mixed precision only");
+    Vecs<float>& v = P->v32;
+    HIP_TRY(vec_pack<float>(d_r, v.p, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    FSD_TRY(op_precond<float>(P, v.p, v.q, nullptr, nullptr, nullptr));
+    HIP_TRY(vec_unpack<float>(v.q, d_z, P->ax[0].n, P->P1, P->rows, P->stream));
     return FSD_OK;
 }
 

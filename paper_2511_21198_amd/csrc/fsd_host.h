@@ -32,6 +32,7 @@ struct Tables {
     T* specR[3] = {nullptr, nullptr, nullptr};
     T* a[3] = {nullptr, nullptr, nullptr};    // A_n eigenvalues
     T* lc[3] = {nullptr, nullptr, nullptr};   // eta_i (k+ + k-) * tau eigenvalues
+    void* sfrag[3] = {nullptr, nullptr, nullptr};  // bf16 MFMA fragments of S (float32, n <= 256)
 };
 
 template <typename T>
@@ -75,6 +76,7 @@ struct fsd_problem_s {
     bool symmetric = false;
     int solver = FSD_SOLVER_PCG;
     bool mixed = false;
+    bool gdst[3] = {false, false, false};   // float32 DST-I on the matrix cores, per axis
     int restart = 20;
     int maxparts = 0;     // partial sums per reduction slot
     size_t ws_bytes = 0;

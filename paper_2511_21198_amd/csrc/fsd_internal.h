@@ -116,6 +116,24 @@ struct DstArgs {
     const Ctrl* ctrl;
 };
 
+// Float32 DST-I as a bf16 MFMA product (fsd_gdst.hip), axes with n <= 256.
+struct GdstArgs {
+    PassGeo g;
+    const float* u;
+    float* o;
+    const void* frag;     // bf16 fragments of S (see fsd_gdst.hip)
+    const float* a_last; const float* lc_last;
+    const float* a1; const float* lc1;
+    const float* a2; const float* lc2;
+    int dim;
+    double* partials;     // Parseval partials (scale pass)
+    const Ctrl* ctrl;
+};
+bool gdst_supported(int n);
+hipError_t launch_gdst_row(const GdstArgs& a, hipStream_t s);
+hipError_t launch_gdst_col(const GdstArgs& a, bool scale, int* nblocks, hipStream_t s);
+int gdst_col_blocks(const PassGeo& g);
+
 // ---------------------------------------------------------------- launchers
 // Each launcher dispatches on the transform length L = 2(n+1) of the pass.
 

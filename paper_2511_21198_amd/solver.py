@@ -29,7 +29,7 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
                 kminus: Sequence[float], M: int = 1, T: float = 1.0, solver: str = "auto",
                 restart: int = 20, tol: float = 1e-9, maxit: int = 0, precision: str = "fp64",
                 inner_tol: float = 1e-5, max_outer: int = 8, x0: str = "prev", domain=None,
-                allow_delta_zero: bool = False) -> nat.Params:
+                allow_delta_zero: bool = False, dst_mfma: bool = False) -> nat.Params:
     """fsd_params from keyword arguments (defaults from fsd_default_params)."""
     p = nat.Params()
     check(lib.fsd_default_params(C.byref(p)), "fsd_default_params")
@@ -54,6 +54,7 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
     p.x0_mode = {"prev": nat.X0_PREV, "zero": nat.X0_ZERO, "external": nat.X0_EXTERNAL,
                  "extrap": nat.X0_EXTRAP, "guarded": nat.X0_GUARDED}[x0]
     p.allow_delta_zero = int(allow_delta_zero)
+    p.dst_mfma = int(dst_mfma)
     return p
 
 
@@ -65,9 +66,10 @@ class Problem:
                  solver: str = "auto", restart: int = 20, tol: float = 1e-9, maxit: int = 0,
                  precision: str = "fp64", inner_tol: float = 1e-5, max_outer: int = 8,
                  x0: str = "prev", domain=None, allow_delta_zero: bool = False,
-                 device: Optional[torch.device] = None, stream: Optional[torch.cuda.Stream] = None):
+                 dst_mfma: bool = False, device: Optional[torch.device] = None,
+                 stream: Optional[torch.cuda.Stream] = None):
         p = make_params(dim, n, delta, kplus, kminus, M, T, solver, restart, tol, maxit, precision,
-                        inner_tol, max_outer, x0, domain, allow_delta_zero)
+                        inner_tol, max_outer, x0, domain, allow_delta_zero, dst_mfma)
         self.params = p
         self.dim = dim
         self.n = tuple(int(v) for v in n[:dim])
@@ -114,6 +116,12 @@ class Problem:
     def apply_Pinv(self, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = self._out(out)
         check(lib.fsd_apply_Pinv(self._h, _ptr(r), _ptr(out)), "fsd_apply_Pinv")
+        return out
+
+    def apply_Pinv32(self, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The float32 preconditioner of the mixed-precision inner solve."""
+        out = self._out(out)
+        check(lib.fsd_apply_Pinv32(self._h, _ptr(r), _ptr(out)), "fsd_apply_Pinv32")
         return out
 
     def solve(self, b: torch.Tensor, x: torch.Tensor, raise_on_error: bool = True):

@@ -78,6 +78,24 @@ def test_operators(fsd, case):
     assert relerr(z, op.apply_Pinv(orc, X)) <= 1e-12
 
 
+# The float32 preconditioner of the mixed-precision inner solve.  By FFT its
+# error is float32 round-off (bound 1e-5).  With dst_mfma the DST-I matrix
+# is rounded to bf16 (unit roundoff 2^-9; the rounding errors of the
+# entries are independent, so one application is off by about 2^-9/sqrt(3)
+# relative) and applied six times: bound 1e-2.
+@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[2], CASES[5], CASES[8]],
+                         ids=[_ids(c) for c in (CASES[0], CASES[1], CASES[2], CASES[5], CASES[8])])
+@pytest.mark.parametrize("mfma", [False, True])
+def test_float32_preconditioner(fsd, case, mfma):
+    dim, n, d, kp, km = case
+    prob = fsd(dim, n, d, kp, km, M=7, T=0.8, precision="mixed", dst_mfma=mfma)
+    orc = op.Problem(dim, n, d, kp, km, T=0.8, M=7)
+    X = workloads.random_grid(orc.shape, 4)
+    z = host(prob.apply_Pinv32(dev(X)))
+    err = relerr(z, op.apply_Pinv(orc, X))
+    assert err <= (1e-2 if mfma and min(n[:dim]) <= 256 else 1e-5), err
+
+
 def _run_gpu(prob, u0, Fs, steps):
     u = dev(u0)
     its = []
@@ -110,6 +128,27 @@ def test_cn_run_vs_oracle(fsd, solver, case, precision):
     u_ref, its_ref = cn.run(orc, u0, Fs, tol=1e-13, x0_mode="prev", solver=solver)
     bound = 1e-10 if precision == "fp64" else 1e-8
     assert relerr(u_gpu, u_ref) <= bound, (its_gpu, its_ref)
+
+
+@pytest.mark.parametrize("solver,case", [
+    ("pcg", (3, [31, 23, 15], [0.3, 0.5, 0.7], [1, 1, 1], [1, 1, 1])),
+    ("gmres", (3, [15, 31, 7], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3])),
+    ("gmres", (2, [383, 191], [0.45, 0.65], [1.5, 0.5], [0.5, 1.5])),
+])
+def test_cn_run_mixed_mfma_dst(fsd, solver, case):
+    """Mixed precision with the bf16 matrix-core DST in the float32
+    preconditioner: the float64 defect correction still reaches 1e-8."""
+    dim, n, d, kp, km = case
+    M = 4
+    prob = fsd(dim, n, d, kp, km, M=M, T=1.0, tol=1e-12, solver=solver, precision="mixed",
+               inner_tol=1e-5, dst_mfma=True)
+    orc = op.Problem(dim, n, d, kp, km, T=1.0, M=M)
+    rng = np.random.default_rng(17)
+    u0 = rng.standard_normal(orc.shape)
+    F = workloads.random_grid(orc.shape, 19)
+    u_gpu, _ = _run_gpu(prob, u0, lambda m: F, M)
+    u_ref, _ = cn.run(orc, u0, lambda m: F, tol=1e-13, x0_mode="prev", solver=solver)
+    assert relerr(u_gpu, u_ref) <= 1e-8
 
 
 def _golden(sel):
