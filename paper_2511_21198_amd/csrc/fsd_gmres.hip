@@ -120,8 +120,17 @@ __device__ inline void block_multi_sum_ext(const double (&acc)[NVMAX + 1], int n
 // N is a multiple of the vector width (the padded layout rounds the x extent
 // up to 32) and every vector is 256-byte aligned.
 
-// partials[i * G + blk] = sum_e V_i[e] w[e] for i < nv, and row nv the
-// partial ||w||^2 (the reference of the reorthogonalisation test).
+// Arnoldi on P^{-1} A - I.  The preconditioned operator is close to the
+// identity (Theorem 3.1), so w = P^{-1} A v_j is dominated by v_j, and
+// Gram-Schmidt on w itself cancels that component with an absolute rounding
+// error of about eps ||w||, far above ||w - V V^T w||: a second pass is then
+// always needed.  Subtracting v_j first (w - v_j is exact where w and v_j
+// agree to a factor of 2) leaves a vector the projection does not cancel,
+// and one pass usually passes the reorthogonalisation test.  The Krylov
+// space is the same; the Hessenberg column gets 1 added on its diagonal.
+//
+// partials[i * G + blk] = sum_e V_i[e] (w[e] - V_{nv-1}[e]) for i < nv, and
+// row nv the partial ||w - V_{nv-1}||^2 (the reference of the test).
 template <typename T, int NV, bool EXACT>
 __global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, int nv_rt,
                                              const T* __restrict__ w, long N,
@@ -137,8 +146,10 @@ __global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, i
     const long NW = N / VW, ldw = ld / VW;
     const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
     const VT* __restrict__ wv = reinterpret_cast<const VT*>(w);
+    const VT* __restrict__ vj = Vv + (long)(nv - 1) * ldw;
     for (long e = blockIdx.x * (long)GT + threadIdx.x; e < NW; e += (long)gridDim.x * GT) {
-        const VT we = wv[e];
+        VT we = wv[e];
+        vfms<T>(we, T(1), vj[e]);
         VT v[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
@@ -152,7 +163,9 @@ __global__ __launch_bounds__(GT) void k_mdot(const T* __restrict__ V, long ld, i
 }
 
 // out = in - sum_i h_i V_i (h from ctrl->gm + hoff), then
-//   mode MX_DOTS:   partial dots V_i^T out (rows < nv) and ||out||^2 (row nv);
+//   mode MX_DOTS:   out = in - V_{nv-1} - sum_i h_i V_i (the shifted first
+//                   Gram-Schmidt pass, see k_mdot), partial dots V_i^T out
+//                   (rows < nv) and ||out||^2 (row nv);
 //   mode MX_NORM:   partial ||out||^2;
 //   mode MX_REORTH: as MX_NORM, but only when ctrl->gm_reorth is set (the
 //                   second Gram-Schmidt pass); otherwise nothing.
@@ -178,8 +191,10 @@ __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, 
     const VT* __restrict__ Vv = reinterpret_cast<const VT*>(V);
     const VT* inv = reinterpret_cast<const VT*>(in);
     VT* outv = reinterpret_cast<VT*>(out);
+    const VT* __restrict__ vj = Vv + (long)(nv - 1) * ldw;
     for (long e = blockIdx.x * (long)GT + threadIdx.x; e < NW; e += (long)gridDim.x * GT) {
         VT o = inv[e];
+        if (dots) vfms<T>(o, T(1), vj[e]);   // exact where in and v_j agree to a factor 2
         VT v[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i)
@@ -289,7 +304,12 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (op == GM_H1) {
-        for (int i = 0; i < nv; ++i) gm[oH + i + (m + 1) * j] = sums[i];
+        // coefficients of the shifted pass (kept for it in the h2 slot) and
+        // the Hessenberg column of P^{-1} A = (P^{-1} A - I) + I
+        for (int i = 0; i < nv; ++i) {
+            gm[oT + i] = sums[i];
+            gm[oH + i + (m + 1) * j] = sums[i] + (i == j ? 1.0 : 0.0);
+        }
         c->gm_w2 = sums[nv];
     } else if (op == GM_H2) {
         // Daniel-Gragg-Kaufman-Stewart test: keep w' when the first pass

@@ -521,12 +521,13 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
                     HIP_TRY(gm_mdot<T>(v.V, Np, j + 1, v.w, Np, P->partials, P->ctrl, &np, s));
                 }
                 HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H1, s));
-                // first Gram-Schmidt pass: v_{j+1} = w - V h1, with V^T v_{j+1}
-                // and ||v_{j+1}||^2 for the reorthogonalisation test
+                // first Gram-Schmidt pass on the shifted vector:
+                // v_{j+1} = (w - v_j) - V h1, with V^T v_{j+1} and ||v_{j+1}||^2
+                // for the reorthogonalisation test
                 T* vn = v.V + (long)(j + 1) * Np;
                 {
                     ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (j + 3));
-                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, vn, Np, P->ctrl, j * (m + 1), MX_DOTS,
+                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, vn, Np, P->ctrl, h2off, MX_DOTS,
                                         P->partials, &np, s));
                 }
                 HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H2, s));
