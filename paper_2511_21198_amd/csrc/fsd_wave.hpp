@@ -444,16 +444,29 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
     }
 }
 
+// n = L/2 - 1 for every pass (L = 2(n + 1)), so the per-thread trip
+// counts are constants: all loads of a thread are issued before the first
+// LDS store (one memory latency per tile instead of one per element).
 template <typename T, int L, int GRP>
 __device__ inline void dst_load_strided_w(const T* __restrict__ u, T* line, long base, long es,
-                                          int n, int ig) {
+                                          int ig) {
     using W = WGeo<T, L>;
-    for (int i = ig; i < n; i += GRP) {
-        const T v = u[base + (long)i * es];
-        line[W::idx(i + 1)] = v;
-        line[W::idx(L - 1 - i)] = -v;
+    constexpr int NN = L / 2 - 1, NIT = (NN + GRP - 1) / GRP;
+    T v[NIT];
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int i = ig + it * GRP;
+        v[it] = i < NN ? u[base + (long)i * es] : T(0);
     }
-    if (ig == 0) { line[W::idx(0)] = 0; line[W::idx(n + 1)] = 0; }
+#pragma unroll
+    for (int it = 0; it < NIT; ++it) {
+        const int i = ig + it * GRP;
+        if (i < NN) {
+            line[W::idx(i + 1)] = v[it];
+            line[W::idx(L - 1 - i)] = -v[it];
+        }
+    }
+    if (ig == 0) { line[W::idx(0)] = 0; line[W::idx(NN + 1)] = 0; }
 }
 
 // ------------------------------------------------------ strided y/z passes
@@ -493,16 +506,38 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
     T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
-    for (int i = ig; i < n; i += GRP) rline[W::idx(i)] = a.u_fft[base + (long)i * es];
-    for (int i = n + ig; i < L; i += GRP) rline[W::idx(i)] = T(0);
+    // n = L/2 - 1 (L = 2(n + 1)): constant trip counts, loads issued first
+    constexpr int NN = L / 2 - 1, NIT = (NN + GRP - 1) / GRP, NZ = (L - NN + GRP - 1) / GRP;
+    {
+        T v[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = ig + it * GRP;
+            v[it] = i < NN ? a.u_fft[base + (long)i * es] : T(0);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = ig + it * GRP;
+            if (i < NN) rline[W::idx(i)] = v[it];
+        }
+#pragma unroll
+        for (int it = 0; it < NZ; ++it) {
+            const int i = NN + ig + it * GRP;
+            if (i < L) rline[W::idx(i)] = T(0);
+        }
+    }
     __syncthreads();
     const bool pad_line = x0 + xl >= a.g.nx;
     if (a.o2) {
-        for (int i = ig; i < n; i += GRP) {
-            const T l = i > 0 ? rline[W::idx(i - 1)] : T(0);
-            const T c = rline[W::idx(i)];
-            const T r = rline[W::idx(i + 1)];
-            a.o2[base + (long)i * es] = pad_line ? T(0) : (l + T(6) * c + r) * T(0.125);
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int i = ig + it * GRP;
+            if (i < NN) {
+                const T l = i > 0 ? rline[W::idx(i - 1)] : T(0);
+                const T c = rline[W::idx(i)];
+                const T r = rline[W::idx(i + 1)];
+                a.o2[base + (long)i * es] = pad_line ? T(0) : (l + T(6) * c + r) * T(0.125);
+            }
         }
     }
     // lane groups pull their lines
@@ -536,36 +571,54 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
         }
     }
     __syncthreads();
-    // row stores with the A_n stencil on u_sten and the epilogue
-    const int CH = (n + GRP - 1) / GRP;
+    // row stores with the A_n stencil on u_sten and the epilogue; each
+    // thread owns CH consecutive line points, and every global value it
+    // needs (stencil neighbours, epilogue operand) is loaded before the
+    // first use
+    constexpr int CH = (NN + GRP - 1) / GRP;
     const int ib = ig * CH;
-    const int ie = min(n, ib + CH);
     const T sgn = (xl & 1) ? T(-1) : T(1);
     const int x = x0 + xl;
     double acc = 0.0;
     const bool has_sten = a.u_sten != nullptr;
-    T prev = 0, cur = 0;
-    if (has_sten && ib < ie) {
-        prev = ib > 0 ? a.u_sten[base + (long)(ib - 1) * es] : T(0);
-        cur = a.u_sten[base + (long)ib * es];
+    T st[CH + 2];
+    T ep[CH];
+#pragma unroll
+    for (int k = 0; k < CH + 2; ++k) {
+        const int i = ib - 1 + k;
+        st[k] = (has_sten && i >= 0 && i < NN) ? a.u_sten[base + (long)i * es] : T(0);
     }
-    for (int i = ib; i < ie; ++i) {
-        T v = sgn * rline[W::idx(i)];
-        if (has_sten) {
-            const T next = (i + 1 < n) ? a.u_sten[base + (long)(i + 1) * es] : T(0);
-            v += (prev + T(6) * cur + next) * T(0.125);
-            prev = cur;
-            cur = next;
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int i = ib + k;
+        T e = 0;
+        if (i < NN) {
+            const long gi = base + (long)i * es;
+            if (a.epi == EPI_ADD_F) {
+                if (x < a.g.n1)
+                    e = (T)(a.dt * a.F[x + (long)a.g.n1 * ((long)i * a.g.fr_i + (long)o * a.g.fr_o)]);
+            } else if (a.epi == EPI_DOT_P) {
+                e = a.dot_p[gi];
+            } else if (a.epi == EPI_RESID) {
+                e = a.b[gi];
+            }
         }
+        ep[k] = e;
+    }
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+        const int i = ib + k;
+        if (i >= NN) break;
+        T v = sgn * rline[W::idx(i)];
+        if (has_sten) v += (st[k] + T(6) * st[k + 1] + st[k + 2]) * T(0.125);
         const long gi = base + (long)i * es;
         if (pad_line) v = T(0);
         if (a.epi == EPI_ADD_F) {
-            if (x < a.g.n1)
-                v += (T)(a.dt * a.F[x + (long)a.g.n1 * ((long)i * a.g.fr_i + (long)o * a.g.fr_o)]);
+            v += ep[k];
         } else if (a.epi == EPI_DOT_P) {
-            acc += (double)a.dot_p[gi] * (double)v;
+            acc += (double)ep[k] * (double)v;
         } else if (a.epi == EPI_RESID) {
-            v = a.b[gi] - v;
+            v = ep[k] - v;
             acc += (double)v * (double)v;
         }
         a.o1[gi] = v;
@@ -617,7 +670,7 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
         s_Q[tid] = Q;
     }
     T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
-    dst_load_strided_w<T, L, GRP>(a.u, rline, base, es, n, ig);
+    dst_load_strided_w<T, L, GRP>(a.u, rline, base, es, ig);
     __syncthreads();
     T xr[LPL][8], xi[LPL][8];
 #pragma unroll
@@ -674,7 +727,9 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
     const bool odd = xl & 1;
     const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
     const bool pad_line = x0 + xl >= a.g.nx;
-    for (int i = ig; i < n; i += GRP) {
+    constexpr int NN = L / 2 - 1;
+#pragma unroll
+    for (int i = ig; i < NN; i += GRP) {
         const T z = other[W::idx(i + 1)];
         a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
     }
@@ -705,6 +760,7 @@ hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
 
 template <typename T, int L>
 hipError_t toep_s_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
+    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
     const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
     if (nb) *nb = g;
     if (!g) return hipSuccess;
@@ -734,6 +790,7 @@ hipError_t dst_x_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
 
 template <typename T, int L, bool SCALE>
 hipError_t dst_s_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
+    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
     const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
     if (nb) *nb = g;
     if (!g) return hipSuccess;
