@@ -482,6 +482,11 @@ struct WS {
     static constexpr int NW = NCL / (W::LW * W::LPL);
     static constexpr int NT = 64 * NW;
     static constexpr int GRP = NT / TX;
+    // Minimum wavefronts per SIMD the strided DST pass is compiled for:
+    // float holds 128 VGPRs without spilling; the double SCALE variant does
+    // not (it would spill ~100 bytes per lane, measured slower than running
+    // at lower occupancy), so double takes no cap.
+    static constexpr int MINW = sizeof(T) == 8 ? 1 : 4;
 };
 
 template <typename T, int L>
@@ -630,9 +635,12 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
 }
 
 // Strided DST pass; with SCALE, the last-axis pass S Lambda^{-1} S with the
-// Parseval partial sums of (r, P^{-1} r).
+// Parseval partial sums of (r, P^{-1} r).  The tile's LDS allows about four
+// wavefronts per SIMD; for float the register budget is held to that (128
+// VGPRs), or the SCALE variant at L = 512 would drop to one workgroup per CU.
 template <typename T, int L, bool SCALE>
-__global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
+__global__ __launch_bounds__((WS<T, L>::NT)) __attribute__((amdgpu_waves_per_eu(WS<T, L>::MINW)))
+void k2_dst_s(DstArgs<T> a) {
     using W = WGeo<T, L>;
     using S = WS<T, L>;
     constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
@@ -672,27 +680,25 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
     T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     dst_load_strided_w<T, L, GRP>(a.u, rline, base, es, ig);
     __syncthreads();
-    T xr[LPL][8], xi[LPL][8];
-#pragma unroll
-    for (int p = 0; p < LPL; ++p) {
-        const int slot = wave * LW * LPL + g + LW * p;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = W::idx(tl + G * q);
-            xr[p][q] = s_re[slot * LP + e];
-            xi[p][q] = s_im[slot * LP + e];
-        }
-    }
-    __syncthreads();
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
     double acc = 0.0;
+    // One line in registers at a time: a lane group's LDS region is its own,
+    // so line p + 1 stays there untouched while line p is transformed.
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int slot = wave * LW * LPL + g + LW * p;
         T* re = s_re + slot * LP;
         T* im = s_im + slot * LP;
-        wfft<T, L, false, !SCALE>(xr[p], xi[p], tl, tw, re, im);
+        T xr[1][8], xi[1][8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = W::idx(tl + G * q);
+            xr[0][q] = re[e];
+            xi[0][q] = im[e];
+        }
+        wave_sync();
+        wfft<T, L, false, !SCALE>(xr[0], xi[0], tl, tw, re, im);
         if constexpr (SCALE) {
             const T P0 = s_P[2 * slot], Q0 = s_Q[2 * slot];
             const T P1v = s_P[2 * slot + 1], Q1v = s_Q[2 * slot + 1];
@@ -705,22 +711,22 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_dst_s(DstArgs<T> a) {
                     const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
                     const T inv0 = P0 != T(0) ? fast_rcp(ak * P0 + lk * Q0) : T(0);
                     const T inv1 = P1v != T(0) ? fast_rcp(ak * P1v + lk * Q1v) : T(0);
-                    const T s1 = -xi[p][q] * a.c;
-                    const T s2 = xr[p][q] * a.c;
+                    const T s1 = -xi[0][q] * a.c;
+                    const T s2 = xr[0][q] * a.c;
                     wr = s1 * inv0;
                     wi = s2 * inv1;
                     if (f <= n) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
                 }
-                xr[p][q] = wr;
-                xi[p][q] = wi;
+                xr[0][q] = wr;
+                xi[0][q] = wi;
             }
-            wfft<T, L, false, true>(xr[p], xi[p], tl, tw, re, im);
+            wfft<T, L, false, true>(xr[0], xi[0], tl, tw, re, im);
         }
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const int e = W::idx(tl + G * q);
-            re[e] = xr[p][q];
-            im[e] = xi[p][q];
+            re[e] = xr[0][q];
+            im[e] = xi[0][q];
         }
     }
     __syncthreads();
