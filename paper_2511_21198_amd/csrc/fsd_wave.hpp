@@ -387,17 +387,22 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     }
 }
 
-// DST-I of two real lines per complex line, x axis.
+// DST-I of two real lines per complex line, x axis.  Each element of a row
+// is read from global memory once (points 0..L/2-1 of the odd extension);
+// the mirrored half V[L-j] = -V[j] comes back through the line's LDS region
+// (reading it a second time from global memory, in reversed lane order,
+// measured 1.7x slower).
 template <typename T, int L>
 __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
     using W = WGeo<T, L>;
     constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    constexpr int NN = L / 2 - 1;
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[WX<T, L>::LINES * LP];
     __shared__ T s_im[WX<T, L>::LINES * LP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, tl = lane % G;
-    const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
+    const int P1 = a.g.P1, nrows = a.g.nrows;
     T xr[LPL][8], xi[LPL][8];
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
@@ -408,18 +413,41 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
             const bool rv = row < nrows;
             const long base = (long)row * P1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                // odd extension: V[0] = V[n+1] = 0, V[j] = u[j-1], V[L-j] = -u[j-1]
+            for (int q = 0; q < 4; ++q) {
+                // odd extension: V[0] = V[n+1] = 0, V[j] = u[j-1] (j = 1..n)
                 const int e = tl + G * q;
-                T v = 0;
-                if (rv) {
-                    if (e >= 1 && e <= n) v = a.u[base + e - 1];
-                    else if (e >= n + 2) v = -a.u[base + (L - 1 - e)];
-                }
+                const T v = (rv && e >= 1) ? a.u[base + e - 1] : T(0);
                 if (h == 0) xr[p][q] = v; else xi[p][q] = v;
             }
         }
     }
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+        T* re = s_re + slot * LP;
+        T* im = s_im + slot * LP;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = W::idx(tl + G * q);
+            re[e] = xr[p][q];
+            im[e] = xi[p][q];
+        }
+        if (tl == 0) { re[W::idx(NN + 1)] = T(0); im[W::idx(NN + 1)] = T(0); }
+    }
+    wave_sync();
+#pragma unroll
+    for (int p = 0; p < LPL; ++p) {
+        const int slot = wave * LW * LPL + g + LW * p;
+        const T* re = s_re + slot * LP;
+        const T* im = s_im + slot * LP;
+#pragma unroll
+        for (int q = 4; q < 8; ++q) {
+            const int e = tl + G * q;   // V[e] = -V[L - e], L - e in 1..n+1
+            xr[p][q] = -re[W::idx(L - e)];
+            xi[p][q] = -im[W::idx(L - e)];
+        }
+    }
+    wave_sync();
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
 #pragma unroll
@@ -436,9 +464,9 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
             if (row >= nrows) break;
             const long base = (long)row * P1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 const int k = tl + G * q;   // DST index k = 1..n -> output k-1
-                if (k >= 1 && k <= n) a.o[base + k - 1] = h ? xr[p][q] * a.c : -xi[p][q] * a.c;
+                if (k >= 1) a.o[base + k - 1] = h ? xr[p][q] * a.c : -xi[p][q] * a.c;
             }
         }
     }
@@ -447,6 +475,9 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
 // n = L/2 - 1 for every pass (L = 2(n + 1)), so the per-thread trip
 // counts are constants: all loads of a thread are issued before the first
 // LDS store (one memory latency per tile instead of one per element).
+// Only points 0..L/2 of the odd extension are staged (V[0] = V[n+1] = 0,
+// V[j] = u[j-1]); the lane groups read the mirrored half V[L-j] = -V[j]
+// from there (line_regs_odd).
 template <typename T, int L, int GRP>
 __device__ inline void dst_load_strided_w(const T* __restrict__ u, T* line, long base, long es,
                                           int ig) {
@@ -461,12 +492,29 @@ __device__ inline void dst_load_strided_w(const T* __restrict__ u, T* line, long
 #pragma unroll
     for (int it = 0; it < NIT; ++it) {
         const int i = ig + it * GRP;
-        if (i < NN) {
-            line[W::idx(i + 1)] = v[it];
-            line[W::idx(L - 1 - i)] = -v[it];
-        }
+        if (i < NN) line[W::idx(i + 1)] = v[it];
     }
     if (ig == 0) { line[W::idx(0)] = 0; line[W::idx(NN + 1)] = 0; }
+}
+
+// Registers of one complex line (points tl + G q) from a line region that
+// holds points 0..L/2 of two odd extensions (re, im).
+template <typename T, int L>
+__device__ inline void line_regs_odd(T (&xr)[8], T (&xi)[8], int tl, const T* re, const T* im) {
+    using W = WGeo<T, L>;
+    constexpr int G = W::G;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = W::idx(tl + G * q);
+        xr[q] = re[e];
+        xi[q] = im[e];
+    }
+#pragma unroll
+    for (int q = 4; q < 8; ++q) {
+        const int e = W::idx(L - tl - G * q);   // L - e in 1..L/2
+        xr[q] = -re[e];
+        xi[q] = -im[e];
+    }
 }
 
 // ------------------------------------------------------ strided y/z passes
@@ -691,12 +739,7 @@ void k2_dst_s(DstArgs<T> a) {
         T* re = s_re + slot * LP;
         T* im = s_im + slot * LP;
         T xr[1][8], xi[1][8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = W::idx(tl + G * q);
-            xr[0][q] = re[e];
-            xi[0][q] = im[e];
-        }
+        line_regs_odd<T, L>(xr[0], xi[0], tl, re, im);
         wave_sync();
         wfft<T, L, false, !SCALE>(xr[0], xi[0], tl, tw, re, im);
         if constexpr (SCALE) {
@@ -722,8 +765,9 @@ void k2_dst_s(DstArgs<T> a) {
             }
             wfft<T, L, false, true>(xr[0], xi[0], tl, tw, re, im);
         }
+        // points 1..n are the ones read back (outputs q < 4; ZOUT)
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
+        for (int q = 0; q < 4; ++q) {
             const int e = W::idx(tl + G * q);
             re[e] = xr[0][q];
             im[e] = xi[0][q];
@@ -751,6 +795,7 @@ void k2_dst_s(DstArgs<T> a) {
 
 template <typename T, int L>
 hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
+    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
     if constexpr (wave_engine_length<L>()) {
         constexpr int rows = 2 * WX<T, L>::LINES;
         const int g = (a.g.nrows + rows - 1) / rows;
@@ -781,6 +826,7 @@ hipError_t toep_s_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
 
 template <typename T, int L>
 hipError_t dst_x_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
+    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
     if constexpr (wave_engine_length<L>()) {
         constexpr int rows = 2 * WX<T, L>::LINES;
         const int g = (a.g.nrows + rows - 1) / rows;
