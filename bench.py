@@ -9,15 +9,19 @@ GMRES(20) with the sine-transform preconditioner, tol 1e-8.
 A step is one fsd_cn_step: right-hand side, then the solve.  The headline
 value is the mixed-precision solver (float32 inner GMRES, float64 defect
 correction); the same steps are run with the float64 solver for the
-comparison and the relative difference of the two final states.
+comparison and the relative difference of the two final states.  Both start
+each step from u^{m-1}; `mixed_extrap` adds the mixed solver started from the
+linear extrapolation 2u^{m-1} - u^{m-2} (the warm start without a network),
+against the same float64 run.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
 
 Prints one JSON line (rank 0).  Inputs are generated on the host and copied
-to the GPU before timing.  The roofline entry is the dominant kernel of the
-timed mixed-precision steps, timed with hipEvents inside the library on its
-stream; `cpu_baseline` times the float64 oracle on this host for one CN step
-(the first step of the same workload).
+to the GPU before timing.  The timed steps run without per-kernel events; the
+roofline entry is the dominant kernel of the same mixed-precision steps run
+again from the same state with hipEvents recorded by the library around each
+launch on its stream; `cpu_baseline` times the float64 oracle on this host
+for one CN step (the first step of the same workload).
 """
 from __future__ import annotations
 
@@ -52,7 +56,14 @@ def cpu_model():
 
 
 def run_steps(prob, u0, F, steps, warmup, profile=False):
-    """Advance warmup + steps CN steps; time the last `steps`."""
+    """Advance warmup + steps CN steps; time the last `steps`.
+
+    The timed steps run without per-kernel events: a hipEvent pair around
+    every launch adds about 10% to the wall time at 255^3.  With `profile`,
+    the same `steps` steps are then repeated from the post-warm-up state with
+    the library's per-kernel hipEvents on its stream (identical iteration
+    counts: the solves are deterministic), which give the per-kernel averages
+    of the roofline entry."""
     import torch
     u = u0.clone()
     iters = []
@@ -62,9 +73,7 @@ def run_steps(prob, u0, F, steps, warmup, profile=False):
         iters.append(st["iters"])
         outer.append(st["outer_iters"])
     torch.cuda.synchronize()
-    if profile:
-        prob.profile(True)
-        prob.profile_read()           # discard anything before the timed region
+    u_w = u.clone() if profile else None
     t0 = time.perf_counter()
     for _ in range(steps):
         u, st = prob.cn_step(u, F)
@@ -72,9 +81,21 @@ def run_steps(prob, u0, F, steps, warmup, profile=False):
         outer.append(st["outer_iters"])
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = prob.profile_read() if profile else None
+    prof = None
     if profile:
+        prob.reset_history()
+        v = u_w
+        prob.profile(True)
+        prob.profile_read()           # discard anything before the profiled steps
+        for k in range(steps):
+            v, st = prob.cn_step(v, F)
+            if st["iters"] != iters[warmup + k]:
+                log(f"note: profiled step {k} took {st['iters']} iterations, timed step "
+                    f"{iters[warmup + k]}")
+        torch.cuda.synchronize()
+        prof = prob.profile_read()
         prob.profile(False)
+        del v
     return u, (t1 - t0), iters, outer, prof
 
 
@@ -322,6 +343,8 @@ def main(argv=None):
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
     ap.add_argument("--x0-mixed", default="prev", choices=["prev", "extrap"])
+    ap.add_argument("--no-warm", action="store_true",
+                    help="skip the mixed solver run from the extrapolated warm start")
     ap.add_argument("--no-ref", action="store_true",
                     help="skip the tight float64 reference run used for the error figures")
     ap.add_argument("--no-secondary", action="store_true",
@@ -372,6 +395,14 @@ def main(argv=None):
         umx, tmx, itmx, outmx, profmx = run_steps(pmx, u0, F, a.steps, a.warmup, profile=True)
         res["mixed"] = dict(t=tmx, iters=itmx, outer=outmx, prof=profmx)
         del pmx
+        if a.x0_mixed == "prev" and not a.no_warm:
+            # the same mixed solver started from the extrapolation 2u^{m-1} - u^{m-2}
+            log("mixed solver, extrapolated warm start ...")
+            pwx = Problem(**{**common, "x0": "extrap"}, precision="mixed", inner_tol=a.inner_tol,
+                          max_outer=8)
+            uwx, twx, itwx, outwx, _ = run_steps(pwx, u0, F, a.steps, a.warmup)
+            res["mixed_extrap"] = dict(t=twx, iters=itwx, outer=outwx)
+            del pwx
     errs = {}
     if not a.no_ref:
         log("tight float64 reference (tol 1e-12, untimed) ...")
@@ -385,6 +416,8 @@ def main(argv=None):
             errs["fp64"] = float(torch.linalg.vector_norm(u64 - uref) / nrm)
         if "mixed" in res:
             errs["mixed"] = float(torch.linalg.vector_norm(umx - uref) / nrm)
+        if "mixed_extrap" in res:
+            errs["mixed_extrap"] = float(torch.linalg.vector_norm(uwx - uref) / nrm)
     head = "mixed" if "mixed" in res else "fp64"
     T = res[head]["t"]
     value = a.steps / T
@@ -437,6 +470,13 @@ def main(argv=None):
     if rel is not None:
         out["speedup_vs_fp64"] = round(out["fp64_steps_per_s"] and value / out["fp64_steps_per_s"], 3)
         out["rel_diff_mixed_vs_fp64"] = rel
+    if "mixed_extrap" in res:
+        wx = res["mixed_extrap"]
+        out["mixed_extrap"] = {"steps_per_s": round(a.steps / wx["t"], 3), "iters_inner": wx["iters"],
+                               "outer": wx["outer"]}
+        if "fp64" in res:
+            out["mixed_extrap"]["speedup_vs_fp64_prev"] = round(
+                (a.steps / wx["t"]) / out["fp64_steps_per_s"], 3)
     if errs:
         out["rel_err_vs_tight_fp64"] = errs
     if not a.no_secondary:
