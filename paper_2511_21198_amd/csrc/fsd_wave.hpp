@@ -255,6 +255,67 @@ __device__ inline void wfft(T (&xr)[8], T (&xi)[8], int tl, const Twiddles<T, L>
     WRun<T, L, 0, 1, ZIN, ZOUT>::run(xr, xi, tl, tw, re, im);
 }
 
+// NL lines of one lane group in lock-step: every stage runs on all NL lines,
+// and each exchange writes all of them before one wavefront barrier and
+// reads them back before the next, so the LDS round trips of the lines
+// overlap (one barrier pair per stage instead of NL).
+template <typename T, int L, int R, int M, int NL>
+__device__ inline void wexchange_n(T (&xr)[NL][8], T (&xi)[NL][8], int tl, T* const (&re)[NL],
+                                   T* const (&im)[NL]) {
+    using W = WGeo<T, L>;
+    constexpr int G = W::G, S = 8 / R;
+#pragma unroll
+    for (int p = 0; p < NL; ++p) {
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+            const int b = tl + G * u;
+            const int base = (b / M) * M * R + b % M;
+#pragma unroll
+            for (int s = 0; s < R; ++s) {
+                const int e = W::idx(base + s * M);
+                re[p][e] = xr[p][u + s * S];
+                im[p][e] = xi[p][u + s * S];
+            }
+        }
+    }
+    wave_sync();
+#pragma unroll
+    for (int p = 0; p < NL; ++p) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int e = W::idx(tl + G * q);
+            xr[p][q] = re[p][e];
+            xi[p][q] = im[p][e];
+        }
+    }
+    wave_sync();
+}
+
+template <typename T, int L, int S, int M, bool ZIN, bool ZOUT, int NL>
+struct WRunN {
+    __device__ static inline void run(T (&xr)[NL][8], T (&xi)[NL][8], int tl,
+                                      const Twiddles<T, L>& tw, T* const (&re)[NL],
+                                      T* const (&im)[NL]) {
+        constexpr Plan P = make_plan(L);
+        if constexpr (S < P.nst) {
+            constexpr int R = P.r[S];
+            constexpr bool zin = ZIN && S == 0 && R == 8;
+            constexpr bool zout = ZOUT && S + 1 == P.nst && R == 8;
+#pragma unroll
+            for (int p = 0; p < NL; ++p) wstage<T, L, R, M, S, zin, zout>(xr[p], xi[p], tw);
+            if constexpr (S + 1 < P.nst) wexchange_n<T, L, R, M, NL>(xr, xi, tl, re, im);
+            WRunN<T, L, S + 1, M * R, ZIN, ZOUT, NL>::run(xr, xi, tl, tw, re, im);
+        }
+    }
+};
+
+// Forward FFTs of NL lines (line p in xr[p], xi[p], LDS region re[p], im[p]).
+template <typename T, int L, bool ZIN, bool ZOUT, int NL>
+__device__ inline void wfft_n(T (&xr)[NL][8], T (&xi)[NL][8], int tl, const Twiddles<T, L>& tw,
+                              T* const (&re)[NL], T* const (&im)[NL]) {
+    WRunN<T, L, 0, 1, ZIN, ZOUT, NL>::run(xr, xi, tl, tw, re, im);
+}
+
 // Toeplitz spectrum multiply in registers: Y = conj(C Z).
 template <typename T, int L>
 __device__ inline void wspec(T (&xr)[8], T (&xi)[8], int tl, const T* __restrict__ spec) {
@@ -287,42 +348,47 @@ struct WX {
     static constexpr int LINES = NW * W::LW * W::LPL;   // complex lines per workgroup
 };
 
-template <typename T, int L>
+// The prologue (PRO_*) is a template parameter: one lean kernel per mode.
+template <typename T, int L, int PRO>
 __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     using W = WGeo<T, L>;
     constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    constexpr int NN = L / 2 - 1;   // line length n; points q >= 4 are the zero padding
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[WX<T, L>::LINES * LP];
     __shared__ T s_im[WX<T, L>::LINES * LP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, tl = lane % G;
-    const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
+    const int P1 = a.g.P1, nrows = a.g.nrows;
     T beta = 0, scale = 1;
     bool first = true;
-    if (a.pro == PRO_PUPDATE) { first = a.ctrl->first != 0; beta = (T)a.ctrl->beta; }
-    if (a.pro == PRO_SCALE) scale = (T)a.ctrl->gm_scale;
+    if constexpr (PRO == PRO_PUPDATE) { first = a.ctrl->first != 0; beta = (T)a.ctrl->beta; }
+    if constexpr (PRO == PRO_SCALE) scale = (T)a.ctrl->gm_scale;
 
     T xr[LPL][8], xi[LPL][8];
+    T* re[LPL];
+    T* im[LPL];
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
-        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
-        T* re = s_re + (wave * LW * LPL + g + LW * p) * LP;
-        T* im = s_im + (wave * LW * LPL + g + LW * p) * LP;
+        const int slot = wave * LW * LPL + g + LW * p;
+        re[p] = s_re + slot * LP;
+        im[p] = s_im + slot * LP;
+        const int line = blockIdx.x * WX<T, L>::LINES + slot;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = 2 * line + h;
             const bool rv = row < nrows;
             const long base = (long)row * P1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 const int e = tl + G * q;
                 T v = 0;
-                if (rv && e < n) {
-                    if (a.pro == PRO_PUPDATE) {
+                if (rv && e < NN) {
+                    if constexpr (PRO == PRO_PUPDATE) {
                         const T z = a.u_fft[base + e];
                         v = first ? z : z + beta * a.pro_p[base + e];
                         a.pro_p[base + e] = v;
-                    } else if (a.pro == PRO_SCALE) {
+                    } else if constexpr (PRO == PRO_SCALE) {
                         v = scale * a.u_fft[base + e];
                         a.pro_p[base + e] = v;
                     } else {
@@ -332,25 +398,34 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
                 if (h == 0) xr[p][q] = v; else xi[p][q] = v;
             }
         }
-        if (a.o2) {
-            // A_n u along x from the natural-order copy of the line
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+        for (int q = 4; q < 8; ++q) { xr[p][q] = T(0); xi[p][q] = T(0); }
+    }
+    if (a.o2) {
+        // A_n u along x from natural-order copies of the lines (points 0..n)
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
                 const int e = W::idx(tl + G * q);
-                re[e] = xr[p][q];
-                im[e] = xi[p][q];
+                re[p][e] = xr[p][q];
+                im[p][e] = xi[p][q];
             }
-            wave_sync();
+        }
+        wave_sync();
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+            const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int row = 2 * line + h;
                 if (row >= nrows) break;
-                const T* src = h ? im : re;
+                const T* src = h ? im[p] : re[p];
                 const long base = (long)row * P1;
 #pragma unroll
-                for (int q = 0; q < 8; ++q) {
+                for (int q = 0; q < 4; ++q) {
                     const int e = tl + G * q;
-                    if (e < n) {
+                    if (e < NN) {
                         const T l = e > 0 ? src[W::idx(e - 1)] : T(0);
                         const T r = src[W::idx(e + 1)];
                         const T c = h ? xi[p][q] : xr[p][q];
@@ -358,18 +433,15 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
                     }
                 }
             }
-            wave_sync();
         }
+        wave_sync();
     }
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
+    wfft_n<T, L, true, false, LPL>(xr, xi, tl, tw, re, im);
 #pragma unroll
-    for (int p = 0; p < LPL; ++p) {
-        const int slot = wave * LW * LPL + g + LW * p;
-        wfft<T, L, true, false>(xr[p], xi[p], tl, tw, s_re + slot * LP, s_im + slot * LP);
-        wspec<T, L>(xr[p], xi[p], tl, a.spec);
-        wfft<T, L, false, true>(xr[p], xi[p], tl, tw, s_re + slot * LP, s_im + slot * LP);
-    }
+    for (int p = 0; p < LPL; ++p) wspec<T, L>(xr[p], xi[p], tl, a.spec);
+    wfft_n<T, L, false, true, LPL>(xr, xi, tl, tw, re, im);
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
@@ -379,9 +451,9 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
             if (row >= nrows) break;
             const long base = (long)row * P1;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
+            for (int q = 0; q < 4; ++q) {
                 const int e = tl + G * q;
-                if (e < n) a.o1[base + e] = h ? -xi[p][q] : xr[p][q];
+                if (e < NN) a.o1[base + e] = h ? -xi[p][q] : xr[p][q];
             }
         }
     }
@@ -450,10 +522,16 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
     wave_sync();
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
+    {
+        T* re[LPL];
+        T* im[LPL];
 #pragma unroll
-    for (int p = 0; p < LPL; ++p) {
-        const int slot = wave * LW * LPL + g + LW * p;
-        wfft<T, L, false, true>(xr[p], xi[p], tl, tw, s_re + slot * LP, s_im + slot * LP);
+        for (int p = 0; p < LPL; ++p) {
+            const int slot = wave * LW * LPL + g + LW * p;
+            re[p] = s_re + slot * LP;
+            im[p] = s_im + slot * LP;
+        }
+        wfft_n<T, L, false, true, LPL>(xr, xi, tl, tw, re, im);
     }
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
@@ -608,19 +686,28 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
     __syncthreads();
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
+    {
+        T* re[LPL];
+        T* im[LPL];
 #pragma unroll
-    for (int p = 0; p < LPL; ++p) {
-        const int slot = wave * LW * LPL + g + LW * p;
-        T* re = s_re + slot * LP;
-        T* im = s_im + slot * LP;
-        wfft<T, L, true, false>(xr[p], xi[p], tl, tw, re, im);
-        wspec<T, L>(xr[p], xi[p], tl, a.spec);
-        wfft<T, L, false, true>(xr[p], xi[p], tl, tw, re, im);
+        for (int p = 0; p < LPL; ++p) {
+            const int slot = wave * LW * LPL + g + LW * p;
+            re[p] = s_re + slot * LP;
+            im[p] = s_im + slot * LP;
+        }
+        wfft_n<T, L, true, false, LPL>(xr, xi, tl, tw, re, im);
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const int e = W::idx(tl + G * q);
-            re[e] = xr[p][q];
-            im[e] = xi[p][q];
+        for (int p = 0; p < LPL; ++p) wspec<T, L>(xr[p], xi[p], tl, a.spec);
+        wfft_n<T, L, false, true, LPL>(xr, xi, tl, tw, re, im);
+        // points 0..n-1 are the ones read back (outputs q < 4; ZOUT)
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = W::idx(tl + G * q);
+                re[p][e] = xr[p][q];
+                im[p][e] = xi[p][q];
+            }
         }
     }
     __syncthreads();
@@ -731,18 +818,42 @@ void k2_dst_s(DstArgs<T> a) {
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
     double acc = 0.0;
-    // One line in registers at a time: a lane group's LDS region is its own,
-    // so line p + 1 stays there untouched while line p is transformed.
+    if constexpr (!SCALE) {
+        // plain DST: the LPL lines of a lane group in lock-step
+        T xr[LPL][8], xi[LPL][8];
+        T* re[LPL];
+        T* im[LPL];
 #pragma unroll
-    for (int p = 0; p < LPL; ++p) {
-        const int slot = wave * LW * LPL + g + LW * p;
-        T* re = s_re + slot * LP;
-        T* im = s_im + slot * LP;
-        T xr[1][8], xi[1][8];
-        line_regs_odd<T, L>(xr[0], xi[0], tl, re, im);
+        for (int p = 0; p < LPL; ++p) {
+            const int slot = wave * LW * LPL + g + LW * p;
+            re[p] = s_re + slot * LP;
+            im[p] = s_im + slot * LP;
+            line_regs_odd<T, L>(xr[p], xi[p], tl, re[p], im[p]);
+        }
         wave_sync();
-        wfft<T, L, false, !SCALE>(xr[0], xi[0], tl, tw, re, im);
-        if constexpr (SCALE) {
+        wfft_n<T, L, false, true, LPL>(xr, xi, tl, tw, re, im);
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int e = W::idx(tl + G * q);
+                re[p][e] = xr[p][q];
+                im[p][e] = xi[p][q];
+            }
+        }
+    } else {
+        // scale pass: one line in registers at a time (register budget); a
+        // lane group's LDS region is its own, so line p + 1 stays there
+        // untouched while line p is transformed
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+            const int slot = wave * LW * LPL + g + LW * p;
+            T* re = s_re + slot * LP;
+            T* im = s_im + slot * LP;
+            T xr[8], xi[8];
+            line_regs_odd<T, L>(xr, xi, tl, re, im);
+            wave_sync();
+            wfft<T, L, false, false>(xr, xi, tl, tw, re, im);
             const T P0 = s_P[2 * slot], Q0 = s_Q[2 * slot];
             const T P1v = s_P[2 * slot + 1], Q1v = s_Q[2 * slot + 1];
 #pragma unroll
@@ -754,23 +865,23 @@ void k2_dst_s(DstArgs<T> a) {
                     const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
                     const T inv0 = P0 != T(0) ? fast_rcp(ak * P0 + lk * Q0) : T(0);
                     const T inv1 = P1v != T(0) ? fast_rcp(ak * P1v + lk * Q1v) : T(0);
-                    const T s1 = -xi[0][q] * a.c;
-                    const T s2 = xr[0][q] * a.c;
+                    const T s1 = -xi[q] * a.c;
+                    const T s2 = xr[q] * a.c;
                     wr = s1 * inv0;
                     wi = s2 * inv1;
                     if (f <= n) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
                 }
-                xr[0][q] = wr;
-                xi[0][q] = wi;
+                xr[q] = wr;
+                xi[q] = wi;
             }
-            wfft<T, L, false, true>(xr[0], xi[0], tl, tw, re, im);
-        }
-        // points 1..n are the ones read back (outputs q < 4; ZOUT)
+            wfft<T, L, false, true>(xr, xi, tl, tw, re, im);
+            // points 1..n are the ones read back (outputs q < 4; ZOUT)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = W::idx(tl + G * q);
-            re[e] = xr[0][q];
-            im[e] = xi[0][q];
+            for (int q = 0; q < 4; ++q) {
+                const int e = W::idx(tl + G * q);
+                re[e] = xr[q];
+                im[e] = xi[q];
+            }
         }
     }
     __syncthreads();
@@ -800,7 +911,18 @@ hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
         constexpr int rows = 2 * WX<T, L>::LINES;
         const int g = (a.g.nrows + rows - 1) / rows;
         if (nb) *nb = g;
-        if (g) hipLaunchKernelGGL((k2_toep_x<T, L>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
+        if (g) {
+            switch (a.pro) {
+                case PRO_PUPDATE:
+                    hipLaunchKernelGGL((k2_toep_x<T, L, PRO_PUPDATE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
+                    break;
+                case PRO_SCALE:
+                    hipLaunchKernelGGL((k2_toep_x<T, L, PRO_SCALE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
+                    break;
+                default:
+                    hipLaunchKernelGGL((k2_toep_x<T, L, PRO_NONE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
+            }
+        }
     } else {
         const int g = x_blocks<T>(L, a.g.nrows);
         if (nb) *nb = g;
