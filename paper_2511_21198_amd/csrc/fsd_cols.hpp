@@ -1,0 +1,372 @@
+// Column engine for the float32 strided (y / z) passes of length L = 512
+// (n = 255): the transforms of a tile's lines are split between threads by
+// residue, so that global loads and stores go straight between registers and
+// HBM rows, and one LDS transpose per transform is the only data exchange.
+//
+// Tile: CP = 16 complex lines (x positions x0 + 2p and x0 + 2p + 1 packed as
+// real and imaginary parts, a 128-byte row segment) at one outer index;
+// 256 threads, thread (p, r) with p = tid % 16 and r = tid / 16.
+//
+// Forward transform of a line V of length L = 512 = 16 x 32 (Cooley-Tukey,
+// j = r + 16 m, k = k1 + 32 k2):
+//   X[k1 + 32 k2] = sum_r w16^{r k2} (w512^{r k1} sum_m V[r + 16 m] w32^{m k1}).
+// Thread (p, r) holds V[r + 16 m] for its residue r (the rows r + 16 m of
+// the grid), computes the 32-point DFTs over m and the twiddles in
+// registers, and the tile is transposed through LDS so that thread (p, t)
+// holds the columns k1 = t and t + 16, whose 16-point DFTs over r give
+// X[k1 + 32 k2].  A second forward transform of a spectrum held that way
+// (j = j1 + 16 j2, inputs f = k1 + 32 k2) runs the same steps in the other
+// order and leaves Y[j1 + 16 j2] in thread (p, j1): the rows it read.
+//
+// LDS: the transpose runs in two halves of k1 through a 32 KB buffer, plus
+// the twiddle table (4 KB), so four workgroups fit on a CU.
+#pragma once
+
+#include <type_traits>
+
+#include "fsd_wave.hpp"
+
+namespace fsd {
+namespace colx {
+
+constexpr int L = 512;          // transform length
+constexpr int NN = L / 2 - 1;   // line length n
+constexpr int CR = 16;          // residues: threads per complex line
+constexpr int CP = 16;          // complex lines per tile
+constexpr int NT = CR * CP;     // threads per workgroup
+constexpr int TX = 2 * CP;      // x positions per tile
+
+// cos(2 pi q / 32) for q = 0..8
+__host__ __device__ constexpr float c32base(int q) {
+    return q == 0 ? 1.0f : q == 1 ? 0.98078528040323044913f : q == 2 ? 0.92387953251128675613f
+         : q == 3 ? 0.83146961230254523708f : q == 4 ? 0.70710678118654752440f
+         : q == 5 ? 0.55557023301960222474f : q == 6 ? 0.38268343236508977173f
+         : q == 7 ? 0.19509032201612826785f : 0.0f;
+}
+__host__ __device__ constexpr float cos32(int q) {
+    q &= 31;
+    return q <= 8 ? c32base(q) : q <= 16 ? -c32base(16 - q) : q <= 24 ? -c32base(q - 16)
+                                                                       : c32base(32 - q);
+}
+__host__ __device__ constexpr float sin32(int q) { return cos32(q - 8); }
+
+template <int B, int E, typename F>
+__device__ inline void static_for(F&& f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// x *= w32^Q, w32 = exp(-2 pi i / 32)
+template <int Q>
+__device__ inline void mul_w32(float& xr, float& xi) {
+    constexpr int q = Q & 31;
+    if constexpr (q == 0) {
+        return;
+    } else if constexpr (q == 8) {          // -i
+        const float t = xr; xr = xi; xi = -t;
+    } else if constexpr (q == 16) {
+        xr = -xr; xi = -xi;
+    } else if constexpr (q == 24) {         // +i
+        const float t = xr; xr = -xi; xi = t;
+    } else {
+        constexpr float c = cos32(q), s = sin32(q);
+        const float a = xr, b = xi;
+        xr = a * c + b * s;
+        xi = b * c - a * s;
+    }
+}
+
+// 32-point forward DFT in registers (n = 4 n1 + n2, k = k1 + 8 k2).
+// NOUT = 16: only outputs 0..15 are needed.
+template <int NOUT = 32>
+__device__ inline void dft32(float (&xr)[32], float (&xi)[32]) {
+    float tr[4][8], ti[4][8];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 8; ++n1) {
+            tr[n2][n1] = xr[4 * n1 + n2];
+            ti[n2][n1] = xi[4 * n1 + n2];
+        }
+        dft8(tr[n2], ti[n2]);
+    }
+    static_for<1, 8>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        mul_w32<k>(tr[1][k], ti[1][k]);
+        mul_w32<2 * k>(tr[2][k], ti[2][k]);
+        mul_w32<3 * k>(tr[3][k], ti[3][k]);
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+        const float a0r = tr[0][k1], a0i = ti[0][k1], a1r = tr[1][k1], a1i = ti[1][k1];
+        const float a2r = tr[2][k1], a2i = ti[2][k1], a3r = tr[3][k1], a3i = ti[3][k1];
+        const float s02r = a0r + a2r, s02i = a0i + a2i, d02r = a0r - a2r, d02i = a0i - a2i;
+        const float s13r = a1r + a3r, s13i = a1i + a3i, d13r = a1r - a3r, d13i = a1i - a3i;
+        xr[k1] = s02r + s13r;       xi[k1] = s02i + s13i;
+        xr[k1 + 8] = d02r + d13i;   xi[k1 + 8] = d02i - d13r;
+        if constexpr (NOUT == 32) {
+            xr[k1 + 16] = s02r - s13r;  xi[k1 + 16] = s02i - s13i;
+            xr[k1 + 24] = d02r - d13i;  xi[k1 + 24] = d02i + d13r;
+        }
+    }
+}
+
+// 16-point forward DFT (n = 4 n1 + n2, k = k1 + 4 k2), in place; NOUT = 8:
+// only outputs 0..7 are needed.
+template <int NOUT = 16>
+__device__ inline void dft16(float (&xr)[16], float (&xi)[16]) {
+    float ar[4][4], ai[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) {
+            ar[n2][n1] = xr[4 * n1 + n2];
+            ai[n2][n1] = xi[4 * n1 + n2];
+        }
+        dft4(ar[n2], ai[n2]);
+    }
+    static_for<1, 4>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        mul_w32<2 * k>(ar[1][k], ai[1][k]);
+        mul_w32<4 * k>(ar[2][k], ai[2][k]);
+        mul_w32<6 * k>(ar[3][k], ai[3][k]);
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        const float a0r = ar[0][k1], a0i = ai[0][k1], a1r = ar[1][k1], a1i = ai[1][k1];
+        const float a2r = ar[2][k1], a2i = ai[2][k1], a3r = ar[3][k1], a3i = ai[3][k1];
+        const float s02r = a0r + a2r, s02i = a0i + a2i, d02r = a0r - a2r, d02i = a0i - a2i;
+        const float s13r = a1r + a3r, s13i = a1i + a3i, d13r = a1r - a3r, d13i = a1i - a3i;
+        xr[k1] = s02r + s13r;      xi[k1] = s02i + s13i;
+        xr[k1 + 4] = d02r + d13i;  xi[k1 + 4] = d02i - d13r;
+        if constexpr (NOUT == 16) {
+            xr[k1 + 8] = s02r - s13r;   xi[k1 + 8] = s02i - s13i;
+            xr[k1 + 12] = d02r - d13i;  xi[k1 + 12] = d02i + d13r;
+        }
+    }
+}
+
+struct Smem {
+    float2 buf[16 * CR * CP];   // half a transpose (also the mirror exchange)
+    float2 tw[L];               // exp(-2 pi i e / L)
+};
+
+struct Tile {
+    int p, r;
+    long base;     // element offset of (x0 + 2p, row 0) at the tile's outer index
+    bool pad0, pad1;
+};
+
+__device__ inline Tile tile_of(const PassGeo& g) {
+    Tile t;
+    const int tid = threadIdx.x;
+    t.p = tid & (CP - 1);
+    t.r = tid >> 4;
+    const int ntx = g.P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int x = xt * TX + 2 * t.p;
+    t.base = (long)o * g.ostride + x;
+    t.pad0 = x >= g.nx;
+    t.pad1 = x + 1 >= g.nx;
+    return t;
+}
+
+__device__ inline void load_tw(Smem& S, const float* __restrict__ tw) {
+    for (int e = threadIdx.x; e < L; e += NT) S.tw[e] = make_float2(tw[2 * e], tw[2 * e + 1]);
+}
+
+__device__ inline const float2* row2(const float* v, long off) {
+    return reinterpret_cast<const float2*>(v + off);
+}
+__device__ inline float2* row2(float* v, long off) { return reinterpret_cast<float2*>(v + off); }
+
+// Points r + 16 m (m = 0..31) of the odd extensions (V[0] = V[n+1] = 0,
+// V[j] = u[j-1], V[L-j] = -V[j]) of the tile's two real lines per complex
+// line.  The mirrored half comes from thread (p, 16 - r) through LDS.
+// Ends with the LDS buffer free (barrier).
+__device__ inline void load_odd(Smem& S, const Tile& t, const float* __restrict__ u, long es,
+                                float (&xr)[32], float (&xi)[32]) {
+    float2 v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int j = t.r + 16 * m;   // <= n
+        v[m] = j >= 1 ? *row2(u, t.base + (long)(j - 1) * es) : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        S.buf[(t.r * 16 + m) * CP + t.p] = v[m];
+        xr[m] = v[m].x;
+        xi[m] = v[m].y;
+    }
+    __syncthreads();
+    const int rp = (16 - t.r) & 15;
+#pragma unroll
+    for (int m = 16; m < 32; ++m) {
+        // V[r + 16 m] = -V[(16 - r) + 16 (31 - m)] (r >= 1), -V[16 (32 - m)] (r = 0)
+        float2 w;
+        if (t.r == 0) {
+            const int mm = 32 - m;
+            w = mm == 16 ? make_float2(0.f, 0.f) : S.buf[mm * CP + t.p];
+        } else {
+            w = S.buf[(rp * 16 + (31 - m)) * CP + t.p];
+        }
+        xr[m] = -w.x;
+        xi[m] = -w.y;
+    }
+    __syncthreads();
+}
+
+// After the per-thread 32-point DFTs (B[k1] in xr/xi): y[h][rr] = w512^{rr k1}
+// B_rr[k1] for k1 = t + 16 h, gathered from the 16 residues rr.
+__device__ inline void transpose_fwd(Smem& S, const Tile& t, const float (&xr)[32],
+                                     const float (&xi)[32], float (&yr)[2][16], float (&yi)[2][16]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k1 = kk + 16 * h;
+            const float2 w = S.tw[t.r * k1];
+            const float a = xr[k1], b = xi[k1];
+            S.buf[(kk * CR + t.r) * CP + t.p] = make_float2(a * w.x - b * w.y, a * w.y + b * w.x);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int rr = 0; rr < CR; ++rr) {
+            const float2 w = S.buf[(t.r * CR + rr) * CP + t.p];
+            yr[h][rr] = w.x;
+            yi[h][rr] = w.y;
+        }
+        __syncthreads();
+    }
+}
+
+// Second transform, half h: thread (p, t) holds the spectrum at
+// f = k1 + 32 k2 (k1 = t + 16 h) after its 16-point DFTs over k2 (outputs j1);
+// scales them by the twiddles w512^{k1 j1} and gathers, for j1 = r, the
+// values of the 16 columns k1 of this half into xr[16 h .. 16 h + 15].
+__device__ inline void transpose_inv_half(Smem& S, const Tile& t, int h, const float (&dr)[16],
+                                          const float (&di)[16], float (&xr)[32], float (&xi)[32]) {
+    const int k1 = t.r + 16 * h;
+#pragma unroll
+    for (int j1 = 0; j1 < 16; ++j1) {
+        const float2 w = S.tw[k1 * j1];
+        const float a = dr[j1], b = di[j1];
+        S.buf[(j1 * CR + t.r) * CP + t.p] = make_float2(a * w.x - b * w.y, a * w.y + b * w.x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int tt = 0; tt < CR; ++tt) {
+        const float2 w = S.buf[(t.r * CR + tt) * CP + t.p];
+        xr[tt + 16 * h] = w.x;
+        xi[tt + 16 * h] = w.y;
+    }
+    __syncthreads();
+}
+
+// Strided DST-I pass (SCALE = false), or the last-axis pass S Lambda^{-1} S
+// with the Parseval partials of (r, P^{-1} r) (SCALE = true).
+// Register budget: four wavefronts per SIMD (128 VGPRs) for the plain pass;
+// the scale pass holds both halves of a transpose plus the Lambda operands
+// and is compiled for three (168 VGPRs) instead of spilling.
+template <bool SCALE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(SCALE ? 3 : 4)))
+void k_col_dst(DstArgs<float> a) {
+    __shared__ Smem S;
+    __shared__ double s_red[NT / 64];
+    if (a.ctrl && a.ctrl->done) return;
+    const Tile t = tile_of(a.g);
+    const long es = a.g.estride;
+    load_tw(S, a.tw);
+    float xr[32], xi[32];
+    load_odd(S, t, a.u, es, xr, xi);
+    dft32(xr, xi);
+    float yr[2][16], yi[2][16];
+    transpose_fwd(S, t, xr, xi, yr, yi);
+    if constexpr (!SCALE) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k1 = t.r + 16 * h;
+            dft16<8>(yr[h], yi[h]);
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) {
+                const int k = k1 + 32 * k2;   // DST index 1..n -> row k - 1
+                if (k >= 1) {
+                    const float s0 = t.pad0 ? 0.f : -yi[h][k2] * a.c;
+                    const float s1 = t.pad1 ? 0.f : yr[h][k2] * a.c;
+                    *row2(a.o, t.base + (long)(k - 1) * es) = make_float2(s0, s1);
+                }
+            }
+        }
+    } else {
+        // Lambda on line x at frequency k: a_last[k] P(x) + lc_last[k] Q(x)
+        float P[2], Q[2];
+        {
+            const int o = blockIdx.x / (a.g.P1 / TX);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                const int x = (int)(t.base - (long)o * a.g.ostride) + c;
+                P[c] = 0.f;
+                Q[c] = 0.f;
+                if (x < a.g.nx) {
+                    const float a1 = a.a1[x], l1 = a.lc1[x];
+                    if (a.dim == 2) {
+                        P[c] = a1 + l1;
+                        Q[c] = a1;
+                    } else {
+                        const float a2 = a.a2[o], l2 = a.lc2[o];
+                        P[c] = a2 * (a1 + l1) + l2 * a1;
+                        Q[c] = a2 * a1;
+                    }
+                }
+            }
+        }
+        double acc = 0.0;
+        // each half: 16-point DFTs over r (spectrum at f = k1 + 32 k2), the
+        // Lambda^{-1} scale, 16-point DFTs over k2, then its half of the
+        // transpose (frees the half's registers before the next one)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int k1 = t.r + 16 * h;
+            dft16<16>(yr[h], yi[h]);
+#pragma unroll
+            for (int k2 = 0; k2 < 16; ++k2) {
+                const int f = k1 + 32 * k2;
+                const int k = f <= NN ? f : L - f;
+                float wr = 0.f, wi = 0.f;
+                if (k >= 1 && k <= NN) {
+                    const float ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
+                    const float inv0 = P[0] != 0.f ? fast_rcp(ak * P[0] + lk * Q[0]) : 0.f;
+                    const float inv1 = P[1] != 0.f ? fast_rcp(ak * P[1] + lk * Q[1]) : 0.f;
+                    const float s1 = -yi[h][k2] * a.c;
+                    const float s2 = yr[h][k2] * a.c;
+                    wr = s1 * inv0;
+                    wi = s2 * inv1;
+                    if (f <= NN) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
+                }
+                yr[h][k2] = wr;
+                yi[h][k2] = wi;
+            }
+            dft16<16>(yr[h], yi[h]);
+            transpose_inv_half(S, t, h, yr[h], yi[h], xr, xi);
+        }
+        dft32<16>(xr, xi);
+#pragma unroll
+        for (int j2 = 0; j2 < 16; ++j2) {
+            const int j = t.r + 16 * j2;   // DST index 1..n -> row j - 1
+            if (j >= 1) {
+                const float s0 = t.pad0 ? 0.f : -xi[j2] * a.c;
+                const float s1 = t.pad1 ? 0.f : xr[j2] * a.c;
+                *row2(a.o, t.base + (long)(j - 1) * es) = make_float2(s0, s1);
+            }
+        }
+        if (a.partials) {
+            const double s = block_sum<NT>(acc, s_red);
+            if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
+        }
+    }
+}
+
+}  // namespace colx
+}  // namespace fsd

@@ -1,6 +1,6 @@
 // float32 instantiations of the line-transform passes (inner solves of the
 // mixed-precision defect correction).
-#include "fsd_wave.hpp"
+#include "fsd_passes.hpp"
 
 namespace fsd {
 FSD_DEFINE_LAUNCHERS2(float)

@@ -1,5 +1,5 @@
 // float64 instantiations of the line-transform passes.
-#include "fsd_wave.hpp"
+#include "fsd_passes.hpp"
 
 namespace fsd {
 FSD_DEFINE_LAUNCHERS2(double)

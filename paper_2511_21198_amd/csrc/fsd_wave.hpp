@@ -900,115 +900,4 @@ void k2_dst_s(DstArgs<T> a) {
     }
 }
 
-// ------------------------------------------------------------- dispatch
-// Lengths 64..512 use the wave engine; the others the LDS-stage engine of
-// fsd_lines.hpp.
-
-template <typename T, int L>
-hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
-    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
-    if constexpr (wave_engine_length<L>()) {
-        constexpr int rows = 2 * WX<T, L>::LINES;
-        const int g = (a.g.nrows + rows - 1) / rows;
-        if (nb) *nb = g;
-        if (g) {
-            switch (a.pro) {
-                case PRO_PUPDATE:
-                    hipLaunchKernelGGL((k2_toep_x<T, L, PRO_PUPDATE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-                    break;
-                case PRO_SCALE:
-                    hipLaunchKernelGGL((k2_toep_x<T, L, PRO_SCALE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-                    break;
-                default:
-                    hipLaunchKernelGGL((k2_toep_x<T, L, PRO_NONE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-            }
-        }
-    } else {
-        const int g = x_blocks<T>(L, a.g.nrows);
-        if (nb) *nb = g;
-        if (g) hipLaunchKernelGGL((k_toep_x<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int L>
-hipError_t toep_s_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
-    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
-    const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
-    if (nb) *nb = g;
-    if (!g) return hipSuccess;
-    if constexpr (wave_engine_length<L>()) {
-        static_assert(WS<T, L>::TX == 2 * lines_per_block(L, sizeof(T) == 8), "tile width");
-        hipLaunchKernelGGL((k2_toep_s<T, L>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_toep_s<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int L>
-hipError_t dst_x_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
-    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
-    if constexpr (wave_engine_length<L>()) {
-        constexpr int rows = 2 * WX<T, L>::LINES;
-        const int g = (a.g.nrows + rows - 1) / rows;
-        if (nb) *nb = g;
-        if (g) hipLaunchKernelGGL((k2_dst_x<T, L>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-    } else {
-        const int g = x_blocks<T>(L, a.g.nrows);
-        if (nb) *nb = g;
-        if (g) hipLaunchKernelGGL((k_dst_x<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-template <typename T, int L, bool SCALE>
-hipError_t dst_s_one(const DstArgs<T>& a, int* nb, hipStream_t s) {
-    if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
-    const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
-    if (nb) *nb = g;
-    if (!g) return hipSuccess;
-    if constexpr (wave_engine_length<L>()) {
-        hipLaunchKernelGGL((k2_dst_s<T, L, SCALE>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
-    } else if constexpr (SCALE) {
-        hipLaunchKernelGGL((k_dsts_s<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
-    } else {
-        hipLaunchKernelGGL((k_dst_s<T, L>), dim3(g), dim3(Tile<T, L>::NT), 0, s, a);
-    }
-    return hipGetLastError();
-}
-
-#define FSD_W_CASE_TX(LL) case LL: return toep_x_one<FT, LL>(a, nb, s);
-#define FSD_W_CASE_TS(LL) case LL: return toep_s_one<FT, LL>(a, nb, s);
-#define FSD_W_CASE_DX(LL) case LL: return dst_x_one<FT, LL>(a, nb, s);
-#define FSD_W_CASE_DS(LL) case LL: return dst_s_one<FT, LL, false>(a, nb, s);
-#define FSD_W_CASE_DSS(LL) case LL: return dst_s_one<FT, LL, true>(a, nb, s);
-
-#define FSD_DEFINE_LAUNCHERS2(T)                                                              \
-    template <>                                                                              \
-    hipError_t launch_toep_x<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
-        using FT = T;                                                                        \
-        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_TX) default: return hipErrorInvalidValue; }   \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_toep_s<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
-        using FT = T;                                                                        \
-        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_TS) default: return hipErrorInvalidValue; }   \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_dst_x<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
-        using FT = T;                                                                        \
-        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_DX) default: return hipErrorInvalidValue; }   \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_dst_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
-        using FT = T;                                                                        \
-        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_DS) default: return hipErrorInvalidValue; }   \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_dsts_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {        \
-        using FT = T;                                                                        \
-        switch (L) { FSD_FOR_EACH_L(FSD_W_CASE_DSS) default: return hipErrorInvalidValue; }  \
-    }
-
 }  // namespace fsd

@@ -83,8 +83,14 @@ def test_operators(fsd, case):
 # is rounded to bf16 (unit roundoff 2^-9; the rounding errors of the
 # entries are independent, so one application is off by about 2^-9/sqrt(3)
 # relative) and applied six times: bound 1e-2.
-@pytest.mark.parametrize("case", [CASES[0], CASES[1], CASES[2], CASES[5], CASES[8]],
-                         ids=[_ids(c) for c in (CASES[0], CASES[1], CASES[2], CASES[5], CASES[8])])
+# Axes of 255 points (transform length 512) on y and z take the column
+# engine of the float32 strided passes.
+PRE32_CASES = [CASES[0], CASES[1], CASES[2], CASES[5], CASES[8],
+               (3, [5, 255, 255], [0.35, 0.55, 0.75], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
+               (2, [47, 255], [0.6, 0.3], [1.2, 0.9], [0.7, 1.4])]
+
+
+@pytest.mark.parametrize("case", PRE32_CASES, ids=[_ids(c) for c in PRE32_CASES])
 @pytest.mark.parametrize("mfma", [False, True])
 def test_float32_preconditioner(fsd, case, mfma):
     dim, n, d, kp, km = case
