@@ -112,6 +112,13 @@ typedef struct {
                               DST-I as a bf16 matrix-core product on axes with
                               n <= 256 (1) or by FFT (0, default: faster as
                               measured at 255^3) */
+    double reorth_eta2;    /* GMRES reorthogonalisation test: a second
+                              Gram-Schmidt pass when ||w'||^2 <= reorth_eta2
+                              ||w||^2 after the first (0: never; 1 or more:
+                              always).  Negative (default): 0.5 for float64
+                              solves, 0 for the float32 inner solves of mixed
+                              precision, whose result the float64 defect
+                              correction checks. */
 } fsd_params;
 
 /* Per-solve statistics. */
@@ -129,7 +136,7 @@ typedef struct fsd_problem_s* fsd_problem;
 
 /* Fill p with defaults: dim 3, n = 63, domain (0,1), delta 0.5, k = 1,
  * M = 1, T = 1, AUTO solver, restart 20, tol 1e-9, maxit 0, FP64,
- * inner_tol 1e-5, max_outer 8, x0 PREV, dst_mfma 0. */
+ * inner_tol 1e-5, max_outer 8, x0 PREV, dst_mfma 0, reorth_eta2 -1. */
 fsd_status fsd_default_params(fsd_params* p);
 
 /* Validate p and build the host-side plan (Section 2 coefficients s_k, q_k,

@@ -46,6 +46,7 @@ class Params(C.Structure):
         ("x0_mode", C.c_int),
         ("allow_delta_zero", C.c_int),
         ("dst_mfma", C.c_int),
+        ("reorth_eta2", C.c_double),
     ]
 
 

@@ -218,28 +218,26 @@ __device__ inline void load_odd(Smem& S, const Tile& t, const float* __restrict_
     __syncthreads();
 }
 
-// After the per-thread 32-point DFTs (B[k1] in xr/xi): y[h][rr] = w512^{rr k1}
-// B_rr[k1] for k1 = t + 16 h, gathered from the 16 residues rr.
-__device__ inline void transpose_fwd(Smem& S, const Tile& t, const float (&xr)[32],
-                                     const float (&xi)[32], float (&yr)[2][16], float (&yi)[2][16]) {
+// After the per-thread 32-point DFTs (B[k1] in xr/xi), half h of the
+// transpose: y[rr] = w512^{rr k1} B_rr[k1] for k1 = t + 16 h, gathered from
+// the 16 residues rr (reads xr[16 h .. 16 h + 15] only).
+__device__ inline void transpose_fwd_half(Smem& S, const Tile& t, int h, const float (&xr)[32],
+                                          const float (&xi)[32], float (&yr)[16], float (&yi)[16]) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-            const int k1 = kk + 16 * h;
-            const float2 w = S.tw[t.r * k1];
-            const float a = xr[k1], b = xi[k1];
-            S.buf[(kk * CR + t.r) * CP + t.p] = make_float2(a * w.x - b * w.y, a * w.y + b * w.x);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int rr = 0; rr < CR; ++rr) {
-            const float2 w = S.buf[(t.r * CR + rr) * CP + t.p];
-            yr[h][rr] = w.x;
-            yi[h][rr] = w.y;
-        }
-        __syncthreads();
+    for (int kk = 0; kk < 16; ++kk) {
+        const int k1 = kk + 16 * h;
+        const float2 w = S.tw[t.r * k1];
+        const float a = xr[k1], b = xi[k1];
+        S.buf[(kk * CR + t.r) * CP + t.p] = make_float2(a * w.x - b * w.y, a * w.y + b * w.x);
     }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < CR; ++rr) {
+        const float2 w = S.buf[(t.r * CR + rr) * CP + t.p];
+        yr[rr] = w.x;
+        yi[rr] = w.y;
+    }
+    __syncthreads();
 }
 
 // Second transform, half h: thread (p, t) holds the spectrum at
@@ -283,8 +281,9 @@ void k_col_dst(DstArgs<float> a) {
     load_odd(S, t, a.u, es, xr, xi);
     dft32(xr, xi);
     float yr[2][16], yi[2][16];
-    transpose_fwd(S, t, xr, xi, yr, yi);
     if constexpr (!SCALE) {
+        transpose_fwd_half(S, t, 0, xr, xi, yr[0], yi[0]);
+        transpose_fwd_half(S, t, 1, xr, xi, yr[1], yi[1]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int k1 = t.r + 16 * h;
@@ -323,9 +322,11 @@ void k_col_dst(DstArgs<float> a) {
             }
         }
         double acc = 0.0;
-        // each half: 16-point DFTs over r (spectrum at f = k1 + 32 k2), the
-        // Lambda^{-1} scale, 16-point DFTs over k2, then its half of the
-        // transpose (frees the half's registers before the next one)
+        // each half of k1: 16-point DFTs over r (spectrum at f = k1 + 32 k2),
+        // the Lambda^{-1} scale, 16-point DFTs over k2, then its half of the
+        // second transpose
+        transpose_fwd_half(S, t, 0, xr, xi, yr[0], yi[0]);
+        transpose_fwd_half(S, t, 1, xr, xi, yr[1], yi[1]);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int k1 = t.r + 16 * h;
@@ -365,6 +366,181 @@ void k_col_dst(DstArgs<float> a) {
             const double s = block_sum<NT>(acc, s_red);
             if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
         }
+    }
+}
+
+// 32-point DFT of a line whose points 16..31 are zero (zero-padded input):
+// the radix-8 DFTs over n1 (points 4 n1 + n2) have their inputs 4..7 zero.
+__device__ inline void dft32_zin(float (&xr)[32], float (&xi)[32]) {
+    float tr[4][8], ti[4][8];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) {
+            tr[n2][n1] = xr[4 * n1 + n2];
+            ti[n2][n1] = xi[4 * n1 + n2];
+        }
+#pragma unroll
+        for (int n1 = 4; n1 < 8; ++n1) { tr[n2][n1] = 0.f; ti[n2][n1] = 0.f; }
+        dft8_pruned<float, true, false>(tr[n2], ti[n2]);
+    }
+    static_for<1, 8>([&](auto K) {
+        constexpr int k = decltype(K)::value;
+        mul_w32<k>(tr[1][k], ti[1][k]);
+        mul_w32<2 * k>(tr[2][k], ti[2][k]);
+        mul_w32<3 * k>(tr[3][k], ti[3][k]);
+    });
+#pragma unroll
+    for (int k1 = 0; k1 < 8; ++k1) {
+        const float a0r = tr[0][k1], a0i = ti[0][k1], a1r = tr[1][k1], a1i = ti[1][k1];
+        const float a2r = tr[2][k1], a2i = ti[2][k1], a3r = tr[3][k1], a3i = ti[3][k1];
+        const float s02r = a0r + a2r, s02i = a0i + a2i, d02r = a0r - a2r, d02i = a0i - a2i;
+        const float s13r = a1r + a3r, s13i = a1i + a3i, d13r = a1r - a3r, d13i = a1i - a3i;
+        xr[k1] = s02r + s13r;       xi[k1] = s02i + s13i;
+        xr[k1 + 8] = d02r + d13i;   xi[k1 + 8] = d02i - d13r;
+        xr[k1 + 16] = s02r - s13r;  xi[k1 + 16] = s02i - s13i;
+        xr[k1 + 24] = d02r - d13i;  xi[k1 + 24] = d02i + d13r;
+    }
+}
+
+// A_n along the line, (v[j-1] + 6 v[j] + v[j+1]) / 8 with zeros outside
+// 0..n-1, for the rows j = r + 16 m < n a thread holds: the values go to
+// LDS in natural order and the neighbours come back from there.  Ends with
+// the LDS buffer free (barrier).
+__device__ inline void line_stencil(Smem& S, const Tile& t, const float2 (&v)[16], float2 (&out)[16]) {
+#pragma unroll
+    for (int m = 0; m < 16; ++m) S.buf[(t.r + 16 * m) * CP + t.p] = v[m];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int j = t.r + 16 * m;
+        float2 l = make_float2(0.f, 0.f), rr = make_float2(0.f, 0.f);
+        if (j > 0) l = S.buf[(j - 1) * CP + t.p];
+        if (j + 1 < NN) rr = S.buf[(j + 1) * CP + t.p];
+        out[m] = make_float2((l.x + 6.f * v[m].x + rr.x) * 0.125f,
+                             (l.y + 6.f * v[m].y + rr.y) * 0.125f);
+    }
+    __syncthreads();
+}
+
+// Strided Toeplitz pass (float32, L = 512): o1 = Toep(u_fft) [+ A_n u_sten]
+// with the epilogue, o2 = A_n u_fft (when set).  The Toeplitz factor is the
+// circulant of length L applied as conj(FFT(conj(C) ... )): forward
+// transform of the zero-padded line, Y = conj(C Z), forward transform, and
+// the conjugate of the first n points.
+// The epilogue (EPI_*) is a template parameter: one kernel per mode keeps
+// the registers of the unused epilogues' operands out of the others.
+// Register budget: two wavefronts per SIMD.  With the two line stencils the
+// kernel does not fit 168 VGPRs without spilling, and the spilling build
+// measured slower (106 against 76 us for the y pass at 255^3).
+template <typename T, int EPI>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_col_toep(ToepArgs<T> a) {
+    static_assert(std::is_same<T, float>::value, "float32 passes only");
+    __shared__ Smem S;
+    __shared__ float2 s_spec[L];   // read after barriers: not hoisted into registers
+    __shared__ double s_red[NT / 64];
+    if (a.ctrl && a.ctrl->done) return;
+    const Tile t = tile_of(a.g);
+    const long es = a.g.estride;
+    const int o = blockIdx.x / (a.g.P1 / TX);
+    const int x = (int)(t.base - (long)o * a.g.ostride);
+    load_tw(S, a.tw);
+    for (int e = threadIdx.x; e < L; e += NT) s_spec[e] = make_float2(a.spec[2 * e], a.spec[2 * e + 1]);
+    float xr[32], xi[32];
+    {
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = t.r + 16 * m;
+            v[m] = j < NN ? *row2(a.u_fft, t.base + (long)j * es) : make_float2(0.f, 0.f);
+        }
+        if (a.o2) {
+            float2 st[16];
+            line_stencil(S, t, v, st);
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                const int j = t.r + 16 * m;
+                if (j < NN)
+                    *row2(a.o2, t.base + (long)j * es) =
+                        make_float2(t.pad0 ? 0.f : st[m].x, t.pad1 ? 0.f : st[m].y);
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            xr[m] = v[m].x;
+            xi[m] = v[m].y;
+        }
+    }
+    dft32_zin(xr, xi);
+    float yr2[2][16], yi2[2][16];
+    transpose_fwd_half(S, t, 0, xr, xi, yr2[0], yi2[0]);
+    transpose_fwd_half(S, t, 1, xr, xi, yr2[1], yi2[1]);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int k1 = t.r + 16 * h;
+        float (&yr)[16] = yr2[h];
+        float (&yi)[16] = yi2[h];
+        dft16<16>(yr, yi);
+        // Y = conj(C Z) at f = k1 + 32 k2
+#pragma unroll
+        for (int k2 = 0; k2 < 16; ++k2) {
+            const int f = k1 + 32 * k2;
+            const float2 c = s_spec[f];
+            const float zr = yr[k2], zi = yi[k2];
+            yr[k2] = c.x * zr - c.y * zi;
+            yi[k2] = -(c.x * zi + c.y * zr);
+        }
+        dft16<16>(yr, yi);
+        transpose_inv_half(S, t, h, yr, yi, xr, xi);
+    }
+    dft32<16>(xr, xi);
+    // rows j = r + 16 j2 < n: out = conj(Y) [+ A_n u_sten] and the epilogue
+    float2 sten[16];
+    if (a.u_sten) {
+        // the offset is made opaque here so that these loads are issued after
+        // the transforms instead of being hoisted to the top of the kernel,
+        // where their registers would stay live through both transforms
+        long off = t.base;
+        asm volatile("" : "+v"(off));
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = t.r + 16 * m;
+            v[m] = j < NN ? *row2(a.u_sten, off + (long)j * es) : make_float2(0.f, 0.f);
+        }
+        line_stencil(S, t, v, sten);
+    } else {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) sten[m] = make_float2(0.f, 0.f);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int j = t.r + 16 * m;
+        if (j >= NN) continue;
+        const long gi = t.base + (long)j * es;
+        float v0 = xr[m] + sten[m].x, v1 = -xi[m] + sten[m].y;
+        if (t.pad0) v0 = 0.f;
+        if (t.pad1) v1 = 0.f;
+        if constexpr (EPI == EPI_ADD_F) {
+            const long fo = (long)a.g.n1 * ((long)j * a.g.fr_i + (long)o * a.g.fr_o);
+            if (x < a.g.n1) v0 += (float)(a.dt * a.F[x + fo]);
+            if (x + 1 < a.g.n1) v1 += (float)(a.dt * a.F[x + 1 + fo]);
+        } else if constexpr (EPI == EPI_DOT_P) {
+            const float2 d = *row2(a.dot_p, gi);
+            acc += (double)d.x * (double)v0 + (double)d.y * (double)v1;
+        } else if constexpr (EPI == EPI_RESID) {
+            const float2 b = *row2(a.b, gi);
+            v0 = b.x - v0;
+            v1 = b.y - v1;
+            acc += (double)v0 * (double)v0 + (double)v1 * (double)v1;
+        }
+        *row2(a.o1, gi) = make_float2(v0, v1);
+    }
+    if constexpr (EPI == EPI_DOT_P || EPI == EPI_RESID) {
+        const double s = block_sum<NT>(acc, s_red);
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = s;
     }
 }
 

@@ -313,11 +313,12 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
         c->gm_w2 = sums[nv];
     } else if (op == GM_H2) {
         // Daniel-Gragg-Kaufman-Stewart test: keep w' when the first pass
-        // removed less than half of ||w||^2; otherwise take the second pass
-        // (its coefficients h2 are added to the Hessenberg column).
+        // removed less than a fraction 1 - gm_eta2 of ||w||^2 (gm_eta2 = 0.5:
+        // half); otherwise take the second pass (its coefficients h2 are
+        // added to the Hessenberg column).
         const double wp2 = sums[nv];
         c->gm_wp2 = wp2;
-        const int re = !(wp2 > 0.5 * c->gm_w2);
+        const int re = !(wp2 > c->gm_eta2 * c->gm_w2);
         c->gm_reorth = re;
         c->gm_rflag[j] = re;
         c->gm_nreorth += re;

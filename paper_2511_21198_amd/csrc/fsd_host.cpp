@@ -482,8 +482,13 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     const long Np = P->Np;
     const int m = P->restart;
     int np = 0;
+    // reorthogonalisation threshold: float64 solves keep the DGKS test at
+    // 1/2; the float32 inner solves of mixed precision take one pass (their
+    // result only feeds the float64 defect correction, and at 255^3 the
+    // second pass changed no iteration count)
+    const double eta2 = P->p.reorth_eta2 >= 0.0 ? P->p.reorth_eta2 : (is_f32<T>() ? 0.0 : 0.5);
     HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), m, s,
-                      abs_tol * abs_tol));
+                      abs_tol * abs_tol, eta2));
     // ||P^{-1} b||
     FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr));
     HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
@@ -806,6 +811,7 @@ fsd_status fsd_default_params(fsd_params* p) {
     p->maxit = 0;
     p->precision = FSD_PREC_FP64;
     p->dst_mfma = 0;
+    p->reorth_eta2 = -1.0;
     p->inner_tol = 1e-5;
     p->max_outer = 8;
     p->x0_mode = FSD_X0_PREV;

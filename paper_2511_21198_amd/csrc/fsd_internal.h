@@ -36,6 +36,7 @@ struct Ctrl {
     double abs2;      // absolute floor of thresh (0: purely relative test)
     double gm_w2;     // GMRES: ||w||^2 before Gram-Schmidt
     double gm_wp2;    // GMRES: ||w'||^2 after the first Gram-Schmidt pass
+    double gm_eta2;   // GMRES: second pass when ||w'||^2 <= gm_eta2 ||w||^2
     int gm_reorth;    // GMRES: the current step takes the second pass
     int gm_nreorth;   // GMRES: second passes taken in this solve
     int gm_rflag[kMaxRestartHdr];   // GMRES: second pass taken at column j (this cycle)

@@ -49,7 +49,22 @@ hipError_t toep_s_one(const ToepArgs<T>& a, int* nb, hipStream_t s) {
     const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
     if (nb) *nb = g;
     if (!g) return hipSuccess;
-    if constexpr (wave_engine_length<L>()) {
+    if constexpr (column_engine_length<T, L>()) {
+        static_assert(colx::TX == 2 * lines_per_block(L, false), "tile width");
+        switch (a.epi) {
+            case EPI_ADD_F:
+                hipLaunchKernelGGL((colx::k_col_toep<T, EPI_ADD_F>), dim3(g), dim3(colx::NT), 0, s, a);
+                break;
+            case EPI_DOT_P:
+                hipLaunchKernelGGL((colx::k_col_toep<T, EPI_DOT_P>), dim3(g), dim3(colx::NT), 0, s, a);
+                break;
+            case EPI_RESID:
+                hipLaunchKernelGGL((colx::k_col_toep<T, EPI_RESID>), dim3(g), dim3(colx::NT), 0, s, a);
+                break;
+            default:
+                hipLaunchKernelGGL((colx::k_col_toep<T, EPI_NONE>), dim3(g), dim3(colx::NT), 0, s, a);
+        }
+    } else if constexpr (wave_engine_length<L>()) {
         static_assert(WS<T, L>::TX == 2 * lines_per_block(L, sizeof(T) == 8), "tile width");
         hipLaunchKernelGGL((k2_toep_s<T, L>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
     } else {

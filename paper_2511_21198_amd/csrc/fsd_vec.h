@@ -44,7 +44,7 @@ hipError_t vec_copy(const T* a, T* b, long N, hipStream_t s);
 hipError_t vec_extrap(double* x, double* up, long N, int have, hipStream_t s);
 // abs2: absolute floor of the stopping threshold, thresh = max(tol2 bb, abs2).
 hipError_t ctrl_init(Ctrl* c, double tol2, int maxit, int restart, hipStream_t s,
-                     double abs2 = 0.0);
+                     double abs2 = 0.0, double eta2 = 0.5);
 hipError_t scalar_step(Ctrl* c, const double* partials, int nparts, int op, hipStream_t s);
 
 }  // namespace fsd

@@ -122,13 +122,14 @@ __global__ __launch_bounds__(VT) void k_extrap(double* __restrict__ x, double* _
     }
 }
 
-__global__ void k_ctrl_init(Ctrl* c, double tol2, int maxit, int restart, double abs2) {
+__global__ void k_ctrl_init(Ctrl* c, double tol2, int maxit, int restart, double abs2,
+                            double eta2) {
     if (threadIdx.x == 0) {
         c->bb = 0; c->rr = 0; c->rz = 0; c->pq = 0; c->alpha = 0; c->beta = 0;
         c->thresh = 0; c->tol2 = tol2; c->iters = 0; c->maxit = maxit; c->done = 0;
         c->status = 0; c->first = 1; c->gm_j = 0; c->gm_m = restart; c->gm_k = 0;
         c->gm_beta = 0; c->gm_hnext = 0; c->gm_scale = 0; c->abs2 = abs2;
-        c->gm_w2 = 0; c->gm_wp2 = 0; c->gm_reorth = 0; c->gm_nreorth = 0;
+        c->gm_w2 = 0; c->gm_wp2 = 0; c->gm_eta2 = eta2; c->gm_reorth = 0; c->gm_nreorth = 0;
         for (int j = 0; j < kMaxRestart; ++j) c->gm_rflag[j] = 0;
     }
 }
@@ -248,8 +249,9 @@ hipError_t vec_extrap(double* x, double* up, long N, int have, hipStream_t s) {
     hipLaunchKernelGGL(k_extrap, dim3(vgrid(N)), dim3(VT), 0, s, x, up, N, have);
     return hipGetLastError();
 }
-hipError_t ctrl_init(Ctrl* c, double tol2, int maxit, int restart, hipStream_t s, double abs2) {
-    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, c, tol2, maxit, restart, abs2);
+hipError_t ctrl_init(Ctrl* c, double tol2, int maxit, int restart, hipStream_t s, double abs2,
+                     double eta2) {
+    hipLaunchKernelGGL(k_ctrl_init, dim3(1), dim3(64), 0, s, c, tol2, maxit, restart, abs2, eta2);
     return hipGetLastError();
 }
 hipError_t scalar_step(Ctrl* c, const double* partials, int nparts, int op, hipStream_t s) {

@@ -29,7 +29,8 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
                 kminus: Sequence[float], M: int = 1, T: float = 1.0, solver: str = "auto",
                 restart: int = 20, tol: float = 1e-9, maxit: int = 0, precision: str = "fp64",
                 inner_tol: float = 1e-5, max_outer: int = 8, x0: str = "prev", domain=None,
-                allow_delta_zero: bool = False, dst_mfma: bool = False) -> nat.Params:
+                allow_delta_zero: bool = False, dst_mfma: bool = False,
+                reorth_eta2: Optional[float] = None) -> nat.Params:
     """fsd_params from keyword arguments (defaults from fsd_default_params)."""
     p = nat.Params()
     check(lib.fsd_default_params(C.byref(p)), "fsd_default_params")
@@ -55,6 +56,7 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
                  "extrap": nat.X0_EXTRAP, "guarded": nat.X0_GUARDED}[x0]
     p.allow_delta_zero = int(allow_delta_zero)
     p.dst_mfma = int(dst_mfma)
+    p.reorth_eta2 = -1.0 if reorth_eta2 is None else float(reorth_eta2)
     return p
 
 
@@ -66,10 +68,11 @@ class Problem:
                  solver: str = "auto", restart: int = 20, tol: float = 1e-9, maxit: int = 0,
                  precision: str = "fp64", inner_tol: float = 1e-5, max_outer: int = 8,
                  x0: str = "prev", domain=None, allow_delta_zero: bool = False,
-                 dst_mfma: bool = False, device: Optional[torch.device] = None,
+                 dst_mfma: bool = False, reorth_eta2: Optional[float] = None,
+                 device: Optional[torch.device] = None,
                  stream: Optional[torch.cuda.Stream] = None):
         p = make_params(dim, n, delta, kplus, kminus, M, T, solver, restart, tol, maxit, precision,
-                        inner_tol, max_outer, x0, domain, allow_delta_zero, dst_mfma)
+                        inner_tol, max_outer, x0, domain, allow_delta_zero, dst_mfma, reorth_eta2)
         self.params = p
         self.dim = dim
         self.n = tuple(int(v) for v in n[:dim])

@@ -157,6 +157,26 @@ def test_cn_run_mixed_mfma_dst(fsd, solver, case):
     assert relerr(u_gpu, u_ref) <= 1e-8
 
 
+@pytest.mark.parametrize("precision,eta2", [("mixed", 0.5), ("mixed", 1.0), ("fp64", 0.0),
+                                             ("fp64", 1.0)])
+def test_gmres_reorth_threshold(fsd, precision, eta2):
+    """The reorthogonalisation threshold only changes the Arnoldi basis's
+    rounding, not the result: never (0), the DGKS test (0.5) and always (1)
+    all reach the oracle's solution at the solver's accuracy."""
+    dim, n, d, kp, km = (3, [15, 31, 7], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3])
+    M = 4
+    tol = 1e-13 if precision == "fp64" else 1e-12
+    prob = fsd(dim, n, d, kp, km, M=M, T=1.0, tol=tol, solver="gmres", precision=precision,
+               inner_tol=1e-5, reorth_eta2=eta2)
+    orc = op.Problem(dim, n, d, kp, km, T=1.0, M=M)
+    rng = np.random.default_rng(23)
+    u0 = rng.standard_normal(orc.shape)
+    F = workloads.random_grid(orc.shape, 29)
+    u_gpu, _ = _run_gpu(prob, u0, lambda m: F, M)
+    u_ref, _ = cn.run(orc, u0, lambda m: F, tol=1e-13, x0_mode="prev", solver="gmres")
+    assert relerr(u_gpu, u_ref) <= (1e-10 if precision == "fp64" else 1e-8)
+
+
 def _golden(sel):
     rows = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))["rows"]
     return [r for r in rows if sel(r)]
