@@ -36,8 +36,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 # Device sources behind each kernel kind (the structures they read included).
-_LINE_SRC = ["fsd_internal.h", "fsd_lines.hpp", "fsd_wave.hpp", "fsd_lines_f32.hip",
-             "fsd_lines_f64.hip"]
+_LINE_SRC = ["fsd_internal.h", "fsd_lines.hpp", "fsd_wave.hpp", "fsd_cols.hpp", "fsd_passes.hpp",
+             "fsd_lines_f32.hip", "fsd_lines_f64.hip"]
 _SOURCES = {"toep": _LINE_SRC, "dst": _LINE_SRC, "dsts": _LINE_SRC,
             "gm": ["fsd_internal.h", "fsd_gmres.h", "fsd_gmres.hip"],
             "pcg": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
@@ -60,6 +60,9 @@ def source_hash(kind: str | None = None) -> str:
 
 
 _KINDS = [
+    (re.compile(r"k_col_toep\b"), "toep_s"),
+    (re.compile(r"k_col_dst\s*<\s*true"), "dsts"),
+    (re.compile(r"k_col_dst\b"), "dst_y"),
     (re.compile(r"k2?_toep_x\b"), "toep_x"),
     (re.compile(r"k2?_toep_s\b"), "toep_s"),
     (re.compile(r"k2?_dst_x\b"), "dst_x"),
@@ -159,6 +162,26 @@ def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.
     return res, factors
 
 
+def _stats_table(trace_dir: str, top: int):
+    """Markdown rows of the rocprofv3 --stats kernel summary in trace_dir."""
+    paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
+    if not paths:
+        return []
+    with open(paths[0]) as f:
+        rows = list(csv.DictReader(f))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    out = ["| kernel | calls | total ms | avg us | min us | max us | % |",
+           "|---|---:|---:|---:|---:|---:|---:|"]
+    for r in rows[:top]:
+        name = r["Name"]
+        if len(name) > 110:
+            name = name[:110]
+        out.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.3f} | "
+                   f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                   f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", required=True)
@@ -195,6 +218,10 @@ def main(argv=None):
                      f"{e['total_ms']:.3f} | {hb / 1e6:.2f} | {e['hbm_gbps']:.0f} |" if hb else
                      f"| {k} | {e['dispatches']} | {e['skipped']} | {e['avg_us']:.2f} | "
                      f"{e['total_ms']:.3f} | - | - |")
+    stats = _stats_table(a.trace, 25)
+    if stats:
+        lines += ["", "rocprofv3 `--stats` kernel summary of the same run (`*_kernel_stats.csv`, "
+                  "top 25 by total time; averages include the skipped dispatches):", ""] + stats
     text = "\n".join(lines) + "\n"
     if a.md:
         with open(a.md, "w") as f:
