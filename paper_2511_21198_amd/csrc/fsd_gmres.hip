@@ -315,10 +315,11 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
         // Daniel-Gragg-Kaufman-Stewart test: keep w' when the first pass
         // removed less than a fraction 1 - gm_eta2 of ||w||^2 (gm_eta2 = 0.5:
         // half); otherwise take the second pass (its coefficients h2 are
-        // added to the Hessenberg column).
+        // added to the Hessenberg column).  gm_eta2 = 0: never (the host
+        // then does not launch the second pass).
         const double wp2 = sums[nv];
         c->gm_wp2 = wp2;
-        const int re = !(wp2 > c->gm_eta2 * c->gm_w2);
+        const int re = c->gm_eta2 > 0.0 && !(wp2 > c->gm_eta2 * c->gm_w2);
         c->gm_reorth = re;
         c->gm_rflag[j] = re;
         c->gm_nreorth += re;

@@ -536,8 +536,9 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
                                         P->partials, &np, s));
                 }
                 HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H2, s));
-                // second pass, in place, only when the test asks for it
-                {
+                // second pass, in place, only when the test asks for it (never
+                // with a zero threshold: no launch)
+                if (eta2 > 0.0) {
                     ProfScope ps(P, K_GM_REORTH, is_f32<T>(), vb * (j + 3));
                     HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, vn, vn, Np, P->ctrl, h2off, MX_REORTH,
                                         P->partials, &np, s));
