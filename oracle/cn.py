@@ -4,8 +4,9 @@ Test infrastructure only (see the package docstring).
 
 For m = 1..M: b^m = (A_N - K) u^{m-1} + dt F^{m-1/2}; u^m = A^{-1} b^m,
 solved by PCG when k_{i,+} = k_{i,-} on every axis, else by left-preconditioned
-GMRES (Remark after ``linear_sys``; Section 3), or directly by LU for tiny
-grids.
+GMRES (Remark after ``linear_sys``; Section 3), on request by GMRES on the
+two-sided system (``two_side_system``, solver "gmres2"), or directly by LU
+for tiny grids.
 """
 from __future__ import annotations
 
@@ -30,6 +31,11 @@ def solve_step(prob: operators.Problem, b: np.ndarray, x0: np.ndarray | None,
         solver = "pcg" if prob.symmetric else "gmres"
     if solver == "pcg":
         return krylov.pcg(A, Minv, b, x0, tol, maxit)
+    if solver == "gmres2":
+        # two-sided system; the initial u = x0 is P^{-1/2} v0 with v0 = P^{1/2} x0
+        Mh = lambda v: operators.apply_Pinv_half(prob, v, Lam)
+        v0 = None if x0 is None else operators.apply_P_half(prob, x0, Lam)
+        return krylov.gmres_two_sided(A, Mh, b, v0, tol, restart, maxit)
     return krylov.gmres_left(A, Minv, b, x0, tol, restart, maxit)
 
 

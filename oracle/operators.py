@@ -353,6 +353,21 @@ def apply_Pinv(prob: Problem, R: np.ndarray, Lam: np.ndarray | None = None) -> n
     return dst_all(dst_all(R) / Lam)
 
 
+def apply_Pinv_half(prob: Problem, R: np.ndarray, Lam: np.ndarray | None = None) -> np.ndarray:
+    """P^{-1/2} R = S_N Lambda^{-1/2} S_N R, the half preconditioner of the
+    two-sided system (Section 3.2, ``two_side_system``)."""
+    if Lam is None:
+        Lam = precond_eigs(prob)
+    return dst_all(dst_all(R) / np.sqrt(Lam))
+
+
+def apply_P_half(prob: Problem, X: np.ndarray, Lam: np.ndarray | None = None) -> np.ndarray:
+    """P^{1/2} X = S_N Lambda^{1/2} S_N X."""
+    if Lam is None:
+        Lam = precond_eigs(prob)
+    return dst_all(dst_all(X) * np.sqrt(Lam))
+
+
 def apply_P(prob: Problem, X: np.ndarray, Lam: np.ndarray | None = None) -> np.ndarray:
     """P X = S_N Lambda S_N X."""
     if Lam is None:

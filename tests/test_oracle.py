@@ -338,3 +338,90 @@ def test_apply_A_at_sampled_entries(prob):
     for idx in np.ndindex(*prob.shape):
         assert abs(op.apply_A_at(prob, X, idx) - Y[idx]) <= 1e-13 * np.abs(Y).max()
         assert abs(op.apply_A_at(prob, X, idx, -1.0) - R[idx]) <= 1e-13 * np.abs(R).max()
+
+
+# ------------------------------------------------ two-sided system (NEXT row)
+
+NONSYM = [
+    _prob(3, [7, 7, 7], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
+    _prob(3, [5, 6, 7], [0.1, 0.5, 0.9], [19.0, 21.0, 23.0], [21.0, 23.0, 25.0]),
+    _prob(2, [15, 9], [0.8, 0.9], [1.0, 2.0], [2.0, 0.5]),
+]
+
+
+def _dense_half(prob):
+    """P^{-1/2} and P^{1/2} from the eigendecomposition of the dense tau
+    preconditioner (an independent route to the sine-transform forms)."""
+    P = op.dense_preconditioner(prob)
+    w, V = np.linalg.eigh(P)
+    return V @ np.diag(w ** -0.5) @ V.T, V @ np.diag(w ** 0.5) @ V.T
+
+
+@pytest.mark.parametrize("prob", NONSYM[:2] + PROBS[:3])
+def test_half_preconditioner_dense(prob):
+    """S_N Lambda^{-1/2} S_N and S_N Lambda^{1/2} S_N equal the symmetric
+    square roots of P^{-1} and P; applied twice they give P^{-1}."""
+    Pmh, Ph = _dense_half(prob)
+    R = np.random.default_rng(21).standard_normal(prob.shape)
+    z = op.apply_Pinv_half(prob, R)
+    np.testing.assert_allclose(z.reshape(-1), Pmh @ R.reshape(-1), rtol=1e-11,
+                               atol=1e-12 * np.abs(z).max())
+    np.testing.assert_allclose(op.apply_P_half(prob, R).reshape(-1), Ph @ R.reshape(-1),
+                               rtol=1e-11, atol=1e-12 * np.abs(R).max())
+    np.testing.assert_allclose(op.apply_Pinv_half(prob, z), op.apply_Pinv(prob, R),
+                               atol=1e-13 * np.abs(z).max())
+
+
+@pytest.mark.parametrize("prob", NONSYM)
+def test_two_sided_gmres_vs_lu(prob):
+    A, _ = op.dense_system(prob)
+    b = np.random.default_rng(22).standard_normal(prob.shape)
+    x_ref = np.linalg.solve(A, b.reshape(-1)).reshape(prob.shape)
+    for x0 in (None, np.random.default_rng(23).standard_normal(prob.shape)):
+        x, info = cn.solve_step(prob, b, x0, 1e-13, solver="gmres2")
+        assert info.converged
+        assert np.linalg.norm(x - x_ref) <= 1e-11 * np.linalg.norm(x_ref)
+
+
+def _varsigma(prob):
+    d = prob.dim
+    return 1.5 * max(math.tan(prob.delta[i] * math.pi / 2) * abs(prob.kplus[i] - prob.kminus[i])
+                     / (prob.kplus[i] + prob.kminus[i]) for i in range(d))
+
+
+@pytest.mark.parametrize("prob", NONSYM)
+def test_theorem_3_2_rate(prob):
+    """Theorem 3.2: GMRES on P^{-1/2} A P^{-1/2} v = P^{-1/2} b has
+    ||r_k|| <= omega^k ||r_0||, omega = sqrt((2 + 4 s^2) / (3 + 4 s^2)) with
+    s the Lemma 3.10 bound; checked at every iteration, restarted (restart 5)
+    and not."""
+    vs = _varsigma(prob)
+    omega = math.sqrt((2 + 4 * vs ** 2) / (3 + 4 * vs ** 2))
+    A = lambda v: op.apply_A(prob, v)
+    Mh = lambda v: op.apply_Pinv_half(prob, v)
+    b = np.random.default_rng(24).standard_normal(prob.shape)
+    for restart in (100, 5):
+        _, info = krylov.gmres_two_sided(A, Mh, b, None, 1e-12, restart, 100)
+        h = np.array(info.history)
+        k = np.arange(len(h))
+        assert np.all(h <= omega ** k * h[0] * (1 + 1e-10)), (restart, h, omega)
+
+
+@pytest.mark.parametrize("prob", NONSYM)
+def test_theorem_3_3_one_vs_two_sided(prob):
+    """Theorem 3.3: from corresponding initial guesses (here zero) the
+    one-sided GMRES residual ||P^{-1} b - P^{-1} A u_j|| is at most 2 sqrt(2)
+    times the two-sided one ||P^{-1/2} b - P^{-1/2} A P^{-1/2} v_j||, at
+    every iteration j >= 1 (both runs inside their first restart cycle)."""
+    Lam = op.precond_eigs(prob)
+    A = lambda v: op.apply_A(prob, v)
+    Minv = lambda v: op.apply_Pinv(prob, v, Lam)
+    Mh = lambda v: op.apply_Pinv_half(prob, v, Lam)
+    b = np.random.default_rng(25).standard_normal(prob.shape)
+    _, one = krylov.gmres_left(A, Minv, b, None, 1e-12, 200, 200)
+    _, two = krylov.gmres_two_sided(A, Mh, b, None, 1e-12, 200, 200)
+    r1 = np.array(one.history) * np.linalg.norm(Minv(b))
+    r2 = np.array(two.history) * np.linalg.norm(Mh(b))
+    k = min(len(r1), len(r2))
+    assert k > 3
+    assert np.all(r1[1:k] <= 2 * math.sqrt(2) * r2[1:k] * (1 + 1e-10)), (r1[:k], r2[:k])
