@@ -301,6 +301,28 @@ def batched_workload(a, streams=8, steps=8):
     return out
 
 
+def two_sided(w, F, u0, steps, warmup):
+    """GMRES(20) on the two-sided system P^{-1/2} A P^{-1/2} v = P^{-1/2} b
+    (the system Theorem 3.2 bounds) on the headline workload, float64 and
+    mixed precision, with the Theorem 3.2 rate omega of the workload."""
+    import math
+    from paper_2511_21198_amd.solver import Problem
+    common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
+                  solver="gmres2", restart=20, tol=w.tol, x0="prev")
+    vs = 1.5 * max(math.tan(w.delta[i] * math.pi / 2) * abs(w.kplus[i] - w.kminus[i])
+                   / (w.kplus[i] + w.kminus[i]) for i in range(3))
+    out = {"solver": "GMRES(20) on P^{-1/2} A P^{-1/2}, two half-preconditioner applications "
+                     "per iteration", "varsigma": round(vs, 4),
+           "omega": round(math.sqrt((2 + 4 * vs ** 2) / (3 + 4 * vs ** 2)), 4)}
+    for name, kw in (("fp64", dict(precision="fp64")),
+                     ("mixed", dict(precision="mixed", inner_tol=1e-4, max_outer=8))):
+        p = Problem(**common, **kw)
+        _, t, it, outer, _ = run_steps(p, u0, F, steps, warmup)
+        out[name] = {"steps_per_s": round(steps / t, 3), "iters": it, "outer": outer}
+        del p
+    return out
+
+
 def secondary_symmetric(a):
     """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
     PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
@@ -480,6 +502,8 @@ def main(argv=None):
     if errs:
         out["rel_err_vs_tight_fp64"] = errs
     if not a.no_secondary:
+        log("two-sided GMRES ...")
+        out["two_sided"] = two_sided(w, F, u0, a.steps, a.warmup)
         out["matvec_fp64"] = matvec_bench(w)
         out["secondary"] = secondary_symmetric(a)
     if not a.no_learned:

@@ -64,7 +64,11 @@ typedef enum {
 typedef enum {
     FSD_SOLVER_AUTO = 0,   /* PCG iff k_{i,+} == k_{i,-} on every axis */
     FSD_SOLVER_PCG = 1,
-    FSD_SOLVER_PGMRES = 2  /* left-preconditioned restarted GMRES */
+    FSD_SOLVER_PGMRES = 2, /* left-preconditioned restarted GMRES */
+    FSD_SOLVER_PGMRES2 = 3 /* restarted GMRES on the two-sided system
+                              P^{-1/2} A P^{-1/2} v = P^{-1/2} b, u = P^{-1/2} v
+                              (Section 3.2, the system Theorem 3.2 bounds); stops
+                              when ||P^{-1/2}(b - A u)|| <= tol ||P^{-1/2} b|| */
 } fsd_solver;
 
 typedef enum {

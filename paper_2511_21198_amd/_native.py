@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libfsd.so")
 # fsd_status
 OK, EINVAL, ENOTCONV, EBREAKDOWN, ENONFINITE, ESMALLWS, EHIP, EUNSUPPORTED, ENOTBOUND = range(9)
 # fsd_solver
-SOLVER_AUTO, SOLVER_PCG, SOLVER_PGMRES = 0, 1, 2
+SOLVER_AUTO, SOLVER_PCG, SOLVER_PGMRES, SOLVER_PGMRES2 = 0, 1, 2, 3
 # fsd_precision
 PREC_FP64, PREC_MIXED = 0, 1
 # fsd_x0_mode

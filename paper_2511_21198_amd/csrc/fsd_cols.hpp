@@ -338,8 +338,8 @@ void k_col_dst(DstArgs<float> a) {
                 float wr = 0.f, wi = 0.f;
                 if (k >= 1 && k <= NN) {
                     const float ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
-                    const float inv0 = P[0] != 0.f ? fast_rcp(ak * P[0] + lk * Q[0]) : 0.f;
-                    const float inv1 = P[1] != 0.f ? fast_rcp(ak * P[1] + lk * Q[1]) : 0.f;
+                    const float inv0 = P[0] != 0.f ? lam_inv(ak * P[0] + lk * Q[0], a.half) : 0.f;
+                    const float inv1 = P[1] != 0.f ? lam_inv(ak * P[1] + lk * Q[1], a.half) : 0.f;
                     const float s1 = -yi[h][k2] * a.c;
                     const float s2 = yr[h][k2] * a.c;
                     wr = s1 * inv0;

@@ -197,7 +197,8 @@ __global__ __launch_bounds__(256) void k_gdst_col(GdstArgs a) {
                 float wk = 0.f;
                 if (k < n && Pv != 0.f) {
                     const float sv = acc[s][r];
-                    wk = sv / (a.a_last[k] * Pv + a.lc_last[k] * Qv);
+                    const float lam = a.a_last[k] * Pv + a.lc_last[k] * Qv;
+                    wk = a.half ? sv * __builtin_amdgcn_rsqf(lam) : sv / lam;
                     part += (double)sv * (double)wk;
                 }
                 w[r] = wk;

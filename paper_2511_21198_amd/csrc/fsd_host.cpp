@@ -144,7 +144,7 @@ size_t layout(fsd_problem P, char* base) {
     P->partials = B.take<double>((size_t)P->maxparts * nslots);
     layout_tables<double>(P, B, P->t64);
     if (P->mixed) layout_tables<float>(P, B, P->t32);
-    const bool gm = P->solver == FSD_SOLVER_PGMRES;
+    const bool gm = P->solver == FSD_SOLVER_PGMRES || P->solver == FSD_SOLVER_PGMRES2;
     layout_vecs<double>(P, B, P->v64, gm && !P->mixed);
     if (P->mixed) layout_vecs<float>(P, B, P->v32, gm);
     return B.off;
@@ -290,7 +290,7 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
 // partial sums of (r, z).
 template <typename T>
 fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, double* partials,
-                      int* nparts) {
+                      int* nparts, bool half = false) {
     Tables<T>& tb = tabs<T>(P);
     Vecs<T>& v = vecs<T>(P);
     const int last = P->dim - 1;
@@ -362,6 +362,7 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
                 G.lc2 = reinterpret_cast<const float*>(tb.lc[1]);
             }
             G.partials = partials;
+            G.half = half ? 1 : 0;
             HIP_TRY(launch_gdst_col(G, true, nparts, P->stream));
         } else {
             DstArgs<T> S = mk(last, gl, cur, mid);
@@ -371,6 +372,7 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
             S.lc1 = tb.lc[0];
             if (P->dim == 3) { S.a2 = tb.a[1]; S.lc2 = tb.lc[1]; }
             S.partials = partials;
+            S.half = half ? 1 : 0;
             HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream));
         }
     }
@@ -489,8 +491,11 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     const double eta2 = P->p.reorth_eta2 >= 0.0 ? P->p.reorth_eta2 : (is_f32<T>() ? 0.0 : 0.5);
     HIP_TRY(ctrl_init(P->ctrl, tol * tol, (int)std::min<long>(maxit, 1L << 30), m, s,
                       abs_tol * abs_tol, eta2));
-    // ||P^{-1} b||
-    FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr));
+    // two-sided system: the basis lives in the P^{1/2} coordinates, every
+    // preconditioner application is P^{-1/2}
+    const bool split = P->solver == FSD_SOLVER_PGMRES2;
+    // ||P^{-1} b|| (||P^{-1/2} b||)
+    FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
     HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
     HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s));
     if (x0_zero) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
@@ -503,7 +508,7 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             MatvecOpts o;
             o.epi = EPI_RESID;
             FSD_TRY(op_matvec<T>(P, x, v.r, o, nullptr, b, nullptr, P->ctrl, &np));
-            FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr));
+            FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr, split));
         }
         HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
@@ -514,12 +519,21 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             for (int c = 0; c < chunk && j < m; ++c, ++j) {
                 P->prof_tag = j;
                 T* vj = v.V + (long)j * Np;
-                // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
-                MatvecOpts o;
-                o.pro = PRO_SCALE;
-                FSD_TRY(op_matvec<T>(P, j == 0 ? v.w : vj, v.q, o, nullptr, nullptr, vj, P->ctrl,
-                                     &np));
-                FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr));
+                if (!split) {
+                    // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
+                    MatvecOpts o;
+                    o.pro = PRO_SCALE;
+                    FSD_TRY(op_matvec<T>(P, j == 0 ? v.w : vj, v.q, o, nullptr, nullptr, vj,
+                                         P->ctrl, &np));
+                    FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr));
+                } else {
+                    // w = P^{-1/2} A P^{-1/2} v_j, v_j = scale * (w or V[j])
+                    HIP_TRY(gm_scale<T>(j == 0 ? v.w : vj, vj, Np, P->ctrl, s));
+                    FSD_TRY(op_precond<T>(P, vj, v.z, P->ctrl, nullptr, nullptr, true));
+                    MatvecOpts o;
+                    FSD_TRY(op_matvec<T>(P, v.z, v.q, o, nullptr, nullptr, nullptr, P->ctrl, &np));
+                    FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr, true));
+                }
                 const double vb = (double)P->N * sizeof(T);
                 {
                     ProfScope ps(P, K_GM_MDOT, is_f32<T>(), vb * (j + 2));
@@ -559,9 +573,19 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         }
         // x += V y over the columns of this cycle
         HIP_TRY(gm_scalar(P->ctrl, P->partials, 0, 0, 0, GM_SOLVE, s));
-        {
+        if (!split) {
             ProfScope ps(P, K_GM_UPDATE, is_f32<T>(), (double)P->N * sizeof(T) * (c.gm_k + 2));
             HIP_TRY(gm_update<T>(x, v.V, Np, Np, std::max(1, c.gm_k), P->ctrl, yoff, s));
+        } else if (c.gm_k > 0) {
+            // x += P^{-1/2} (V y): the combination into z, its half
+            // preconditioner into q (no early exit: the solve may be done), x += q
+            HIP_TRY(vec_fill<T>(v.z, Np, T(0), s));
+            {
+                ProfScope ps(P, K_GM_UPDATE, is_f32<T>(), (double)P->N * sizeof(T) * (c.gm_k + 2));
+                HIP_TRY(gm_update<T>(v.z, v.V, Np, Np, c.gm_k, P->ctrl, yoff, s));
+            }
+            FSD_TRY(op_precond<T>(P, v.z, v.q, nullptr, nullptr, nullptr, true));
+            HIP_TRY(vec_axpy<T>(x, v.q, Np, s));
         }
         if (c.done == 1) {
             converged = true;
@@ -589,7 +613,8 @@ template <typename T>
 fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
                   SolveOut& o, double abs_tol = 0.0) {
     P->prof_tag = -1;
-    if (P->solver == FSD_SOLVER_PGMRES) return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
+    if (P->solver == FSD_SOLVER_PGMRES || P->solver == FSD_SOLVER_PGMRES2)
+        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
     return pcg<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
 }
 
@@ -642,7 +667,10 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         // the outer test of the current iterate.
         Vecs<float>& f = P->v32;
         double* r = P->v64.r;
-        const bool left = P->solver == FSD_SOLVER_PGMRES;
+        // GMRES tests the preconditioned residual: P^{-1} r (left), P^{-1/2} r
+        // (two-sided)
+        const bool split = P->solver == FSD_SOLVER_PGMRES2;
+        const bool left = P->solver == FSD_SOLVER_PGMRES || split;
         if (x0_zero) HIP_TRY(vec_fill<double>(x, P->Np, 0.0, P->stream));
         long iters = 0;
         int outer = 0;
@@ -650,7 +678,7 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         double relres = 0.0, bnorm = 0.0, pbnorm = 0.0, prec_rel = 0.0;
         FSD_TRY(norm2(P, b, &bnorm));
         if (left) {
-            FSD_TRY(op_precond<double>(P, b, P->v64.z, nullptr, nullptr, nullptr));
+            FSD_TRY(op_precond<double>(P, b, P->v64.z, nullptr, nullptr, nullptr, split));
             FSD_TRY(norm2(P, P->v64.z, &pbnorm));
         }
         for (;;) {
@@ -662,7 +690,7 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
             if (outer >= P->p.max_outer || iters >= maxit) {
                 if (left) {
                     double pr = 0.0;
-                    FSD_TRY(op_precond<double>(P, r, P->v64.z, nullptr, nullptr, nullptr));
+                    FSD_TRY(op_precond<double>(P, r, P->v64.z, nullptr, nullptr, nullptr, split));
                     FSD_TRY(norm2(P, P->v64.z, &pr));
                     prec_rel = pbnorm > 0.0 ? pr / pbnorm : pr;
                     if (prec_rel <= tol) status = FSD_OK;
@@ -850,7 +878,7 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
         return fail(FSD_EINVAL, "unknown precision");
     if (p->precision == FSD_PREC_MIXED && !(p->inner_tol > 0.0 && p->inner_tol < 1.0))
         return fail(FSD_EINVAL, "inner_tol must be in (0, 1)");
-    if (p->solver < 0 || p->solver > 2) return fail(FSD_EINVAL, "unknown solver");
+    if (p->solver < 0 || p->solver > 3) return fail(FSD_EINVAL, "unknown solver");
     if (p->x0_mode < 0 || p->x0_mode > FSD_X0_GUARDED) return fail(FSD_EINVAL, "unknown x0_mode");
 
     fsd_problem P = new (std::nothrow) fsd_problem_s();

@@ -113,6 +113,7 @@ struct DstArgs {
     const T* a1; const T* lc1;   // x axis factors
     const T* a2; const T* lc2;   // y axis factors (3D scale pass only)
     int dim;
+    int half;             // scale pass: Lambda^{-1/2} (the two-sided system) instead of Lambda^{-1}
     double* partials;     // Parseval partials of (r, P^{-1} r)
     const Ctrl* ctrl;
 };
@@ -127,6 +128,7 @@ struct GdstArgs {
     const float* a1; const float* lc1;
     const float* a2; const float* lc2;
     int dim;
+    int half;             // scale pass: Lambda^{-1/2} instead of Lambda^{-1}
     double* partials;     // Parseval partials (scale pass)
     const Ctrl* ctrl;
 };

@@ -573,8 +573,8 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
             const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
             const T lam0 = ak * P0 + lk * Q0;
             const T lam1 = ak * P1v + lk * Q1v;
-            const T inv0 = P0 != T(0) ? T(1) / lam0 : T(0);
-            const T inv1 = P1v != T(0) ? T(1) / lam1 : T(0);
+            const T inv0 = P0 != T(0) ? (a.half ? T(1) / sqrt(lam0) : T(1) / lam0) : T(0);
+            const T inv1 = P1v != T(0) ? (a.half ? T(1) / sqrt(lam1) : T(1) / lam1) : T(0);
             const T s1 = -s_im[ad] * a.c;
             const T s2 = s_re[ad] * a.c;
             wr = s1 * inv0;

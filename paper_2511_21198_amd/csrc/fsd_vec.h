@@ -37,6 +37,8 @@ hipError_t vec_cast(const Tin* in, Tout* out, long N, double scale, hipStream_t 
 template <typename Td>
 hipError_t vec_axpy64(double* x, const Td* d, long N, double scale, hipStream_t s);
 template <typename T>
+hipError_t vec_axpy(T* x, const T* d, long N, hipStream_t s);   // x += d
+template <typename T>
 hipError_t vec_fill(T* x, long N, T v, hipStream_t s);
 template <typename T>
 hipError_t vec_copy(const T* a, T* b, long N, hipStream_t s);

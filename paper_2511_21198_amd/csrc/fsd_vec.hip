@@ -103,6 +103,12 @@ __global__ __launch_bounds__(VT) void k_axpy64(double* __restrict__ x, const Td*
         x[e] += scale * (double)d[e];
 }
 
+// x += d (same type)
+template <typename T>
+__global__ __launch_bounds__(VT) void k_add(T* __restrict__ x, const T* __restrict__ d, long N) {
+    for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) x[e] += d[e];
+}
+
 template <typename T>
 __global__ __launch_bounds__(VT) void k_fill(T* __restrict__ x, long N, T v) {
     for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) x[e] = v;
@@ -236,6 +242,11 @@ hipError_t vec_axpy64(double* x, const Td* d, long N, double scale, hipStream_t 
     return hipGetLastError();
 }
 template <typename T>
+hipError_t vec_axpy(T* x, const T* d, long N, hipStream_t s) {
+    hipLaunchKernelGGL((k_add<T>), dim3(vgrid(N)), dim3(VT), 0, s, x, d, N);
+    return hipGetLastError();
+}
+template <typename T>
 hipError_t vec_fill(T* x, long N, T v, hipStream_t s) {
     hipLaunchKernelGGL((k_fill<T>), dim3(vgrid(N)), dim3(VT), 0, s, x, N, v);
     return hipGetLastError();
@@ -268,7 +279,8 @@ hipError_t scalar_step(Ctrl* c, const double* partials, int nparts, int op, hipS
                                          int*, hipStream_t);                                     \
     template hipError_t vec_fill<T>(T*, long, T, hipStream_t);                                   \
     template hipError_t vec_copy<T>(const T*, T*, long, hipStream_t);                            \
-    template hipError_t vec_axpy64<T>(double*, const T*, long, double, hipStream_t);
+    template hipError_t vec_axpy64<T>(double*, const T*, long, double, hipStream_t);            \
+    template hipError_t vec_axpy<T>(T*, const T*, long, hipStream_t);
 
 FSD_VEC_INST(double)
 FSD_VEC_INST(float)

@@ -39,6 +39,22 @@ __device__ inline double fast_rcp(double x) {
     return fma(r, e, r);
 }
 
+// Reciprocal square root for the Lambda^{-1/2} scale of the two-sided
+// system: v_rsq_f32 for float; v_rsq_f64 refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2 for double.
+__device__ inline float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double fast_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
+}
+
+// Lambda^{-1} or, for the two-sided system, Lambda^{-1/2}
+template <typename T>
+__device__ inline T lam_inv(T lam, int half) { return half ? fast_rsqrt(lam) : fast_rcp(lam); }
+
 template <typename T, int L>
 struct WGeo {
     static constexpr int G = L / 8;                  // lanes per line
@@ -863,8 +879,8 @@ void k2_dst_s(DstArgs<T> a) {
                 T wr = 0, wi = 0;
                 if (k >= 1 && k <= n) {
                     const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
-                    const T inv0 = P0 != T(0) ? fast_rcp(ak * P0 + lk * Q0) : T(0);
-                    const T inv1 = P1v != T(0) ? fast_rcp(ak * P1v + lk * Q1v) : T(0);
+                    const T inv0 = P0 != T(0) ? lam_inv(ak * P0 + lk * Q0, a.half) : T(0);
+                    const T inv1 = P1v != T(0) ? lam_inv(ak * P1v + lk * Q1v, a.half) : T(0);
                     const T s1 = -xi[q] * a.c;
                     const T s2 = xr[q] * a.c;
                     wr = s1 * inv0;

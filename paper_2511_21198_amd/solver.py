@@ -45,7 +45,7 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
     p.M = int(M)
     p.T = float(T)
     p.solver = {"auto": nat.SOLVER_AUTO, "pcg": nat.SOLVER_PCG, "gmres": nat.SOLVER_PGMRES,
-                "pgmres": nat.SOLVER_PGMRES}[solver]
+                "pgmres": nat.SOLVER_PGMRES, "gmres2": nat.SOLVER_PGMRES2}[solver]
     p.restart = int(restart)
     p.tol = float(tol)
     p.maxit = int(maxit)

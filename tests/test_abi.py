@@ -72,6 +72,7 @@ def _init(nat, p):
     (dict(dim=4), 1), (dict(n=[0, 7, 7]), 1), (dict(delta=[1.0, 0.5, 0.5]), 1),
     (dict(delta=[0.0, 0.5, 0.5]), 1), (dict(kplus=[-1.0, 1.0, 1.0]), 1), (dict(T=0.0), 1),
     (dict(M=0), 1), (dict(tol=0.0), 1), (dict(restart=0), 1), (dict(restart=65), 1),
+    (dict(solver=4), 1), (dict(solver=-1), 1),
     (dict(n=[9, 7, 7]), 7), (dict(n=[2047, 7, 7]), 7), (dict(n=[100, 7, 7]), 7),
 ])
 def test_init_validation(nat, kw, status):
@@ -79,6 +80,13 @@ def test_init_validation(nat, kw, status):
     assert s == status
     assert not h.value
     assert len(nat.lib.fsd_last_error()) > 0
+
+
+def test_two_sided_gmres_accepted(nat):
+    s, h = _init(nat, _params(nat, n=[7, 7, 7], solver=nat.SOLVER_PGMRES2, precision=1))
+    assert s == nat.OK
+    assert nat.lib.fsd_workspace_bytes(h) > 0
+    nat.lib.fsd_destroy(h)
 
 
 def test_delta_zero_allowed_in_test_mode(nat):

@@ -177,6 +177,34 @@ def test_gmres_reorth_threshold(fsd, precision, eta2):
     assert relerr(u_gpu, u_ref) <= (1e-10 if precision == "fp64" else 1e-8)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", [
+    (3, [15, 31, 7], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
+    (2, [63, 47], [0.8, 0.9], [19, 21], [21, 23]),
+    (3, [5, 255, 63], [0.3, 0.7, 0.5], [1.2, 0.9, 1.0], [0.8, 1.1, 0.6]),
+], ids=lambda c: f"{c[0]}d-" + "x".join(map(str, c[1])))
+def test_two_sided_gmres_vs_oracle(fsd, case, precision):
+    """GMRES on the two-sided system P^{-1/2} A P^{-1/2} v = P^{-1/2} b (the
+    half preconditioner Lambda^{-1/2} in the scale pass of every engine):
+    CN steps against the oracle's two-sided GMRES; float64 iteration counts
+    within one of the oracle's."""
+    dim, n, d, kp, km = case
+    M = 3
+    tol = 1e-12 if precision == "fp64" else 1e-11
+    prob = fsd(dim, n, d, kp, km, M=M, T=1.0, tol=tol, solver="gmres2", precision=precision,
+               inner_tol=1e-5)
+    orc = op.Problem(dim, n, d, kp, km, T=1.0, M=M)
+    rng = np.random.default_rng(31)
+    u0 = rng.standard_normal(orc.shape)
+    F = workloads.random_grid(orc.shape, 37)
+    u_gpu, its_gpu = _run_gpu(prob, u0, lambda m: F, M)
+    u_ref, _ = cn.run(orc, u0, lambda m: F, tol=1e-13, x0_mode="prev", solver="gmres2")
+    assert relerr(u_gpu, u_ref) <= (1e-10 if precision == "fp64" else 1e-8)
+    if precision == "fp64":
+        _, its_ref = cn.run(orc, u0, lambda m: F, tol=tol, x0_mode="prev", solver="gmres2")
+        assert all(abs(a - b) <= 1 for a, b in zip(its_gpu, its_ref)), (its_gpu, its_ref)
+
+
 def _golden(sel):
     rows = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))["rows"]
     return [r for r in rows if sel(r)]
