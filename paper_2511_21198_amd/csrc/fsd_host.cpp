@@ -42,11 +42,11 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 enum Kind : int {
     K_TOEP_X, K_TOEP_Y, K_TOEP_Z, K_DST_X, K_DST_Y, K_DSTS_Y, K_DSTS_Z,
-    K_GM_MDOT, K_GM_MAXPY, K_GM_REORTH, K_GM_UPDATE, K_PCG_UPDATE, K_NKINDS
+    K_GM_MDOT, K_GM_MAXPY, K_GM_REORTH, K_GM_UPDATE, K_PCG_UPDATE, K_RESID_PREV, K_NKINDS
 };
 const char* const kKindNames[K_NKINDS] = {"toep_x", "toep_y", "toep_z", "dst_x", "dst_y",
                                           "dsts_y", "dsts_z", "gm_mdot", "gm_maxpy",
-                                          "gm_reorth", "gm_update", "pcg_update"};
+                                          "gm_reorth", "gm_update", "pcg_update", "resid_prev"};
 
 hipEvent_t prof_event(fsd_problem P) {
     if (P->prof_next < P->prof_pool.size()) return P->prof_pool[P->prof_next++];
@@ -386,6 +386,26 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
 }
 
 
+// r = b - A x with the partials of ||r||^2 (np): the Toeplitz matvec with
+// the residual epilogue, or, for the first residual of a CN step from
+// u^{m-1} in float64 (P->r0_hint), the stencil form 2 (b - A_N x) - dt F.
+template <typename T>
+fsd_status first_residual(fsd_problem P, const T* x, const T* b, T* r, const Ctrl* ctrl, int* np) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (P->r0_hint && x == P->v64.x && b == P->v64.b) {
+            P->r0_hint = false;
+            ProfScope ps(P, K_RESID_PREV, false, 4.0 * (double)P->N * sizeof(double));
+            HIP_TRY(resid_prev(x, b, P->r0_F, r, P->ax[0].n, P->ax[1].n,
+                               P->dim == 3 ? P->ax[2].n : 1, P->P1, P->dim, P->p.T / P->p.M,
+                               P->partials, np, P->stream));
+            return FSD_OK;
+        }
+    }
+    MatvecOpts o;
+    o.epi = EPI_RESID;
+    return op_matvec<T>(P, x, r, o, nullptr, b, nullptr, ctrl, np);
+}
+
 fsd_status read_ctrl(fsd_problem P) {
     HIP_TRY(hipMemcpyAsync(P->h_ctrl, P->ctrl, sizeof(Ctrl), hipMemcpyDeviceToHost, P->stream));
     HIP_TRY(hipStreamSynchronize(P->stream));
@@ -427,9 +447,7 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
         HIP_TRY(vec_copy<T>(b, v.r, Np, s));
         HIP_TRY(vec_dot<T>(v.r, v.r, Np, P->partials, P->ctrl, &np, s));
     } else {
-        MatvecOpts o;
-        o.epi = EPI_RESID;
-        FSD_TRY(op_matvec<T>(P, x, v.r, o, nullptr, b, nullptr, P->ctrl, &np));
+        FSD_TRY(first_residual<T>(P, x, b, v.r, P->ctrl, &np));
     }
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_RR0, s));
     FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
@@ -505,9 +523,7 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     for (int cycle = 0; !converged; ++cycle) {
         // r0 = P^{-1}(b - A x)
         if (!(x0_zero && cycle == 0)) {   // with x = 0, w still holds P^{-1} b
-            MatvecOpts o;
-            o.epi = EPI_RESID;
-            FSD_TRY(op_matvec<T>(P, x, v.r, o, nullptr, b, nullptr, P->ctrl, &np));
+            FSD_TRY(first_residual<T>(P, x, b, v.r, P->ctrl, &np));
             FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr, split));
         }
         HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
@@ -623,9 +639,7 @@ fsd_status true_residual(fsd_problem P, const double* x, const double* b, double
     hipStream_t s = P->stream;
     int np = 0;
     HIP_TRY(ctrl_init(P->ctrl, 0.0, 1, P->restart, s));
-    MatvecOpts o;
-    o.epi = EPI_RESID;
-    FSD_TRY(op_matvec<double>(P, x, r, o, nullptr, b, nullptr, nullptr, &np));
+    FSD_TRY(first_residual<double>(P, x, b, r, nullptr, &np));
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
     FSD_TRY(read_ctrl(P));
     *rnorm = std::sqrt(P->h_ctrl->pq);
@@ -1000,6 +1014,7 @@ fsd_status fsd_apply_Pinv32(fsd_problem P, const double* d_r, double* d_z) {
 
 fsd_status fsd_solve(fsd_problem P, const double* d_b, double* d_x, fsd_stats* st) {
     FSD_TRY(check_bound(P));
+    P->r0_hint = false;   // a plain solve never starts from u^{m-1}
     if (!d_b || !d_x) return fail(FSD_EINVAL, "null vector");
     Vecs<double>& v = P->v64;
     HIP_TRY(vec_pack<double>(d_b, v.b, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
@@ -1035,16 +1050,22 @@ fsd_status fsd_cn_step(fsd_problem P, const double* d_u_prev, const double* d_F,
         HIP_TRY(vec_extrap(v.x, v.up, P->Np, P->have_hist ? 1 : 0, s));
         P->have_hist = true;
     }
+    // from u^{m-1} the first residual takes the stencil form (first_residual)
+    P->r0_F = d_F;
     int fallback = 0;
     if (P->p.x0_mode == FSD_X0_GUARDED) {
         double rp = 0.0, rg = 0.0;
+        P->r0_hint = true;
         FSD_TRY(true_residual(P, v.x, v.b, v.r, &rp));
+        P->r0_hint = false;
         HIP_TRY(vec_pack<double>(d_guess, v.p, n1, P->P1, P->rows, 1.0, s));
         FSD_TRY(true_residual(P, v.p, v.b, v.r, &rg));
         if (std::isfinite(rg) && rg <= rp) HIP_TRY(vec_copy<double>(v.p, v.x, P->Np, s));
         else fallback = 1;
     }
+    P->r0_hint = P->p.x0_mode == FSD_X0_PREV || fallback;
     fsd_status stt = solve_internal(P, v.x, v.b, x0_zero, st);
+    P->r0_hint = false;
     if (st) st->x0_fallback = fallback;
     if (stt == FSD_EHIP) return stt;
     HIP_TRY(vec_unpack<double>(v.x, d_u_next, n1, P->P1, P->rows, s));

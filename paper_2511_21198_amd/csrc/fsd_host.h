@@ -94,6 +94,11 @@ struct fsd_problem_s {
     int last_iters = 4;
     int last_inner_iters[4] = {4, 4, 4, 4};   // per defect-correction pass (capped at 3)
     bool have_hist = false;
+    // fsd_cn_step from u^{m-1}: the first residual of the solve, b - A x with
+    // x = the packed u^{m-1} that b was built from (and F), is
+    // 2 (b - A_N x) - dt F (resid_prev); taken once by first_residual
+    bool r0_hint = false;
+    const double* r0_F = nullptr;
 
     bool prof_on = false;
     std::vector<fsd::ProfRec> prof;

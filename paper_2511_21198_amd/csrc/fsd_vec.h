@@ -38,6 +38,10 @@ template <typename Td>
 hipError_t vec_axpy64(double* x, const Td* d, long N, double scale, hipStream_t s);
 template <typename T>
 hipError_t vec_axpy(T* x, const T* d, long N, hipStream_t s);   // x += d
+// r = b - A u^{m-1} for b = rhs(u^{m-1}, F): 2 (b - A_N u) - dt F, partial ||r||^2
+hipError_t resid_prev(const double* u, const double* b, const double* F, double* r, int n1, int n2,
+                      int n3, int P1, int dim, double dt, double* partials, int* nparts,
+                      hipStream_t s);
 template <typename T>
 hipError_t vec_fill(T* x, long N, T v, hipStream_t s);
 template <typename T>

@@ -68,6 +68,94 @@ __global__ __launch_bounds__(VT) void k_dot(const T* __restrict__ a, const T* __
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
+// First residual of a CN step from the previous state (x0 = u^{m-1}):
+// b = (A_N - K) u + dt F and A u = (A_N + K) u give
+// r = b - A u = 2 (b - A_N u) - dt F, with A_N = A_{n3} (x) A_{n2} (x) A_{n1}
+// the separable tridiagonal mass operator (1, 6, 1)/8 per axis (zero beyond
+// the boundary; Section 2, ``linear_sys``): a 27-point stencil (9-point in
+// 2D, A_N = A_{n2} (x) A_{n1}) instead of a Toeplitz matvec.  Padded layout
+// [n3][n2][P1] (n3 = 1 in 2D); F dense [n3][n2][n1] (may be null: f = 0);
+// padding columns of r are written as zeros.  Partial ||r||^2.
+// One wave owns a tile of 64 columns x kRpY rows x kRpZ planes and marches
+// through its planes, keeping the (y, x)-filtered values of three
+// consecutive planes in registers; the x neighbours are two more loads of
+// the same cache lines.  u is read once from HBM (the halo rows and planes
+// of a tile come from the caches), b and F once, r written once.
+constexpr int kRpY = 8, kRpZ = 8;
+
+// s[i] = (A_{n2} (x) A_{n1} u)(y0 + i) on plane zz (zero outside the grid).
+// Loads are branch-free: indices are clamped into the grid and values
+// outside it replaced by zero, so all loads of a plane issue together.
+__device__ inline void resid_plane(const double* __restrict__ u, int xl, int xm, int xp, bool inx,
+                                   bool hasm, bool hasp, int n2, int n3, int P1, int y0, int zz,
+                                   double (&s)[kRpY]) {
+    if (zz < 0 || zz >= n3) {   // uniform: a plane beyond the grid
+#pragma unroll
+        for (int i = 0; i < kRpY; ++i) s[i] = 0.0;
+        return;
+    }
+    double h[kRpY + 2];
+#pragma unroll
+    for (int j = 0; j < kRpY + 2; ++j) {
+        const int yy = y0 - 1 + j;
+        const int yc = yy < 0 ? 0 : (yy >= n2 ? n2 - 1 : yy);
+        const double* ur = u + ((long)zz * n2 + yc) * P1;
+        const double c = ur[xl], m = ur[xm], p = ur[xp];
+        const double v = 0.75 * c + 0.125 * (hasm ? m : 0.0) + 0.125 * (hasp ? p : 0.0);
+        h[j] = (inx && yy >= 0 && yy < n2) ? v : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < kRpY; ++i) s[i] = 0.125 * h[i] + 0.75 * h[i + 1] + 0.125 * h[i + 2];
+}
+
+__global__ __launch_bounds__(VT) void k_resid_prev(const double* __restrict__ u,
+                                                   const double* __restrict__ b,
+                                                   const double* __restrict__ F, double* __restrict__ r,
+                                                   int n1, int n2, int n3, int P1, int dim, double dt,
+                                                   double* __restrict__ partials) {
+    __shared__ double sb[VT / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nxc = (P1 + 63) / 64, nyc = (n2 + kRpY - 1) / kRpY, nzc = (n3 + kRpZ - 1) / kRpZ;
+    const long nwt = (long)nxc * nyc * nzc;
+    const double wc = dim == 2 ? 1.0 : 0.75;   // 2D: no z factor (planes -1 and 1 are empty)
+    double acc = 0.0;
+    for (long t = (long)blockIdx.x * (VT / 64) + wid; t < nwt; t += (long)gridDim.x * (VT / 64)) {
+        const int xc = (int)(t % nxc);
+        const long t2 = t / nxc;
+        const int y0 = (int)(t2 % nyc) * kRpY, z0 = (int)(t2 / nyc) * kRpZ;
+        const int x = xc * 64 + lane;
+        const bool inx = x < n1, inp = x < P1;
+        // clamped columns: every load stays inside the row
+        const int xl = x < P1 ? x : P1 - 1, xm = xl > 0 ? xl - 1 : 0, xp = xl + 1 < P1 ? xl + 1 : xl;
+        const int xf = x < n1 ? x : n1 - 1;
+        const bool hasm = x > 0, hasp = x + 1 < n1;
+        double sm[kRpY], sc[kRpY], sp[kRpY];
+        resid_plane(u, xl, xm, xp, inx, hasm, hasp, n2, n3, P1, y0, z0 - 1, sm);
+        resid_plane(u, xl, xm, xp, inx, hasm, hasp, n2, n3, P1, y0, z0, sc);
+        for (int k = 0; k < kRpZ && z0 + k < n3; ++k) {
+            const int z = z0 + k;
+            resid_plane(u, xl, xm, xp, inx, hasm, hasp, n2, n3, P1, y0, z + 1, sp);
+#pragma unroll
+            for (int i = 0; i < kRpY; ++i) {
+                const int y = y0 + i;
+                if (y < n2) {   // uniform
+                    const long row = (long)z * n2 + y;
+                    const double bv = b[row * P1 + xl];
+                    const double fv = F ? F[xf + (long)n1 * row] : 0.0;
+                    const double an = 0.125 * sm[i] + wc * sc[i] + 0.125 * sp[i];
+                    const double v = inx ? 2.0 * (bv - an) - dt * fv : 0.0;
+                    if (inp) r[row * P1 + x] = v;
+                    acc += v * v;
+                }
+                sm[i] = sc[i];
+                sc[i] = sp[i];
+            }
+        }
+    }
+    const double s = block_sum_vt(acc, sb);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
 // x += alpha p ; r -= alpha q ; partial ||r||^2   (alpha from ctrl)
 template <typename T>
 __global__ __launch_bounds__(VT) void k_update_xr(T* __restrict__ x, T* __restrict__ r,
@@ -229,6 +317,16 @@ hipError_t vec_update_xr(T* x, T* r, const T* p, const T* q, long N, const Ctrl*
     const int g = vgrid(N);
     *nparts = g;
     hipLaunchKernelGGL((k_update_xr<T>), dim3(g), dim3(VT), 0, s, x, r, p, q, N, ctrl, partials);
+    return hipGetLastError();
+}
+hipError_t resid_prev(const double* u, const double* b, const double* F, double* r, int n1, int n2,
+                      int n3, int P1, int dim, double dt, double* partials, int* nparts,
+                      hipStream_t s) {
+    const long nwt = (long)((P1 + 63) / 64) * ((n2 + kRpY - 1) / kRpY) * ((n3 + kRpZ - 1) / kRpZ);
+    const int g = (int)std::max(1L, std::min<long>((nwt + VT / 64 - 1) / (VT / 64), kVecGrid));
+    *nparts = g;
+    hipLaunchKernelGGL(k_resid_prev, dim3(g), dim3(VT), 0, s, u, b, F, r, n1, n2, n3, P1, dim, dt,
+                       partials);
     return hipGetLastError();
 }
 template <typename Tin, typename Tout>
