@@ -268,3 +268,45 @@ def test_determinism(fsd):
         assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[1], outs[2]), solver
         fresh = fsd(dim, n, d, kp, km_, M=4, tol=1e-10, solver=solver)
         assert np.array_equal(host(fresh.cn_step(X)[0]), outs[0]), solver
+
+
+FIRST_RESID_CASES = [
+    # dim, n, with F: ragged tiles in every direction, lanes past the padded
+    # row (n1 = 95: two 64-column tiles over 96 columns), a degenerate grid,
+    # 2D, and a grid with more 64 x 8 x 8 wave tiles (1 x 96 x 64) than the
+    # kernel launches waves (it loops over tiles)
+    (3, [31, 23, 15], True),
+    (3, [95, 23, 11], False),
+    (3, [1, 2, 3], True),
+    (2, [127, 95], True),
+    (2, [1023, 767], True),
+    (3, [3, 767, 511], True),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("case", FIRST_RESID_CASES, ids=lambda c: f"{c[0]}d-" + "x".join(map(str, c[1])))
+def test_first_residual_from_prev(fsd, case, precision):
+    """A CN step from u^{m-1} starts from r0 = b - A u^{m-1} computed as
+    2 (b - A_N u) - dt F.  With a tolerance met at once the step returns
+    u^{m-1} unchanged and reports ||r0|| / ||b||, which must equal the
+    oracle's b - A u with b = (A_N - K) u + dt F (``linear_sys``) formed from
+    the dense Kronecker factors."""
+    dim, n, with_f = case
+    kw = dict(dim=dim, n=n, delta=[0.3, 0.6, 0.8][:dim], kplus=[1.0, 2.0, 0.5][:dim],
+              kminus=[1.0, 2.0, 0.5][:dim], M=4, T=1.0)
+    orc = op.Problem(**kw)
+    u = workloads.random_grid(orc.shape, 301)
+    F = workloads.random_grid(orc.shape, 302) if with_f else None
+    AN, Ks = op._terms(orc, u)
+    K = sum(orc.eta[i] * Ks[i] for i in range(dim))
+    b = AN - K + (orc.dt * F if with_f else 0.0)
+    ref = np.linalg.norm((b - (AN + K)).ravel()) / np.linalg.norm(b.ravel())
+    g = fsd(**kw, solver="pcg", precision=precision, tol=1e6, x0="prev")
+    g.profile(True)
+    out, st = g.cn_step(dev(u), dev(F) if with_f else None)
+    prof = g.profile_read()
+    assert prof.get("resid_prev_f64", {}).get("launches", 0) >= 1
+    assert st["iters"] == 0 and st["converged"] == 1
+    assert np.array_equal(host(out), u)
+    assert abs(st["relres"] - ref) <= 1e-12 * ref
