@@ -41,7 +41,8 @@ _LINE_SRC = ["fsd_internal.h", "fsd_lines.hpp", "fsd_wave.hpp", "fsd_cols.hpp", 
 _SOURCES = {"toep": _LINE_SRC, "dst": _LINE_SRC, "dsts": _LINE_SRC,
             "gm": ["fsd_internal.h", "fsd_gmres.h", "fsd_gmres.hip"],
             "pcg": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
-            "cast": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"]}
+            "cast": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
+            "resid": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"]}
 
 
 def source_hash(kind: str | None = None) -> str:
@@ -74,6 +75,7 @@ _KINDS = [
     (re.compile(r"k_gm_update\b"), "gm_update"),
     (re.compile(r"k_update_xr\b"), "pcg_update"),
     (re.compile(r"k_cast\b"), "cast"),
+    (re.compile(r"k_resid_prev\b"), "resid_prev_f64"),
 ]
 
 
@@ -106,7 +108,7 @@ def classify(rows, dim=3):
         if kind.startswith("toep"):
             last_toep = kind
         dt = _dtype(name)
-        out.append(f"{kind}_{dt}" if dt and kind != "cast" else kind)
+        out.append(f"{kind}_{dt}" if dt and kind not in ("cast", "resid_prev_f64") else kind)
     return out
 
 
