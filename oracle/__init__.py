@@ -14,6 +14,8 @@ coeffs     s_k, q_k, eta, A_n and tau eigenvalues            (Section 2, Section
 operators  dense assembly (tiny sizes) and structured operators (any size)
 krylov     textbook PCG and left-preconditioned restarted GMRES
 cn         the Crank-Nicolson time loop
+circulant  the comparators of the experiments: no preconditioner, T. Chan's
+           and Strang's circulants                           (Section 4)
 examples   the manufactured solutions of Examples 4.1 and 4.2 (Section 4)
 nn         reference 3D convolution network (forward/backward) for the learned
            warm start

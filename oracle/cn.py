@@ -14,24 +14,32 @@ from typing import Callable
 
 import numpy as np
 
-from . import krylov, operators
+from . import circulant, krylov, operators
 
 
 def solve_step(prob: operators.Problem, b: np.ndarray, x0: np.ndarray | None,
                tol: float, solver: str = "auto", restart: int = 20,
-               maxit: int | None = None, Lam: np.ndarray | None = None):
-    """One linear solve A u = b with the tau preconditioner."""
-    if Lam is None:
-        Lam = operators.precond_eigs(prob)
+               maxit: int | None = None, Lam: np.ndarray | None = None,
+               precond: str = "tau"):
+    """One linear solve A u = b with the tau preconditioner, or with one of
+    the comparators of Section 4 (precond "none", "tchan", "strang"; see
+    :mod:`oracle.circulant`)."""
     if maxit is None:
         maxit = int(np.prod(prob.n))
     A = lambda v: operators.apply_A(prob, v)
-    Minv = lambda v: operators.apply_Pinv(prob, v, Lam)
+    if precond == "tau":
+        if Lam is None:
+            Lam = operators.precond_eigs(prob)
+        Minv = lambda v: operators.apply_Pinv(prob, v, Lam)
+    else:
+        Minv = circulant.minv(prob, precond)
     if solver == "auto":
         solver = "pcg" if prob.symmetric else "gmres"
     if solver == "pcg":
         return krylov.pcg(A, Minv, b, x0, tol, maxit)
     if solver == "gmres2":
+        if precond != "tau":
+            raise ValueError("the two-sided system is built for the tau preconditioner")
         # two-sided system; the initial u = x0 is P^{-1/2} v0 with v0 = P^{1/2} x0
         Mh = lambda v: operators.apply_Pinv_half(prob, v, Lam)
         v0 = None if x0 is None else operators.apply_P_half(prob, x0, Lam)
@@ -41,17 +49,19 @@ def solve_step(prob: operators.Problem, b: np.ndarray, x0: np.ndarray | None,
 
 def run(prob: operators.Problem, u0: np.ndarray, F_of_m: Callable[[int], np.ndarray | None],
         tol: float, x0_mode: str = "prev", solver: str = "auto", restart: int = 20,
-        maxit: int | None = None, steps: int | None = None):
+        maxit: int | None = None, steps: int | None = None, precond: str = "tau"):
     """Advance ``steps`` (default M) CN steps from u0.  F_of_m(m) returns
     F^{m-1/2} (or None for f = 0).  x0_mode: "zero" (replication of the
-    experiments) or "prev" (u^{m-1}).  Returns (u, per-step iteration counts)."""
-    Lam = operators.precond_eigs(prob)
+    experiments) or "prev" (u^{m-1}).  precond: "tau" (the method) or a
+    comparator ("none", "tchan", "strang").  Returns (u, per-step iteration
+    counts)."""
+    Lam = operators.precond_eigs(prob) if precond == "tau" else None
     u = u0.copy()
     iters = []
     for m in range(1, (steps or prob.M) + 1):
         b = operators.apply_rhs(prob, u, F_of_m(m))
         x0 = None if x0_mode == "zero" else u
-        u, info = solve_step(prob, b, x0, tol, solver, restart, maxit, Lam)
+        u, info = solve_step(prob, b, x0, tol, solver, restart, maxit, Lam, precond)
         iters.append(info.iters)
     return u, iters
 
