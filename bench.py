@@ -323,6 +323,41 @@ def two_sided(w, F, u0, steps, warmup):
     return out
 
 
+def comparators(w, F, u0):
+    """The comparator preconditioners of Section 4 on the headline workload
+    (float64 left GMRES(20) from u^{m-1}): CN steps/s and iterations, 2 timed
+    steps after 1, against the sine-transform preconditioner; and one
+    application of P^{-1} (100 calls, library hipEvents per pass)."""
+    import torch
+    from paper_2511_21198_amd.solver import Problem
+    common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
+                  solver="gmres", restart=20, tol=w.tol, x0="prev", precision="fp64")
+    out = {"solver": "float64 left GMRES(20), x0 = u^{m-1}; 2 timed CN steps after 1"}
+    r = torch.from_numpy(w.F).cuda()
+    for kind in ("tau", "tchan", "strang", "none"):
+        log(f"comparator {kind} ...")
+        p = Problem(**common, precond=kind, maxit=4000)
+        _, t, it, _, _ = run_steps(p, u0, F, 2, 1)
+        e = {"steps_per_s": round(2 / t, 3), "iters": it}
+        z = torch.empty_like(r)
+        for _ in range(3):
+            p.apply_Pinv(r, z)
+        torch.cuda.synchronize()
+        p.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(100):
+            p.apply_Pinv(r, z)
+        torch.cuda.synchronize()
+        e["apply_Pinv_ms"] = round((time.perf_counter() - t0) * 10.0, 4)
+        prof = p.profile_read()
+        p.profile(False)
+        e["passes"] = {k: {"avg_ms": round(v["avg_ms"], 4), "gbps": round(v["gbps"], 1)}
+                       for k, v in prof.items() if v["launches"]}
+        out[kind] = e
+        del p
+    return out
+
+
 def secondary_symmetric(a):
     """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
     PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
@@ -504,6 +539,7 @@ def main(argv=None):
     if not a.no_secondary:
         log("two-sided GMRES ...")
         out["two_sided"] = two_sided(w, F, u0, a.steps, a.warmup)
+        out["comparators"] = comparators(w, F, u0)
         out["matvec_fp64"] = matvec_bench(w)
         out["secondary"] = secondary_symmetric(a)
     if not a.no_learned:

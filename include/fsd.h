@@ -92,6 +92,21 @@ typedef enum {
                               Costs two extra float64 matvecs. */
 } fsd_x0_mode;
 
+typedef enum {
+    FSD_PC_TAU = 0,        /* the sine-transform preconditioner P = S Lambda S
+                              (Section 3): the method, and the default */
+    FSD_PC_NONE = 1,       /* no preconditioner (P = I): the CG / GMRES columns
+                              of the comparisons in Section 4 */
+    FSD_PC_TCHAN = 2,      /* comparator of Section 4: every Toeplitz factor
+                              (A_i and B_i) replaced by T. Chan's optimal
+                              circulant, c_j = ((n-j) t_j + j t_{j-n}) / n;
+                              P^{-1} applied by DFTs of length n_i.  float64
+                              precision and the one-sided solvers only */
+    FSD_PC_STRANG = 3      /* as FSD_PC_TCHAN with Strang's circulant, which
+                              keeps the central diagonals: s_j = t_j for
+                              j <= n/2, t_{j-n} above */
+} fsd_precond;
+
 /* Problem parameters.  Fill with fsd_default_params() first. */
 typedef struct {
     int dim;               /* 2 or 3 */
@@ -123,6 +138,7 @@ typedef struct {
                               solves, 0 for the float32 inner solves of mixed
                               precision, whose result the float64 defect
                               correction checks. */
+    int precond;           /* fsd_precond (default FSD_PC_TAU) */
 } fsd_params;
 
 /* Per-solve statistics. */

@@ -23,6 +23,8 @@ SOLVER_AUTO, SOLVER_PCG, SOLVER_PGMRES, SOLVER_PGMRES2 = 0, 1, 2, 3
 PREC_FP64, PREC_MIXED = 0, 1
 # fsd_x0_mode
 X0_PREV, X0_ZERO, X0_EXTERNAL, X0_EXTRAP, X0_GUARDED = 0, 1, 2, 3, 4
+# fsd_precond
+PC_TAU, PC_NONE, PC_TCHAN, PC_STRANG = 0, 1, 2, 3
 
 
 class Params(C.Structure):
@@ -47,6 +49,7 @@ class Params(C.Structure):
         ("allow_delta_zero", C.c_int),
         ("dst_mfma", C.c_int),
         ("reorth_eta2", C.c_double),
+        ("precond", C.c_int),
     ]
 
 

@@ -8,6 +8,7 @@
 #include <string>
 #include <type_traits>
 
+#include "fsd_circ.h"
 #include "fsd_gmres.h"
 #include "fsd_host.h"
 #include "fsd_vec.h"
@@ -42,11 +43,13 @@ size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 enum Kind : int {
     K_TOEP_X, K_TOEP_Y, K_TOEP_Z, K_DST_X, K_DST_Y, K_DSTS_Y, K_DSTS_Z,
-    K_GM_MDOT, K_GM_MAXPY, K_GM_REORTH, K_GM_UPDATE, K_PCG_UPDATE, K_RESID_PREV, K_NKINDS
+    K_GM_MDOT, K_GM_MAXPY, K_GM_REORTH, K_GM_UPDATE, K_PCG_UPDATE, K_RESID_PREV, K_CIRC,
+    K_NKINDS
 };
 const char* const kKindNames[K_NKINDS] = {"toep_x", "toep_y", "toep_z", "dst_x", "dst_y",
                                           "dsts_y", "dsts_z", "gm_mdot", "gm_maxpy",
-                                          "gm_reorth", "gm_update", "pcg_update", "resid_prev"};
+                                          "gm_reorth", "gm_update", "pcg_update", "resid_prev",
+                                          "circ"};
 
 hipEvent_t prof_event(fsd_problem P) {
     if (P->prof_next < P->prof_pool.size()) return P->prof_pool[P->prof_next++];
@@ -144,6 +147,17 @@ size_t layout(fsd_problem P, char* base) {
     P->partials = B.take<double>((size_t)P->maxparts * nslots);
     layout_tables<double>(P, B, P->t64);
     if (P->mixed) layout_tables<float>(P, B, P->t32);
+    if (P->pc == FSD_PC_TCHAN || P->pc == FSD_PC_STRANG) {
+        P->zc = B.take<double>(2 * (size_t)P->Np);
+        for (int i = 0; i < P->dim; ++i) {
+            const size_t n = (size_t)P->ax[i].n, M = (size_t)P->ax[i].cM;
+            P->cw[i] = B.take<double>(2 * n);
+            P->cbsp[i] = B.take<double>(2 * M);
+            P->ctw[i] = B.take<double>(M);
+            P->cea[i] = B.take<double>(2 * n);
+            P->ceb[i] = B.take<double>(2 * n);
+        }
+    }
     const bool gm = P->solver == FSD_SOLVER_PGMRES || P->solver == FSD_SOLVER_PGMRES2;
     layout_vecs<double>(P, B, P->v64, gm && !P->mixed);
     if (P->mixed) layout_vecs<float>(P, B, P->v32, gm);
@@ -284,6 +298,81 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
     return FSD_OK;
 }
 
+// Circulant comparators (FSD_PC_TCHAN / FSD_PC_STRANG, Section 4):
+// P^{-1} r = F^{-1} Lambda^{-1} F r with F the d-dimensional DFT (fsd_circ.hip):
+// x forward (real in), y forward (3D), last axis forward / Lambda / inverse,
+// y inverse (3D), x inverse (real out).  Complex intermediates in P->zc.
+fsd_status circ_precond(fsd_problem P, const double* in, double* out, const Ctrl* ctrl) {
+    double2* Z = reinterpret_cast<double2*>(P->zc);
+    const int n1 = P->ax[0].n, n2 = P->ax[1].n, n3 = P->dim == 3 ? P->ax[2].n : 1;
+    auto mk = [&](int axis, int mode) {
+        const Axis& ax = P->ax[axis];
+        CircArgs a;
+        a.n = ax.n;
+        a.M = ax.cM;
+        a.logM = ax.clog;
+        a.lpb = circ_lines_per_block(ax.cM);
+        a.mode = mode;
+        a.w = reinterpret_cast<const double2*>(P->cw[axis]);
+        a.bsp = reinterpret_cast<const double2*>(P->cbsp[axis]);
+        a.tw = reinterpret_cast<const double2*>(P->ctw[axis]);
+        for (int i = 0; i < P->dim; ++i) {
+            a.ea[i] = reinterpret_cast<const double2*>(P->cea[i]);
+            a.eb[i] = reinterpret_cast<const double2*>(P->ceb[i]);
+        }
+        a.dim = P->dim;
+        a.ctrl = ctrl;
+        a.in_c = Z;
+        a.out_c = Z;
+        if (axis == 0) {          // rows
+            a.nlines = P->rows;
+            a.nx = 1;
+            a.os = P->P1;
+            a.st = 1;
+            a.pad = P->P1;
+        } else if (axis == 1) {   // (z, x) columns
+            a.nlines = (long)n3 * n1;
+            a.nx = n1;
+            a.os = (long)n2 * P->P1;
+            a.xs = 1;
+            a.st = P->P1;
+        } else {                  // (y, x) columns
+            a.nlines = (long)n2 * n1;
+            a.nx = n1;
+            a.os = P->P1;
+            a.xs = 1;
+            a.st = (long)n2 * P->P1;
+        }
+        return a;
+    };
+    const double N = (double)P->N;
+    {
+        ProfScope ps(P, K_CIRC, false, 24.0 * N);   // 8 bytes in, 16 out per value
+        CircArgs a = mk(0, CM_FWD_R2C);
+        a.in_r = in;
+        HIP_TRY(launch_circ(a, P->stream));
+    }
+    if (P->dim == 3) {
+        ProfScope ps(P, K_CIRC, false, 32.0 * N);
+        HIP_TRY(launch_circ(mk(1, CM_FWD), P->stream));
+    }
+    {
+        ProfScope ps(P, K_CIRC, false, 32.0 * N);
+        HIP_TRY(launch_circ(mk(P->dim - 1, CM_LAST), P->stream));
+    }
+    if (P->dim == 3) {
+        ProfScope ps(P, K_CIRC, false, 32.0 * N);
+        HIP_TRY(launch_circ(mk(1, CM_INV), P->stream));
+    }
+    {
+        ProfScope ps(P, K_CIRC, false, 24.0 * N);
+        CircArgs a = mk(0, CM_INV_C2R);
+        a.out_r = out;
+        HIP_TRY(launch_circ(a, P->stream));
+    }
+    return FSD_OK;
+}
+
 // Preconditioner z = S_N Lambda^{-1} S_N r (Section 3, ``diag_tau_pre``):
 // DST-I along x, (y,) then DST-I / Lambda^{-1} / DST-I along the last axis,
 // then back.  With `partials`, the last-axis pass also leaves the Parseval
@@ -291,6 +380,18 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
 template <typename T>
 fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, double* partials,
                       int* nparts, bool half = false) {
+    if (P->pc != FSD_PC_TAU) {
+        // comparators of Section 4; the Parseval partials become a dot product
+        if (P->pc == FSD_PC_NONE) {
+            if (in != out) HIP_TRY(vec_copy<T>(in, out, P->Np, P->stream));
+        } else if constexpr (std::is_same<T, double>::value) {
+            FSD_TRY(circ_precond(P, in, out, ctrl));
+        } else {
+            return fail(FSD_EINVAL, "the circulant preconditioners run in float64 only");
+        }
+        if (partials) HIP_TRY(vec_dot<T>(in, out, P->Np, partials, ctrl, nparts, P->stream));
+        return FSD_OK;
+    }
     Tables<T>& tb = tabs<T>(P);
     Vecs<T>& v = vecs<T>(P);
     const int last = P->dim - 1;
@@ -855,6 +956,7 @@ fsd_status fsd_default_params(fsd_params* p) {
     p->precision = FSD_PREC_FP64;
     p->dst_mfma = 0;
     p->reorth_eta2 = -1.0;
+    p->precond = FSD_PC_TAU;
     p->inner_tol = 1e-5;
     p->max_outer = 8;
     p->x0_mode = FSD_X0_PREV;
@@ -894,6 +996,12 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
         return fail(FSD_EINVAL, "inner_tol must be in (0, 1)");
     if (p->solver < 0 || p->solver > 3) return fail(FSD_EINVAL, "unknown solver");
     if (p->x0_mode < 0 || p->x0_mode > FSD_X0_GUARDED) return fail(FSD_EINVAL, "unknown x0_mode");
+    if (p->precond < FSD_PC_TAU || p->precond > FSD_PC_STRANG) return fail(FSD_EINVAL, "unknown precond");
+    const bool circ = p->precond == FSD_PC_TCHAN || p->precond == FSD_PC_STRANG;
+    if (circ && p->precision != FSD_PREC_FP64)
+        return fail(FSD_EINVAL, "the circulant preconditioners run in float64 only");
+    if (circ && p->solver == FSD_SOLVER_PGMRES2)
+        return fail(FSD_EINVAL, "two-sided GMRES needs P^{-1/2}: tau or no preconditioner");
 
     fsd_problem P = new (std::nothrow) fsd_problem_s();
     if (!P) return fail(FSD_EINVAL, "out of host memory");
@@ -902,9 +1010,11 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
     P->dim = p->dim;
     if (P->dim == 2) P->p.n[2] = 1;
     const double dt = p->T / p->M;
+    P->pc = p->precond;
     for (int i = 0; i < P->dim; ++i) {
         axis_setup(P->ax[i], p->n[i], p->a[i], p->b[i], p->delta[i], p->kplus[i], p->kminus[i], dt);
         axis_spectra(P->ax[i], i);
+        if (circ) axis_circulant(P->ax[i], p->precond);
     }
     P->symmetric = true;
     for (int i = 0; i < P->dim; ++i) P->symmetric &= (p->kplus[i] == p->kminus[i]);
@@ -961,6 +1071,16 @@ fsd_status fsd_bind(fsd_problem P, void* d_ws, size_t bytes, void* stream) {
     HIP_TRY(hipMemsetAsync(P->ws, 0, P->ws_bytes, P->stream));
     FSD_TRY(upload_all<double>(P, P->t64));
     if (P->mixed) FSD_TRY(upload_all<float>(P, P->t32));
+    if (P->zc) {
+        for (int i = 0; i < P->dim; ++i) {
+            const Axis& ax = P->ax[i];
+            FSD_TRY(upload_vec<double>(P, P->cw[i], ax.cw));
+            FSD_TRY(upload_vec<double>(P, P->cbsp[i], ax.cbsp));
+            FSD_TRY(upload_vec<double>(P, P->ctw[i], ax.ctw));
+            FSD_TRY(upload_vec<double>(P, P->cea[i], ax.ceA));
+            FSD_TRY(upload_vec<double>(P, P->ceb[i], ax.ceB));
+        }
+    }
     P->bound = true;
     P->have_hist = false;
     return FSD_OK;

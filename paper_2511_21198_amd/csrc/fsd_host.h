@@ -16,6 +16,12 @@ struct Axis {
     std::vector<double> aeig, lam;     // A_n and tau(H(T_n)) eigenvalues, k = 1..n
     std::vector<double> specA, specR;  // pass spectra for A and for the right-hand side
     std::vector<double> tw;            // twiddles exp(-2 pi i e/L), interleaved
+    // circulant comparators (FSD_PC_TCHAN / FSD_PC_STRANG), interleaved complex
+    int cM = 0, clog = 0;              // Bluestein FFT length (power of two >= 2n - 1), log2
+    std::vector<double> ceA, ceB;      // eigenvalues of C(A_n) and of eta C(B_n), n each
+    std::vector<double> cw;            // chirp exp(-i pi j^2 / n), j < n
+    std::vector<double> cbsp;          // M-point spectrum of the conjugated chirp, bit-reversed
+    std::vector<double> ctw;           // exp(-2 pi i k / M), k < M/2
 };
 
 // Records msg as the thread's last error (fsd_last_error) and returns s.
@@ -24,6 +30,7 @@ fsd_status set_error(fsd_status s, const std::string& msg);
 void q_coefficients(double delta, int n, std::vector<long double>& q);
 void axis_setup(Axis& ax, int n, double a, double b, double delta, double kp, double km, double dt);
 void axis_spectra(Axis& ax, int axis_index);
+void axis_circulant(Axis& ax, int kind);
 
 template <typename T>
 struct Tables {
@@ -99,6 +106,15 @@ struct fsd_problem_s {
     // 2 (b - A_N x) - dt F (resid_prev); taken once by first_residual
     bool r0_hint = false;
     const double* r0_F = nullptr;
+    // comparator preconditioners (fsd_precond): complex work vector (Np
+    // interleaved values) and per-axis tables of the circulant passes
+    int pc = FSD_PC_TAU;
+    double* zc = nullptr;
+    double* cw[3] = {nullptr, nullptr, nullptr};
+    double* cbsp[3] = {nullptr, nullptr, nullptr};
+    double* ctw[3] = {nullptr, nullptr, nullptr};
+    double* cea[3] = {nullptr, nullptr, nullptr};
+    double* ceb[3] = {nullptr, nullptr, nullptr};
 
     bool prof_on = false;
     std::vector<fsd::ProfRec> prof;

@@ -158,4 +158,115 @@ void axis_spectra(Axis& ax, int axis_index) {
     }
 }
 
+// ------------------------------------------------------------ circulant comparators
+// Section 4 compares the method with T. Chan's and Strang's circulant
+// preconditioners: every Toeplitz factor (A_n and B_n) is replaced by its
+// circulant approximation.  For a Toeplitz matrix with entries t_{j-k}
+// (textbook definitions, cited but not restated by the paper):
+//   T. Chan:  c_j = ((n - j) t_j + j t_{j-n}) / n   (nearest in Frobenius norm)
+//   Strang:   s_j = t_j for j <= n/2, t_{j-n} for j > n/2 (central diagonals)
+// A circulant with first column c has eigenvalues sum_j c_j e^{-2 pi i j k/n}
+// in the DFT basis.  The DFT of length n (odd for n = 2^a - 1) is taken by
+// Bluestein's chirp transform: X_k = w_k sum_j (x_j w_j) conj(w_{k-j}) with
+// w_j = e^{-i pi j^2 / n}, a convolution done by FFTs of a power-of-two
+// length M >= 2n - 1.
+static void circ_column(const std::vector<long double>& col, const std::vector<long double>& row,
+                        int kind, std::vector<long double>& c) {
+    const int n = (int)col.size();
+    c.assign(n, 0.0L);
+    for (int j = 0; j < n; ++j) {
+        const long double tp = col[j];                     // t_j
+        const long double tn = j > 0 ? row[n - j] : 0.0L;  // t_{j-n}
+        if (kind == FSD_PC_STRANG)
+            c[j] = j <= n / 2 ? tp : tn;
+        else
+            c[j] = ((long double)(n - j) * tp + (long double)j * tn) / (long double)n;
+    }
+}
+
+static void circ_eigs(const std::vector<long double>& c, long double scale, std::vector<double>& out) {
+    const int n = (int)c.size();
+    const long double tp = 2.0L * 3.14159265358979323846264338327950288L;
+    std::vector<long double> cs(n), sn(n);
+    for (int m = 0; m < n; ++m) {
+        cs[m] = cosl(tp * m / n);
+        sn[m] = sinl(tp * m / n);
+    }
+    out.assign(2 * (size_t)n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        long double re = 0.0L, im = 0.0L;
+        for (int j = 0; j < n; ++j) {
+            const int e = (int)(((long)j * k) % n);
+            re += c[j] * cs[e];
+            im -= c[j] * sn[e];
+        }
+        out[2 * k] = (double)(scale * re);
+        out[2 * k + 1] = (double)(scale * im);
+    }
+}
+
+static int bit_reverse(int k, int bits) {
+    int r = 0;
+    for (int b = 0; b < bits; ++b) r |= ((k >> b) & 1) << (bits - 1 - b);
+    return r;
+}
+
+void axis_circulant(Axis& ax, int kind) {
+    const int n = ax.n;
+    std::vector<long double> acol(n, 0.0L), arow(n, 0.0L);   // A_n = tridiag(1, 6, 1) / 8
+    acol[0] = arow[0] = 0.75L;
+    if (n >= 2) acol[1] = arow[1] = 0.125L;
+    std::vector<long double> bcol, brow, c;
+    b_col_row(ax, bcol, brow);
+    circ_column(acol, arow, kind, c);
+    circ_eigs(c, 1.0L, ax.ceA);
+    circ_column(bcol, brow, kind, c);
+    circ_eigs(c, (long double)ax.eta, ax.ceB);
+
+    int M = 2, lg = 1;
+    while (M < 2 * n - 1) { M <<= 1; ++lg; }
+    ax.cM = M;
+    ax.clog = lg;
+    const long double pi = 3.14159265358979323846264338327950288L;
+    std::vector<long double> wr(n), wi(n);
+    ax.cw.assign(2 * (size_t)n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        const long m = ((long)j * j) % (2L * n);   // e^{-i pi j^2/n} has period 2n in j^2
+        wr[j] = cosl(pi * m / n);
+        wi[j] = -sinl(pi * m / n);
+        ax.cw[2 * j] = (double)wr[j];
+        ax.cw[2 * j + 1] = (double)wi[j];
+    }
+    // b_m = conj(w_m) for |m| < n, wrapped to length M
+    std::vector<long double> br(M, 0.0L), bi(M, 0.0L);
+    for (int m = 0; m < n; ++m) {
+        br[m] = wr[m];
+        bi[m] = -wi[m];
+        if (m > 0) { br[M - m] = wr[m]; bi[M - m] = -wi[m]; }
+    }
+    std::vector<long double> cm(M), sm(M);
+    for (int e = 0; e < M; ++e) {
+        cm[e] = cosl(2.0L * pi * e / M);
+        sm[e] = sinl(2.0L * pi * e / M);
+    }
+    ax.cbsp.assign(2 * (size_t)M, 0.0);
+    for (int k = 0; k < M; ++k) {
+        long double re = 0.0L, im = 0.0L;
+        for (int m = 0; m < M; ++m) {
+            if (br[m] == 0.0L && bi[m] == 0.0L) continue;
+            const int e = (int)(((long)m * k) % M);
+            re += br[m] * cm[e] + bi[m] * sm[e];
+            im += bi[m] * cm[e] - br[m] * sm[e];
+        }
+        const int p = bit_reverse(k, lg);
+        ax.cbsp[2 * p] = (double)re;
+        ax.cbsp[2 * p + 1] = (double)im;
+    }
+    ax.ctw.assign((size_t)M, 0.0);   // M/2 complex
+    for (int k = 0; k < M / 2; ++k) {
+        ax.ctw[2 * k] = (double)cm[k];
+        ax.ctw[2 * k + 1] = (double)(-sm[k]);
+    }
+}
+
 }  // namespace fsd

@@ -42,7 +42,8 @@ _SOURCES = {"toep": _LINE_SRC, "dst": _LINE_SRC, "dsts": _LINE_SRC,
             "gm": ["fsd_internal.h", "fsd_gmres.h", "fsd_gmres.hip"],
             "pcg": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
             "cast": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
-            "resid": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"]}
+            "resid": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
+            "circ": ["fsd_internal.h", "fsd_circ.h", "fsd_circ.hip"]}
 
 
 def source_hash(kind: str | None = None) -> str:
@@ -76,6 +77,7 @@ _KINDS = [
     (re.compile(r"k_update_xr\b"), "pcg_update"),
     (re.compile(r"k_cast\b"), "cast"),
     (re.compile(r"k_resid_prev\b"), "resid_prev_f64"),
+    (re.compile(r"k_circ\b"), "circ_f64"),
 ]
 
 
@@ -108,7 +110,7 @@ def classify(rows, dim=3):
         if kind.startswith("toep"):
             last_toep = kind
         dt = _dtype(name)
-        out.append(f"{kind}_{dt}" if dt and kind not in ("cast", "resid_prev_f64") else kind)
+        out.append(f"{kind}_{dt}" if dt and kind not in ("cast", "resid_prev_f64", "circ_f64") else kind)
     return out
 
 

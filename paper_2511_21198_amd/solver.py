@@ -30,7 +30,7 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
                 restart: int = 20, tol: float = 1e-9, maxit: int = 0, precision: str = "fp64",
                 inner_tol: float = 1e-5, max_outer: int = 8, x0: str = "prev", domain=None,
                 allow_delta_zero: bool = False, dst_mfma: bool = False,
-                reorth_eta2: Optional[float] = None) -> nat.Params:
+                reorth_eta2: Optional[float] = None, precond: str = "tau") -> nat.Params:
     """fsd_params from keyword arguments (defaults from fsd_default_params)."""
     p = nat.Params()
     check(lib.fsd_default_params(C.byref(p)), "fsd_default_params")
@@ -57,6 +57,8 @@ def make_params(dim: int, n: Sequence[int], delta: Sequence[float], kplus: Seque
     p.allow_delta_zero = int(allow_delta_zero)
     p.dst_mfma = int(dst_mfma)
     p.reorth_eta2 = -1.0 if reorth_eta2 is None else float(reorth_eta2)
+    p.precond = {"tau": nat.PC_TAU, "none": nat.PC_NONE, "tchan": nat.PC_TCHAN,
+                 "strang": nat.PC_STRANG}[precond]
     return p
 
 
@@ -70,9 +72,10 @@ class Problem:
                  x0: str = "prev", domain=None, allow_delta_zero: bool = False,
                  dst_mfma: bool = False, reorth_eta2: Optional[float] = None,
                  device: Optional[torch.device] = None,
-                 stream: Optional[torch.cuda.Stream] = None):
+                 stream: Optional[torch.cuda.Stream] = None, precond: str = "tau"):
         p = make_params(dim, n, delta, kplus, kminus, M, T, solver, restart, tol, maxit, precision,
-                        inner_tol, max_outer, x0, domain, allow_delta_zero, dst_mfma, reorth_eta2)
+                        inner_tol, max_outer, x0, domain, allow_delta_zero, dst_mfma, reorth_eta2,
+                        precond)
         self.params = p
         self.dim = dim
         self.n = tuple(int(v) for v in n[:dim])

@@ -43,9 +43,10 @@ def test_header_symbols_exported(nat):
 def test_struct_sizes(nat):
     # fsd_params / fsd_stats as laid out by the C compiler (x86-64 SysV)
     # dim, n[3], 5 double[3], M, (pad), T, solver, restart, tol, maxit, precision,
-    # (pad), inner_tol, max_outer, x0_mode, allow_delta_zero, dst_mfma, reorth_eta2
+    # (pad), inner_tol, max_outer, x0_mode, allow_delta_zero, dst_mfma, reorth_eta2,
+    # precond, (pad)
     assert C.sizeof(nat.Params) == (4 + 12 + 5 * 24 + 4 + 4 + 8 + 4 + 4 + 8 + 8 + 4 + 4 + 8 + 4 + 4
-                                    + 4 + 4 + 8)
+                                    + 4 + 4 + 8 + 4 + 4)
     assert C.sizeof(nat.Stats) == 40
 
 
