@@ -42,7 +42,7 @@ struct CircArgs {
 };
 
 // Workgroup shape of a pass with FFT length M: lines per workgroup (the
-// LDS holds lpb * M complex values, at most 64 KiB).
+// LDS holds lpb * M <= 2048 complex line values and the M/2 twiddles).
 int circ_lines_per_block(int M);
 
 hipError_t launch_circ(const CircArgs& a, hipStream_t s);

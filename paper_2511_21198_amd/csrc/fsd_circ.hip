@@ -19,7 +19,7 @@ namespace fsd {
 namespace {
 
 constexpr int CT = 256;
-constexpr int kCircLds = 4096;   // complex values of LDS per workgroup (64 KiB)
+constexpr int kCircLds = 2048;   // complex line values per workgroup (32 KiB; four workgroups per CU)
 
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -34,35 +34,75 @@ __device__ inline long line_base(const CircArgs& a, long l) {
     return (l / a.nx) * a.os + (l % a.nx) * a.xs;
 }
 
-// buf: lpb lines of M values holding the chirped input (zero beyond n).
-// Leaves M times the cyclic convolution with the conjugated chirp, natural
-// order.
-__device__ void bluestein_conv(double2* buf, const CircArgs& a) {
+// buf: lpb lines of M values holding the chirped input (zero beyond n);
+// tw: the M/2 twiddles, staged in LDS.  Leaves M times the cyclic
+// convolution with the conjugated chirp, natural order.  Two radix-2 stages
+// are taken per pass over LDS: the four values j, j + q, j + h, j + h + q
+// (decimation in frequency, half sizes h and q = h/2) or j, j + h, j + 2h,
+// j + 3h (decimation in time, half sizes h and 2h) are closed under both
+// stages, so a thread applies both in registers with the same operations
+// as two radix-2 passes; an odd number of stages leaves one radix-2 pass.
+__device__ void bluestein_conv(double2* buf, const double2* tw, const CircArgs& a) {
     const int M = a.M, H = M >> 1, logH = a.logM - 1;
-    const int nb = a.lpb * H;
-    // forward, decimation in frequency: half size h, twiddle step M / (2h)
-    for (int h = H, lh = logH, ts = 1; h >= 1; h >>= 1, --lh, ts <<= 1) {
-        for (int b = threadIdx.x; b < nb; b += CT) {
-            const int li = b >> logH, r = b & (H - 1);
-            const int g = r >> lh, k = r & (h - 1);
-            const int i0 = li * M + 2 * g * h + k, i1 = i0 + h;
-            const double2 u = buf[i0], v = buf[i1];
+    const int Q = M >> 2, nq = a.lpb * Q;
+    // forward, decimation in frequency: half sizes h, h/2; twiddle step M / (2h)
+    int h = H, lh = logH, ts = 1;
+    for (; h >= 2; h >>= 2, lh -= 2, ts <<= 2) {
+        const int q = h >> 1, lq = lh - 1;
+        for (int b = threadIdx.x; b < nq; b += CT) {
+            const int li = b >> (a.logM - 2), r = b & (Q - 1);
+            const int g = r >> lq, k = r & (q - 1);
+            const int i0 = li * M + 2 * g * h + k;
+            const double2 x0 = buf[i0], x1 = buf[i0 + q], x2 = buf[i0 + h], x3 = buf[i0 + h + q];
+            const double2 a0 = cadd(x0, x2), a2 = cmul(csub(x0, x2), tw[k * ts]);
+            const double2 a1 = cadd(x1, x3), a3 = cmul(csub(x1, x3), tw[(k + q) * ts]);
+            const double2 t = tw[k * 2 * ts];
+            buf[i0] = cadd(a0, a1);
+            buf[i0 + q] = cmul(csub(a0, a1), t);
+            buf[i0 + h] = cadd(a2, a3);
+            buf[i0 + h + q] = cmul(csub(a2, a3), t);
+        }
+        __syncthreads();
+    }
+    if (h == 1) {   // last stage, twiddle 1
+        for (int b = threadIdx.x; b < a.lpb * H; b += CT) {
+            const int i0 = 2 * b;   // lines are contiguous: pair (2b, 2b + 1)
+            const double2 u = buf[i0], v = buf[i0 + 1];
             buf[i0] = cadd(u, v);
-            buf[i1] = cmul(csub(u, v), a.tw[k * ts]);
+            buf[i0 + 1] = csub(u, v);
         }
         __syncthreads();
     }
     for (int e = threadIdx.x; e < a.lpb * M; e += CT) buf[e] = cmul(buf[e], a.bsp[e & (M - 1)]);
     __syncthreads();
-    // inverse, decimation in time with conjugate twiddles
-    for (int h = 1, lh = 0, ts = H; h < M; h <<= 1, ++lh, ts >>= 1) {
-        for (int b = threadIdx.x; b < nb; b += CT) {
-            const int li = b >> logH, r = b & (H - 1);
+    // inverse, decimation in time with conjugate twiddles: half sizes h, 2h
+    h = 1;
+    lh = 0;
+    ts = H;
+    for (; 2 * h < M; h <<= 2, lh += 2, ts >>= 2) {
+        for (int b = threadIdx.x; b < nq; b += CT) {
+            const int li = b >> (a.logM - 2), r = b & (Q - 1);
             const int g = r >> lh, k = r & (h - 1);
-            const int i0 = li * M + 2 * g * h + k, i1 = i0 + h;
-            const double2 u = buf[i0], v = cmulc(buf[i1], a.tw[k * ts]);
+            const int i0 = li * M + 4 * g * h + k;
+            const double2 x0 = buf[i0], x1 = buf[i0 + h], x2 = buf[i0 + 2 * h], x3 = buf[i0 + 3 * h];
+            const double2 t = tw[k * ts];
+            const double2 v1 = cmulc(x1, t), v3 = cmulc(x3, t);
+            const double2 a0 = cadd(x0, v1), a1 = csub(x0, v1), a2 = cadd(x2, v3), a3 = csub(x2, v3);
+            const double2 u2 = cmulc(a2, tw[k * (ts >> 1)]), u3 = cmulc(a3, tw[(k + h) * (ts >> 1)]);
+            buf[i0] = cadd(a0, u2);
+            buf[i0 + 2 * h] = csub(a0, u2);
+            buf[i0 + h] = cadd(a1, u3);
+            buf[i0 + 3 * h] = csub(a1, u3);
+        }
+        __syncthreads();
+    }
+    if (h < M) {    // last stage, half size M/2
+        for (int b = threadIdx.x; b < a.lpb * H; b += CT) {
+            const int li = b >> logH, k = b & (H - 1);
+            const int i0 = li * M + k;
+            const double2 u = buf[i0], v = cmulc(buf[i0 + H], tw[k]);
             buf[i0] = cadd(u, v);
-            buf[i1] = csub(u, v);
+            buf[i0 + H] = csub(u, v);
         }
         __syncthreads();
     }
@@ -81,9 +121,12 @@ __device__ inline void item(const CircArgs& a, int e, int span, int& li, int& j)
 }
 
 __global__ __launch_bounds__(CT) void k_circ(CircArgs a) {
-    extern __shared__ double2 buf[];
+    extern __shared__ double2 lds[];
     if (a.ctrl && a.ctrl->done) return;
     const int M = a.M, n = a.n, lpb = a.lpb;
+    double2* tw = lds;             // M/2 twiddles
+    double2* buf = lds + M / 2;    // lpb lines of M values
+    for (int e = threadIdx.x; e < M / 2; e += CT) tw[e] = a.tw[e];
     const long l0 = (long)blockIdx.x * lpb;
     const int nl = (int)min((long)lpb, a.nlines - l0);
     const bool inv_in = a.mode == CM_INV || a.mode == CM_INV_C2R;
@@ -102,7 +145,7 @@ __global__ __launch_bounds__(CT) void k_circ(CircArgs a) {
         buf[li * M + j] = v;
     }
     __syncthreads();
-    bluestein_conv(buf, a);
+    bluestein_conv(buf, tw, a);
     const double sM = 1.0 / M;
 
     if (a.mode == CM_LAST) {
@@ -138,7 +181,7 @@ __global__ __launch_bounds__(CT) void k_circ(CircArgs a) {
             buf[e] = v;
         }
         __syncthreads();
-        bluestein_conv(buf, a);
+        bluestein_conv(buf, tw, a);
     }
 
     const double sc = inv_out ? sM / n : sM;
@@ -178,7 +221,7 @@ hipError_t launch_circ(const CircArgs& a, hipStream_t s) {
     if (a.mode == CM_INV_C2R && a.pad > a.n && a.st != 1) return hipErrorInvalidValue;
     if (a.nlines <= 0) return hipSuccess;
     const long g = (a.nlines + a.lpb - 1) / a.lpb;
-    const size_t lds = (size_t)a.lpb * a.M * sizeof(double2);
+    const size_t lds = ((size_t)a.lpb * a.M + a.M / 2) * sizeof(double2);
     hipLaunchKernelGGL(k_circ, dim3((unsigned)g), dim3(CT), lds, s, a);
     return hipGetLastError();
 }
