@@ -414,6 +414,8 @@ def main(argv=None):
                     help="skip the 64-instance batched workload")
     ap.add_argument("--only-batched", action="store_true",
                     help="run only the batched workload and print its JSON")
+    ap.add_argument("--only-comparators", action="store_true",
+                    help="run only the comparator preconditioners and print their JSON")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not "
@@ -433,6 +435,10 @@ def main(argv=None):
         print(json.dumps(batched_workload(a)), flush=True)
         return 0
     w = workloads.config_3d_nonsymmetric(seed=0, n=a.n, M=16)
+    if a.only_comparators:
+        F = torch.from_numpy(w.F).cuda()
+        print(json.dumps(comparators(w, F, torch.zeros_like(F))), flush=True)
+        return 0
     dev = torch.device("cuda:0")
     F = torch.from_numpy(w.F).to(dev)
     u0 = torch.zeros_like(F)

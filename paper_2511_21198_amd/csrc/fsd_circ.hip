@@ -127,7 +127,13 @@ __global__ __launch_bounds__(CT) void k_circ(CircArgs a) {
     double2* tw = lds;             // M/2 twiddles
     double2* buf = lds + M / 2;    // lpb lines of M values
     for (int e = threadIdx.x; e < M / 2; e += CT) tw[e] = a.tw[e];
-    const long l0 = (long)blockIdx.x * lpb;
+    // Workgroups go to the 8 XCDs in turn; give each XCD one contiguous run
+    // of tiles, so that neighbouring tiles (which share 128-byte lines in
+    // the strided passes) meet in one L2.  A bijection on [0, gridDim.x).
+    const int nbk = (int)gridDim.x, xq = nbk / 8, xr = nbk % 8;
+    const int xcd = (int)blockIdx.x % 8, xi = (int)blockIdx.x / 8;
+    const int tile = xcd * xq + min(xcd, xr) + xi;
+    const long l0 = (long)tile * lpb;
     const int nl = (int)min((long)lpb, a.nlines - l0);
     const bool inv_in = a.mode == CM_INV || a.mode == CM_INV_C2R;
     const bool inv_out = a.mode != CM_FWD_R2C && a.mode != CM_FWD;

@@ -124,7 +124,8 @@ def _read(path_dir, pattern):
     return rows
 
 
-def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.0, dim=3):
+def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.0, dim=3,
+              scale_from=None):
     tr = _read(trace_dir, "*kernel_trace.csv")
     kinds = classify(tr, dim)
     dur = collections.defaultdict(list)
@@ -154,6 +155,8 @@ def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.
         if "cast" in per and np_len:
             expect = (8.0 if label == "fetch" else 4.0) * np_len
             factors[label] = expect / (sum(per["cast"]) / len(per["cast"]))
+        elif scale_from and label in scale_from:
+            factors[label] = scale_from[label]
         f = factors.get(label, 1.0)
         for k, v in per.items():
             if k in res:
@@ -198,8 +201,14 @@ def main(argv=None):
     ap.add_argument("--md")
     ap.add_argument("--cmd", default="", help="the profiled command, recorded in the outputs")
     ap.add_argument("--title", default="")
+    ap.add_argument("--scale-from", help="summary JSON whose k_cast counter scale factors to use "
+                                         "when this run launched no k_cast")
     a = ap.parse_args(argv)
-    res, factors = summarise(a.trace, a.fetch, a.write, a.np, a.skip_us, a.dim)
+    scale_from = None
+    if a.scale_from:
+        with open(a.scale_from) as f:
+            scale_from = json.load(f).get("counter_scale")
+    res, factors = summarise(a.trace, a.fetch, a.write, a.np, a.skip_us, a.dim, scale_from)
     doc = {"command": a.cmd, "source_hash": source_hash(), "np": a.np,
            "counter_scale": factors, "kinds": res}
     if a.json:
@@ -210,7 +219,8 @@ def main(argv=None):
         lines += [f"# {a.title}", ""]
     lines += ["Command:", "", "```", a.cmd, "```", "",
               f"Library source hash: `{doc['source_hash']}`.  Counter scale factors "
-              f"(k_cast calibration, {a.np} elements): "
+              + (f"(k_cast calibration, {a.np} elements): " if not scale_from else
+                 f"(k_cast calibration taken from `{a.scale_from}`): ")
               + ", ".join(f"{k} x{v:.4f}" for k, v in factors.items()), "",
               f"Dispatches shorter than {a.skip_us:g} us (enqueued after the solve had "
               "stopped; they return at once) are listed as skipped and excluded.", "",
