@@ -66,6 +66,20 @@ def ex42_source(x, y, z, t, delta, kp, km):
                                    + X * Y * flux_derivative(z, delta[2], kp[2], km[2])))
 
 
+def ex42_source_parts(x, y, z, delta, kp, km):
+    """(P, D) with f = cos(t+1) P - sin(t+1) D for Example 4.2: the source
+    separates into two functions of space, so its cell averages at every
+    step are two fixed grids combined with cos(t+1) and sin(t+1) (the cell
+    average is linear).  Example 4.1's source is e^t times its value at
+    t = 0 in the same way."""
+    X, Y, Z = profile(x), profile(y), profile(z)
+    P = X * Y * Z
+    D = (Y * Z * flux_derivative(x, delta[0], kp[0], km[0])
+         + X * Z * flux_derivative(y, delta[1], kp[1], km[1])
+         + X * Y * flux_derivative(z, delta[2], kp[2], km[2]))
+    return P, D
+
+
 def ex41_source_printed(x, y, t, delta, kp, km):
     """The source of Example 4.1 in the paper's own form (binomial sum over
     k = 0..2 of Gamma(5-k)/Gamma(3-k+alpha) times the two one-sided powers);

@@ -310,3 +310,56 @@ def test_first_residual_from_prev(fsd, case, precision):
     assert st["iters"] == 0 and st["converged"] == 1
     assert np.array_equal(host(out), u)
     assert abs(st["relres"] - ref) <= 1e-12 * ref
+
+
+def _beyond_rows():
+    """The paper's (table, orders) families with the printed count at its
+    largest grid, run one size further: 2D n + 1 = 1024 (M = 128 by the
+    tables' M = (n+1)/8), 3D n + 1 = 128 (M = 64 by M = (n+1)/2)."""
+    rows = json.load(open(os.path.join(GOLDEN, "paper_iterations.json")))["rows"]
+    out = []
+    for tab, dim, orders, M, n1, it in rows:
+        if (dim == 2 and n1 == 512) or (dim == 3 and n1 == 64):
+            out.append((tab, dim, tuple(orders), 2 * M, 2 * n1, it))
+    return out
+
+
+@pytest.mark.parametrize("row", _beyond_rows(), ids=lambda r: f"T{r[0]}-{r[4]}-{'_'.join(map(str, r[2]))}")
+def test_mesh_independence_beyond_paper_sizes(fsd, row):
+    """The tau-preconditioned solvers in the replication setting one grid
+    beyond the paper's largest (1023^2 and 127^3, all M steps): the average
+    count stays within one of the printed count at 511^2 / 63^3 (the
+    iteration bounds of Theorems 3.1-3.3 do not depend on N).  The sources
+    are the examples' cell averages, formed once per grid from their
+    separation in time (``ex42_source_parts``)."""
+    import math
+    tab, dim, orders, M, n1, printed = row
+    sym = tab in (1, 3)
+    kp = [5.0] * dim if sym else [19.0, 21.0, 23.0][:dim]
+    km = [5.0] * dim if sym else [21.0, 23.0, 25.0][:dim]
+    n = [n1 - 1] * dim
+    prob = fsd(dim, n, list(orders), kp, km, M=M, T=1.0, tol=1e-9, x0="zero", restart=20,
+               maxit=(n1 - 1) ** 3)
+    orc = op.Problem(dim, n, list(orders), kp, km, T=1.0, M=M)
+    h = orc.h
+    if dim == 2:
+        G = dev(ex.cell_average(lambda X, Y: ex.ex41_source(X, Y, 0.0, orc.delta, kp, km), orc.n, h))
+        Fm = lambda m: math.exp((m - 0.5) * orc.dt) * G
+        u0 = ex.nodal(lambda X, Y: ex.ex41_exact(X, Y, 0.0), orc.n, h)
+    else:
+        P = dev(ex.cell_average(lambda X, Y, Z: ex.ex42_source_parts(X, Y, Z, orc.delta, kp, km)[0],
+                                orc.n, h))
+        D = dev(ex.cell_average(lambda X, Y, Z: ex.ex42_source_parts(X, Y, Z, orc.delta, kp, km)[1],
+                                orc.n, h))
+        Fm = lambda m: (math.cos((m - 0.5) * orc.dt + 1.0) * P
+                        - math.sin((m - 0.5) * orc.dt + 1.0) * D)
+        u0 = ex.nodal(lambda X, Y, Z: ex.ex42_exact(X, Y, Z, 0.0), orc.n, h)
+    u = dev(u0)
+    its = []
+    for m in range(1, M + 1):
+        u, st = prob.cn_step(u, Fm(m))
+        assert st["converged"] == 1
+        its.append(st["iters"])
+    avg = float(np.mean(its))
+    print(f"beyond: table {tab} orders {orders} n+1 = {n1}: {avg:.2f} (printed at n+1 = {n1 // 2}: {printed})")
+    assert avg <= printed + 1.0, (its, printed)

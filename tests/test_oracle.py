@@ -552,3 +552,19 @@ def test_paper_comparator_counts_mostly_exact():
     rows = _comparator_rows()
     exact = sum(1 for r in rows if _comparator_total(r)[0] == _comparator_total(r)[1])
     assert exact >= int(0.85 * len(rows)), (exact, len(rows))
+
+
+def test_example_sources_separate_in_time():
+    """Example 4.1's source is e^t f(x, y, 0); Example 4.2's is
+    cos(t+1) P - sin(t+1) D with (P, D) from ex42_source_parts, at random
+    points and times (the form the large-grid GPU runs use)."""
+    rng = np.random.default_rng(5)
+    x, y, z = (rng.uniform(0.01, 0.99, 200) for _ in range(3))
+    d, kp, km = [0.1, 0.5, 0.9], [19.0, 21.0, 23.0], [21.0, 23.0, 25.0]
+    P, D = ex.ex42_source_parts(x, y, z, d, kp, km)
+    for t in (0.0, 0.3, 1.0):
+        f2 = ex.ex41_source(x, y, t, d, kp, km)
+        assert np.allclose(f2, math.exp(t) * ex.ex41_source(x, y, 0.0, d, kp, km), rtol=1e-14, atol=0)
+        f3 = ex.ex42_source(x, y, z, t, d, kp, km)
+        g3 = math.cos(t + 1.0) * P - math.sin(t + 1.0) * D
+        assert np.abs(f3 - g3).max() <= 1e-14 * np.abs(f3).max()
