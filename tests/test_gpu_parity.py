@@ -363,3 +363,52 @@ def test_mesh_independence_beyond_paper_sizes(fsd, row):
     avg = float(np.mean(its))
     print(f"beyond: table {tab} orders {orders} n+1 = {n1}: {avg:.2f} (printed at n+1 = {n1 // 2}: {printed})")
     assert avg <= printed + 1.0, (its, printed)
+
+
+@pytest.mark.parametrize("dim,orders,sym", [
+    (2, (0.4, 0.5), True), (2, (0.8, 0.9), False), (3, (0.4, 0.5, 0.6), True), (3, (0.1, 0.5, 0.9), False),
+], ids=lambda v: str(v))
+def test_second_order_convergence_gpu(fsd, dim, orders, sym):
+    """Remark 2.1 on the GPU at grids the oracle cannot reach: the max
+    relative error of the manufactured solutions at T = 1 (dt = 4h) drops
+    about 4x per halving of h and dt, up to 1023^2 and 127^3 (float64,
+    tol 1e-12).  The errors fall monotonically; the finest pair (and in 2D
+    every pair) is in the second-order range.  The coarse 3D grids are not
+    yet asymptotic (measured ratios 2.0, 3.3, 4.0 for (0.4, 0.5, 0.6) and
+    1.7, 2.0, 3.2 for the non-symmetric (0.1, 0.5, 0.9) from n + 1 = 16)."""
+    import math
+    kp = [5.0] * dim if sym else [19.0, 21.0, 23.0][:dim]
+    km = [5.0] * dim if sym else [21.0, 23.0, 25.0][:dim]
+    sizes = (64, 128, 256, 512, 1024) if dim == 2 else (16, 32, 64, 128)
+    errs = []
+    for n1 in sizes:
+        M = n1 // 4
+        n = [n1 - 1] * dim
+        prob = fsd(dim, n, list(orders), kp, km, M=M, T=1.0, tol=1e-12, x0="prev")
+        orc = op.Problem(dim, n, list(orders), kp, km, T=1.0, M=M)
+        h = orc.h
+        if dim == 2:
+            G = dev(ex.cell_average(lambda X, Y: ex.ex41_source(X, Y, 0.0, orc.delta, kp, km), orc.n, h))
+            Fm = lambda m: math.exp((m - 0.5) * orc.dt) * G
+            u0 = ex.nodal(lambda X, Y: ex.ex41_exact(X, Y, 0.0), orc.n, h)
+            ue = ex.nodal(lambda X, Y: ex.ex41_exact(X, Y, 1.0), orc.n, h)
+        else:
+            P = dev(ex.cell_average(lambda X, Y, Z: ex.ex42_source_parts(X, Y, Z, orc.delta, kp, km)[0],
+                                    orc.n, h))
+            D = dev(ex.cell_average(lambda X, Y, Z: ex.ex42_source_parts(X, Y, Z, orc.delta, kp, km)[1],
+                                    orc.n, h))
+            Fm = lambda m: (math.cos((m - 0.5) * orc.dt + 1.0) * P
+                            - math.sin((m - 0.5) * orc.dt + 1.0) * D)
+            u0 = ex.nodal(lambda X, Y, Z: ex.ex42_exact(X, Y, Z, 0.0), orc.n, h)
+            ue = ex.nodal(lambda X, Y, Z: ex.ex42_exact(X, Y, Z, 1.0), orc.n, h)
+        u = dev(u0)
+        for m in range(1, M + 1):
+            u, st = prob.cn_step(u, Fm(m))
+            assert st["converged"] == 1
+        errs.append(float(np.abs(host(u) - ue).max() / np.abs(ue).max()))
+    ratios = [errs[i] / errs[i + 1] for i in range(len(errs) - 1)]
+    print(f"order: dim {dim} orders {orders} errors {['%.3e' % e for e in errs]} ratios "
+          f"{['%.2f' % r for r in ratios]}")
+    assert all(r > 1.0 for r in ratios), (errs, ratios)
+    checked = ratios if dim == 2 else ratios[-1:]
+    assert all(3.0 < r < 5.5 for r in checked), (errs, ratios)
