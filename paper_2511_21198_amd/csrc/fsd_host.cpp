@@ -758,6 +758,28 @@ fsd_status norm2(fsd_problem P, const double* b, double* nrm) {
     return FSD_OK;
 }
 
+// ||b||, ||r|| with r = b - A x written to r, and (with pb) ||pb||, read
+// with one host synchronisation: the start of the mixed-precision loop.
+fsd_status start_norms(fsd_problem P, const double* x, const double* b, double* r, const double* pb,
+                       double* bnorm, double* rnorm, double* pbnorm) {
+    hipStream_t s = P->stream;
+    int np = 0;
+    HIP_TRY(ctrl_init(P->ctrl, 0.0, 1, P->restart, s));
+    HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_BB, s));
+    if (pb) {
+        HIP_TRY(vec_dot<double>(pb, pb, P->Np, P->partials, nullptr, &np, s));
+        HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RZ, s));
+    }
+    FSD_TRY(first_residual<double>(P, x, b, r, nullptr, &np));
+    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
+    FSD_TRY(read_ctrl(P));
+    *bnorm = std::sqrt(P->h_ctrl->bb);
+    *rnorm = std::sqrt(P->h_ctrl->pq);
+    if (pb) *pbnorm = std::sqrt(P->h_ctrl->rz);
+    return FSD_OK;
+}
+
 // Solve A x = b on the internal padded vectors (x, b float64).
 fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zero, fsd_stats* st) {
     const double tol = P->p.tol;
@@ -791,14 +813,13 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         int outer = 0;
         int status = FSD_ENOTCONV;
         double relres = 0.0, bnorm = 0.0, pbnorm = 0.0, prec_rel = 0.0;
-        FSD_TRY(norm2(P, b, &bnorm));
-        if (left) {
-            FSD_TRY(op_precond<double>(P, b, P->v64.z, nullptr, nullptr, nullptr, split));
-            FSD_TRY(norm2(P, P->v64.z, &pbnorm));
-        }
-        for (;;) {
+        if (left) FSD_TRY(op_precond<double>(P, b, P->v64.z, nullptr, nullptr, nullptr, split));
+        for (bool start = true;; start = false) {
             double rnorm = 0.0;
-            FSD_TRY(true_residual(P, x, b, r, &rnorm));
+            if (start)
+                FSD_TRY(start_norms(P, x, b, r, left ? P->v64.z : nullptr, &bnorm, &rnorm, &pbnorm));
+            else
+                FSD_TRY(true_residual(P, x, b, r, &rnorm));
             relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
             if (!std::isfinite(relres)) { status = FSD_ENONFINITE; break; }
             if (rnorm == 0.0 || (!left && relres <= tol)) { status = FSD_OK; break; }

@@ -18,6 +18,8 @@ enum ScalarOp : int {
     SC_CHECK = 4,  // rr = S, iters += 1, done if rr <= thresh or iters >= maxit
     SC_BETA = 5,   // beta = S / rz, rz = S, first = 0
     SC_STORE = 6,  // pq = S (plain reduction result for the host)
+    SC_STORE_BB = 7,  // bb = S (a second plain result, read with the first)
+    SC_STORE_RZ = 8,  // rz = S (a third one)
 };
 
 int vec_grid(long N);

@@ -76,12 +76,12 @@ __global__ __launch_bounds__(VT) void k_dot(const T* __restrict__ a, const T* __
 // 2D, A_N = A_{n2} (x) A_{n1}) instead of a Toeplitz matvec.  Padded layout
 // [n3][n2][P1] (n3 = 1 in 2D); F dense [n3][n2][n1] (may be null: f = 0);
 // padding columns of r are written as zeros.  Partial ||r||^2.
-// One wave owns a tile of 64 columns x kRpY rows x kRpZ planes and marches
+// One wave owns a tile of 64 columns x kRpY rows x rz planes and marches
 // through its planes, keeping the (y, x)-filtered values of three
 // consecutive planes in registers; the x neighbours are two more loads of
 // the same cache lines.  u is read once from HBM (the halo rows and planes
 // of a tile come from the caches), b and F once, r written once.
-constexpr int kRpY = 8, kRpZ = 8;
+constexpr int kRpY = 8, kRpZ = 8;   // rows per tile; planes per tile at most (rz <= kRpZ)
 
 // s[i] = (A_{n2} (x) A_{n1} u)(y0 + i) on plane zz (zero outside the grid).
 // Loads are branch-free: indices are clamped into the grid and values
@@ -111,18 +111,18 @@ __device__ inline void resid_plane(const double* __restrict__ u, int xl, int xm,
 __global__ __launch_bounds__(VT) void k_resid_prev(const double* __restrict__ u,
                                                    const double* __restrict__ b,
                                                    const double* __restrict__ F, double* __restrict__ r,
-                                                   int n1, int n2, int n3, int P1, int dim, double dt,
-                                                   double* __restrict__ partials) {
+                                                   int n1, int n2, int n3, int P1, int dim, int rz,
+                                                   double dt, double* __restrict__ partials) {
     __shared__ double sb[VT / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int nxc = (P1 + 63) / 64, nyc = (n2 + kRpY - 1) / kRpY, nzc = (n3 + kRpZ - 1) / kRpZ;
+    const int nxc = (P1 + 63) / 64, nyc = (n2 + kRpY - 1) / kRpY, nzc = (n3 + rz - 1) / rz;
     const long nwt = (long)nxc * nyc * nzc;
     const double wc = dim == 2 ? 1.0 : 0.75;   // 2D: no z factor (planes -1 and 1 are empty)
     double acc = 0.0;
     for (long t = (long)blockIdx.x * (VT / 64) + wid; t < nwt; t += (long)gridDim.x * (VT / 64)) {
         const int xc = (int)(t % nxc);
         const long t2 = t / nxc;
-        const int y0 = (int)(t2 % nyc) * kRpY, z0 = (int)(t2 / nyc) * kRpZ;
+        const int y0 = (int)(t2 % nyc) * kRpY, z0 = (int)(t2 / nyc) * rz;
         const int x = xc * 64 + lane;
         const bool inx = x < n1, inp = x < P1;
         // clamped columns: every load stays inside the row
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(VT) void k_resid_prev(const double* __restrict__ u,
         double sm[kRpY], sc[kRpY], sp[kRpY];
         resid_plane(u, xl, xm, xp, inx, hasm, hasp, n2, n3, P1, y0, z0 - 1, sm);
         resid_plane(u, xl, xm, xp, inx, hasm, hasp, n2, n3, P1, y0, z0, sc);
-        for (int k = 0; k < kRpZ && z0 + k < n3; ++k) {
+        for (int k = 0; k < rz && z0 + k < n3; ++k) {
             const int z = z0 + k;
             resid_plane(u, xl, xm, xp, inx, hasm, hasp, n2, n3, P1, y0, z + 1, sp);
 #pragma unroll
@@ -277,6 +277,12 @@ __global__ __launch_bounds__(VT) void k_scalar(Ctrl* c, const double* __restrict
         case SC_STORE:
             c->pq = S;
             break;
+        case SC_STORE_BB:
+            c->bb = S;
+            break;
+        case SC_STORE_RZ:
+            c->rz = S;
+            break;
         default:
             break;
     }
@@ -322,10 +328,15 @@ hipError_t vec_update_xr(T* x, T* r, const T* p, const T* q, long N, const Ctrl*
 hipError_t resid_prev(const double* u, const double* b, const double* F, double* r, int n1, int n2,
                       int n3, int P1, int dim, double dt, double* partials, int* nparts,
                       hipStream_t s) {
-    const long nwt = (long)((P1 + 63) / 64) * ((n2 + kRpY - 1) / kRpY) * ((n3 + kRpZ - 1) / kRpZ);
+    // planes per tile: 8, halved while the grid has fewer than 2048 wave
+    // tiles (small grids would leave most of the chip idle)
+    const long nxy = (long)((P1 + 63) / 64) * ((n2 + kRpY - 1) / kRpY);
+    int rz = kRpZ;
+    while (rz > 1 && nxy * ((n3 + rz - 1) / rz) < 2048) rz >>= 1;
+    const long nwt = nxy * ((n3 + rz - 1) / rz);
     const int g = (int)std::max(1L, std::min<long>((nwt + VT / 64 - 1) / (VT / 64), kVecGrid));
     *nparts = g;
-    hipLaunchKernelGGL(k_resid_prev, dim3(g), dim3(VT), 0, s, u, b, F, r, n1, n2, n3, P1, dim, dt,
+    hipLaunchKernelGGL(k_resid_prev, dim3(g), dim3(VT), 0, s, u, b, F, r, n1, n2, n3, P1, dim, rz, dt,
                        partials);
     return hipGetLastError();
 }
