@@ -66,6 +66,7 @@ PINV_CASES = [
     (3, [15, 31, 7], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
     (3, [1, 2, 3], [1, 2, 3], [2, 2, 2]),
     (3, [127, 127, 127], [19, 21, 23], [21, 23, 25]),
+    (3, [255, 255, 255], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),   # the benchmark grid
 ]
 
 
