@@ -36,8 +36,14 @@ import numpy as np
 # Hardware queues per process (read when the HIP runtime starts, so before
 # torch is imported).  HIP's default of 4 leaves the batched executor's lanes
 # sharing queues: at 8 the 64-instance workload runs 1,767 against 1,446
-# instance-steps/s (16 gives no more).  A value set by the caller is kept.
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# instance-steps/s (16 gives no more).  Values below 8 are raised to 8; a
+# larger value set by the caller is kept.
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
