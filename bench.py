@@ -411,6 +411,9 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
     ap.add_argument("--inner-tol", type=float, default=1e-4)
+    ap.add_argument("--dst-mfma", action="store_true",
+                    help="mixed solver: float32 DST-I as bf16 matrix-core products (the "
+                         "measured alternative to the FFT passes)")
     ap.add_argument("--x0-mixed", default="prev", choices=["prev", "extrap"])
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the mixed solver run from the extrapolated warm start")
@@ -466,7 +469,7 @@ def main(argv=None):
     if a.only in ("mixed", "both"):
         log("mixed solver ...")
         pmx = Problem(**{**common, "x0": a.x0_mixed}, precision="mixed", inner_tol=a.inner_tol,
-                      max_outer=8)
+                      max_outer=8, dst_mfma=a.dst_mfma)
         umx, tmx, itmx, outmx, profmx = run_steps(pmx, u0, F, a.steps, a.warmup, profile=True)
         res["mixed"] = dict(t=tmx, iters=itmx, outer=outmx, prof=profmx)
         del pmx

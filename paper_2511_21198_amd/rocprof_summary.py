@@ -43,7 +43,8 @@ _SOURCES = {"toep": _LINE_SRC, "dst": _LINE_SRC, "dsts": _LINE_SRC,
             "pcg": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
             "cast": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
             "resid": ["fsd_internal.h", "fsd_vec.h", "fsd_vec.hip"],
-            "circ": ["fsd_internal.h", "fsd_circ.h", "fsd_circ.hip"]}
+            "circ": ["fsd_internal.h", "fsd_circ.h", "fsd_circ.hip"],
+            "gdst": ["fsd_internal.h", "fsd_gdst.hip"], "gdsts": ["fsd_internal.h", "fsd_gdst.hip"]}
 
 
 def source_hash(kind: str | None = None) -> str:
@@ -78,6 +79,8 @@ _KINDS = [
     (re.compile(r"k_cast\b"), "cast"),
     (re.compile(r"k_resid_prev\b"), "resid_prev_f64"),
     (re.compile(r"k_circ\b"), "circ_f64"),
+    (re.compile(r"k_gdst_row\b"), "gdst_x"),
+    (re.compile(r"k_gdst_col\b"), "gdst_col"),
 ]
 
 
@@ -93,6 +96,7 @@ def classify(rows, dim=3):
     kind of each (None for kernels outside the table)."""
     out = []
     last_toep = None
+    cols = 0   # matrix-core DST column passes since the last row pass: y, last axis, y
     for r in rows:
         name = r["Kernel_Name"]
         kind = None
@@ -109,7 +113,14 @@ def classify(rows, dim=3):
             kind = "dsts_z" if dim == 3 else "dsts_y"
         if kind.startswith("toep"):
             last_toep = kind
+        if kind == "gdst_x":
+            cols = 0
+        elif kind == "gdst_col":
+            cols += 1
+            kind = ("gdsts_z" if dim == 3 else "gdsts_y") if (cols == 2 or dim == 2) else "gdst_y"
         dt = _dtype(name)
+        if kind.startswith("gdst"):
+            dt = "f32"
         out.append(f"{kind}_{dt}" if dt and kind not in ("cast", "resid_prev_f64", "circ_f64") else kind)
     return out
 
@@ -169,6 +180,37 @@ def summarise(trace_dir, fetch_dir=None, write_dir=None, np_len=None, skip_us=8.
     return res, factors
 
 
+MFMA_COUNTERS = ("SQ_INSTS_VALU_MFMA_MOPS_BF16", "SQ_VALU_MFMA_BUSY_CYCLES", "SQ_BUSY_CYCLES",
+                 "GRBM_GUI_ACTIVE")
+
+
+def mfma_summary(mfma_dir, res, dim=3):
+    """Per kind: the MFMA counters per dispatch (averaged over the
+    dispatches that issued matrix-core work; the ones enqueued after the
+    solve had stopped return at once) and the bf16 TFLOP/s they imply (a
+    MOPS unit is 512 flops) over the kind's average traced duration."""
+    rows = _read(mfma_dir, "*counter_collection.csv")
+    key = "Dispatch_Id" if "Dispatch_Id" in rows[0] else "Correlation_Id"
+    by_id = collections.OrderedDict()
+    for r in rows:
+        if r["Counter_Name"] in MFMA_COUNTERS:
+            d = by_id.setdefault(r[key], {"Kernel_Name": r["Kernel_Name"]})
+            d[r["Counter_Name"]] = float(r["Counter_Value"])
+    disp = list(by_id.values())
+    per = collections.defaultdict(list)
+    for d, k in zip(disp, classify(disp, dim)):
+        if k is not None and d.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0) > 0:
+            per[k].append(d)
+    out = {}
+    for k, ds in per.items():
+        e = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in MFMA_COUNTERS}
+        e["dispatches"] = len(ds)
+        if k in res:
+            e["bf16_tflops"] = e["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * 512.0 / (res[k]["avg_us"] * 1e-6) / 1e12
+        out[k] = e
+    return out
+
+
 def _stats_table(trace_dir: str, top: int):
     """Markdown rows of the rocprofv3 --stats kernel summary in trace_dir."""
     paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
@@ -201,6 +243,7 @@ def main(argv=None):
     ap.add_argument("--md")
     ap.add_argument("--cmd", default="", help="the profiled command, recorded in the outputs")
     ap.add_argument("--title", default="")
+    ap.add_argument("--mfma", help="rocprofv3 -d directory of a --pmc run of " + " ".join(MFMA_COUNTERS))
     ap.add_argument("--scale-from", help="summary JSON whose k_cast counter scale factors to use "
                                          "when this run launched no k_cast")
     a = ap.parse_args(argv)
@@ -211,6 +254,9 @@ def main(argv=None):
     res, factors = summarise(a.trace, a.fetch, a.write, a.np, a.skip_us, a.dim, scale_from)
     doc = {"command": a.cmd, "source_hash": source_hash(), "np": a.np,
            "counter_scale": factors, "kinds": res}
+    mf = mfma_summary(a.mfma, res, a.dim) if a.mfma else None
+    if mf:
+        doc["mfma"] = mf
     if a.json:
         with open(a.json, "w") as f:
             json.dump(doc, f, indent=1, sort_keys=True)
@@ -232,6 +278,18 @@ def main(argv=None):
                      f"{e['total_ms']:.3f} | {hb / 1e6:.2f} | {e['hbm_gbps']:.0f} |" if hb else
                      f"| {k} | {e['dispatches']} | {e['skipped']} | {e['avg_us']:.2f} | "
                      f"{e['total_ms']:.3f} | - | - |")
+    if mf:
+        lines += ["", "Matrix-core counters (per dispatch, averaged; bf16 TFLOP/s = 512 x "
+                  "SQ_INSTS_VALU_MFMA_MOPS_BF16 / average duration, dense bf16 peak 2500):", "",
+                  "| kind | MFMA MOPS (bf16) | GFLOP | MFMA busy cycles | SQ busy cycles | GRBM active | bf16 TFLOP/s |",
+                  "|---|---:|---:|---:|---:|---:|---:|"]
+        for k, e in sorted(mf.items()):
+            m = e.get("SQ_INSTS_VALU_MFMA_MOPS_BF16", 0.0)
+            if not m:
+                continue
+            lines.append(f"| {k} | {m:.4g} | {m * 512 / 1e9:.2f} | {e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0):.4g} | "
+                         f"{e.get('SQ_BUSY_CYCLES', 0):.4g} | {e.get('GRBM_GUI_ACTIVE', 0):.4g} | "
+                         f"{e.get('bf16_tflops', 0):.1f} |")
     stats = _stats_table(a.trace, 25)
     if stats:
         lines += ["", "rocprofv3 `--stats` kernel summary of the same run (`*_kernel_stats.csv`, "
