@@ -73,7 +73,8 @@ def _init(nat, p):
     (dict(dim=4), 1), (dict(n=[0, 7, 7]), 1), (dict(delta=[1.0, 0.5, 0.5]), 1),
     (dict(delta=[0.0, 0.5, 0.5]), 1), (dict(kplus=[-1.0, 1.0, 1.0]), 1), (dict(T=0.0), 1),
     (dict(M=0), 1), (dict(tol=0.0), 1), (dict(restart=0), 1), (dict(restart=65), 1),
-    (dict(solver=4), 1), (dict(solver=-1), 1),
+    (dict(solver=4), 1), (dict(solver=-1), 1), (dict(precond=4), 1), (dict(precond=-1), 1),
+    (dict(precond=2, precision=1), 1), (dict(precond=3, solver=3), 1),
     (dict(n=[9, 7, 7]), 7), (dict(n=[2047, 7, 7]), 7), (dict(n=[100, 7, 7]), 7),
 ])
 def test_init_validation(nat, kw, status):
@@ -88,6 +89,26 @@ def test_two_sided_gmres_accepted(nat):
     assert s == nat.OK
     assert nat.lib.fsd_workspace_bytes(h) > 0
     nat.lib.fsd_destroy(h)
+
+
+@pytest.mark.parametrize("precond,solver,prec", [(1, 1, 1), (1, 3, 0), (2, 2, 0), (3, 1, 0)])
+def test_comparator_preconditioners_accepted(nat, precond, solver, prec):
+    """No preconditioner runs with every solver and precision; the circulant
+    ones in float64 with the one-sided solvers.  The circulant workspace
+    holds one complex work vector more."""
+    kw = dict(n=[255, 255, 255], solver=solver, precision=prec)
+    s, h = _init(nat, _params(nat, precond=precond, **kw))
+    assert s == nat.OK
+    s0, h0 = _init(nat, _params(nat, **kw))
+    assert s0 == nat.OK
+    extra = nat.lib.fsd_workspace_bytes(h) - nat.lib.fsd_workspace_bytes(h0)
+    Np = 256 * 255 * 255
+    if precond in (2, 3):
+        assert 16 * Np <= extra < 16 * Np + (1 << 20)
+    else:
+        assert extra == 0
+    nat.lib.fsd_destroy(h)
+    nat.lib.fsd_destroy(h0)
 
 
 def test_delta_zero_allowed_in_test_mode(nat):
