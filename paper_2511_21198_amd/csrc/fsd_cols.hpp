@@ -294,7 +294,7 @@ void k_col_dst(DstArgs<float> a) {
                 if (k >= 1) {
                     const float s0 = t.pad0 ? 0.f : -yi[h][k2] * a.c;
                     const float s1 = t.pad1 ? 0.f : yr[h][k2] * a.c;
-                    *row2(a.o, t.base + (long)(k - 1) * es) = make_float2(s0, s1);
+                    st_nt2(a.o + t.base + (long)(k - 1) * es, s0, s1);
                 }
             }
         }
@@ -359,7 +359,7 @@ void k_col_dst(DstArgs<float> a) {
             if (j >= 1) {
                 const float s0 = t.pad0 ? 0.f : -xi[j2] * a.c;
                 const float s1 = t.pad1 ? 0.f : xr[j2] * a.c;
-                *row2(a.o, t.base + (long)(j - 1) * es) = make_float2(s0, s1);
+                st_nt2(a.o + t.base + (long)(j - 1) * es, s0, s1);
             }
         }
         if (a.partials) {
@@ -462,8 +462,8 @@ void k_col_toep(ToepArgs<T> a) {
             for (int m = 0; m < 16; ++m) {
                 const int j = t.r + 16 * m;
                 if (j < NN)
-                    *row2(a.o2, t.base + (long)j * es) =
-                        make_float2(t.pad0 ? 0.f : st[m].x, t.pad1 ? 0.f : st[m].y);
+                    st_nt2(a.o2 + t.base + (long)j * es, t.pad0 ? 0.f : st[m].x,
+                           t.pad1 ? 0.f : st[m].y);
             }
         }
 #pragma unroll
@@ -536,7 +536,7 @@ void k_col_toep(ToepArgs<T> a) {
             v1 = b.y - v1;
             acc += (double)v0 * (double)v0 + (double)v1 * (double)v1;
         }
-        *row2(a.o1, gi) = make_float2(v0, v1);
+        st_nt2(a.o1 + gi, v0, v1);
     }
     if constexpr (EPI == EPI_DOT_P || EPI == EPI_RESID) {
         const double s = block_sum<NT>(acc, s_red);

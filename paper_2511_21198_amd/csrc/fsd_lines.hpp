@@ -289,10 +289,10 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
                 if (a.pro == PRO_PUPDATE) {
                     const T z = a.u_fft[base + i];
                     v = first ? z : z + beta * a.pro_p[base + i];
-                    a.pro_p[base + i] = v;
+                    st_nt(a.pro_p + base + i, v);
                 } else if (a.pro == PRO_SCALE) {
                     v = scale * a.u_fft[base + i];
-                    a.pro_p[base + i] = v;
+                    st_nt(a.pro_p + base + i, v);
                 } else {
                     v = a.u_fft[base + i];
                 }
@@ -314,7 +314,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
                 const T l = i > 0 ? src[TL::idx(i - 1)] : T(0);
                 const T c = src[TL::idx(i)];
                 const T r = src[TL::idx(i + 1)];
-                a.o2[base + i] = (l + T(6) * c + r) * T(0.125);
+                st_nt(a.o2 + base + i, (l + T(6) * c + r) * T(0.125));
             }
         }
     }
@@ -330,7 +330,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
         const long base = (long)row * P1;
         for (int i = tid; i < n; i += NT) {
             const int e = (rr >> 1) * LP + TL::idx(i);
-            a.o1[base + i] = (rr & 1) ? -s_im[e] : s_re[e];
+            st_nt(a.o1 + base + i, (rr & 1) ? -s_im[e] : s_re[e]);
         }
     }
 }
@@ -376,7 +376,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
             const T l = i > 0 ? line[TL::idx(i - 1)] : T(0);
             const T c = line[TL::idx(i)];
             const T r = line[TL::idx(i + 1)];
-            a.o2[base + (long)i * es] = pad_line ? T(0) : (l + T(6) * c + r) * T(0.125);
+            st_nt(a.o2 + base + (long)i * es, pad_line ? T(0) : (l + T(6) * c + r) * T(0.125));
         }
     }
 
@@ -417,7 +417,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
             v = a.b[gi] - v;
             acc += (double)v * (double)v;
         }
-        a.o1[gi] = v;
+        st_nt(a.o1 + gi, v);
     }
     if (a.epi == EPI_DOT_P || a.epi == EPI_RESID) {
         const double s = block_sum<NT>(acc, s_red);
@@ -465,7 +465,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
         const long base = (long)row * P1;
         for (int i = tid; i < n; i += NT) {
             const int e = (rr >> 1) * LP + TL::idx(i + 1);
-            a.o[base + i] = (rr & 1) ? s_re[e] * a.c : -s_im[e] * a.c;
+            st_nt(a.o + base + i, (rr & 1) ? s_re[e] * a.c : -s_im[e] * a.c);
         }
     }
 }
@@ -510,7 +510,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
     const bool pad_line = xt * TX + xl >= a.g.nx;   // stored as exact zeros
     for (int i = ig; i < n; i += GRP) {
         const T z = other[TL::idx(i + 1)];
-        a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
+        st_nt(a.o + base + (long)i * es, pad_line ? T(0) : (odd ? z * a.c : -z * a.c));
     }
 }
 
@@ -591,7 +591,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     const bool pad_line = xt * TX + xl >= a.g.nx;   // stored as exact zeros
     for (int i = ig; i < n; i += GRP) {
         const T z = other[TL::idx(i + 1)];
-        a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
+        st_nt(a.o + base + (long)i * es, pad_line ? T(0) : (odd ? z * a.c : -z * a.c));
     }
     if (a.partials) {
         const double s = block_sum<NT>(acc, s_red);

@@ -403,10 +403,10 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
                     if constexpr (PRO == PRO_PUPDATE) {
                         const T z = a.u_fft[base + e];
                         v = first ? z : z + beta * a.pro_p[base + e];
-                        a.pro_p[base + e] = v;
+                        st_nt(a.pro_p + base + e, v);
                     } else if constexpr (PRO == PRO_SCALE) {
                         v = scale * a.u_fft[base + e];
-                        a.pro_p[base + e] = v;
+                        st_nt(a.pro_p + base + e, v);
                     } else {
                         v = a.u_fft[base + e];
                     }
@@ -445,7 +445,7 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
                         const T l = e > 0 ? src[W::idx(e - 1)] : T(0);
                         const T r = src[W::idx(e + 1)];
                         const T c = h ? xi[p][q] : xr[p][q];
-                        a.o2[base + e] = (l + T(6) * c + r) * T(0.125);
+                        st_nt(a.o2 + base + e, (l + T(6) * c + r) * T(0.125));
                     }
                 }
             }
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = tl + G * q;
-                if (e < NN) a.o1[base + e] = h ? -xi[p][q] : xr[p][q];
+                if (e < NN) st_nt(a.o1 + base + e, h ? -xi[p][q] : xr[p][q]);
             }
         }
     }
@@ -560,7 +560,7 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int k = tl + G * q;   // DST index k = 1..n -> output k-1
-                if (k >= 1) a.o[base + k - 1] = h ? xr[p][q] * a.c : -xi[p][q] * a.c;
+                if (k >= 1) st_nt(a.o + base + k - 1, h ? xr[p][q] * a.c : -xi[p][q] * a.c);
             }
         }
     }
@@ -683,7 +683,7 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
                 const T l = i > 0 ? rline[W::idx(i - 1)] : T(0);
                 const T c = rline[W::idx(i)];
                 const T r = rline[W::idx(i + 1)];
-                a.o2[base + (long)i * es] = pad_line ? T(0) : (l + T(6) * c + r) * T(0.125);
+                st_nt(a.o2 + base + (long)i * es, pad_line ? T(0) : (l + T(6) * c + r) * T(0.125));
             }
         }
     }
@@ -777,7 +777,7 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
             v = ep[k] - v;
             acc += (double)v * (double)v;
         }
-        a.o1[gi] = v;
+        st_nt(a.o1 + gi, v);
     }
     if (a.epi == EPI_DOT_P || a.epi == EPI_RESID) {
         const double s = block_sum<NT>(acc, s_red);
@@ -908,7 +908,7 @@ void k2_dst_s(DstArgs<T> a) {
 #pragma unroll
     for (int i = ig; i < NN; i += GRP) {
         const T z = other[W::idx(i + 1)];
-        a.o[base + (long)i * es] = pad_line ? T(0) : (odd ? z * a.c : -z * a.c);
+        st_nt(a.o + base + (long)i * es, pad_line ? T(0) : (odd ? z * a.c : -z * a.c));
     }
     if (SCALE && a.partials) {
         const double s = block_sum<NT>(acc, s_red);
