@@ -410,7 +410,10 @@ def main(argv=None):
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
-    ap.add_argument("--inner-tol", type=float, default=1e-4)
+    # 1e-3 measured 1.2% above 1e-4 at 255^3 (62.1 against 61.35 CN steps/s,
+    # same inner iteration total): the looser inner solves split the first
+    # steps over three outer passes with smaller Arnoldi bases
+    ap.add_argument("--inner-tol", type=float, default=1e-3)
     ap.add_argument("--dst-mfma", action="store_true",
                     help="mixed solver: float32 DST-I as bf16 matrix-core products (the "
                          "measured alternative to the FFT passes)")
