@@ -758,9 +758,10 @@ fsd_status norm2(fsd_problem P, const double* b, double* nrm) {
     return FSD_OK;
 }
 
-// ||b||, ||r|| with r = b - A x written to r, and (with pb) ||pb||, read
-// with one host synchronisation: the start of the mixed-precision loop.
-fsd_status start_norms(fsd_problem P, const double* x, const double* b, double* r, const double* pb,
+// ||b||, ||r|| with r = b - A x written to r, and (with pb) ||pb|| (a
+// float32 vector, float64 accumulation), read with one host
+// synchronisation: the start of the mixed-precision loop.
+fsd_status start_norms(fsd_problem P, const double* x, const double* b, double* r, const float* pb,
                        double* bnorm, double* rnorm, double* pbnorm) {
     hipStream_t s = P->stream;
     int np = 0;
@@ -768,7 +769,7 @@ fsd_status start_norms(fsd_problem P, const double* x, const double* b, double* 
     HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_BB, s));
     if (pb) {
-        HIP_TRY(vec_dot<double>(pb, pb, P->Np, P->partials, nullptr, &np, s));
+        HIP_TRY(vec_dot<float>(pb, pb, P->Np, P->partials, nullptr, &np, s));
         HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RZ, s));
     }
     FSD_TRY(first_residual<double>(P, x, b, r, nullptr, &np));
@@ -813,11 +814,17 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         int outer = 0;
         int status = FSD_ENOTCONV;
         double relres = 0.0, bnorm = 0.0, pbnorm = 0.0, prec_rel = 0.0;
-        if (left) FSD_TRY(op_precond<double>(P, b, P->v64.z, nullptr, nullptr, nullptr, split));
+        // ||P^{-1} b|| with the float32 preconditioner: the numerator of the
+        // test, ||P^{-1} r||, is the first step of each inner solve, which
+        // applies the same float32 preconditioner
+        if (left) {
+            HIP_TRY((vec_cast<double, float>(b, f.b, P->Np, 1.0, P->stream)));
+            FSD_TRY(op_precond<float>(P, f.b, f.w, nullptr, nullptr, nullptr, split));
+        }
         for (bool start = true;; start = false) {
             double rnorm = 0.0;
             if (start)
-                FSD_TRY(start_norms(P, x, b, r, left ? P->v64.z : nullptr, &bnorm, &rnorm, &pbnorm));
+                FSD_TRY(start_norms(P, x, b, r, left ? f.w : nullptr, &bnorm, &rnorm, &pbnorm));
             else
                 FSD_TRY(true_residual(P, x, b, r, &rnorm));
             relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
