@@ -385,7 +385,7 @@ def secondary_symmetric(a):
                        "to T=1, 8 seeded bumps, u0=0, PCG, tol 1e-10"}
     us = {}
     for name, kw in (("fp64", dict(precision="fp64")),
-                     ("mixed", dict(precision="mixed", inner_tol=1e-4))):
+                     ("mixed", dict(precision="mixed", inner_tol=1e-5))):
         p = Problem(**common, **kw)
         u, t, it, outer, _ = run_steps(p, u0, F, 8, 2)
         us[name] = u
