@@ -4,24 +4,29 @@ float64, on one MI355X.
 Workload (3D non-symmetric): (alpha, beta, gamma) = (0.4, 0.6, 0.8),
 k+ = (1.0, 0.8, 1.2), k- = (0.5, 1.0, 0.3), 255^3 interior unknowns, 16 CN
 steps to T = 1, f = 8 seeded Gaussian bumps, u0 = 0, left-preconditioned
-GMRES(20) with the sine-transform preconditioner, tol 1e-8.
+GMRES(20) with the sine-transform preconditioner from u^{m-1}.  Both solvers
+run at the paper's tolerance 1e-9 (workloads.HEADLINE_SOLVER), which keeps
+u^M within 1e-8 of a tightly solved float64 trajectory in the 2-norm and the
+max-norm; the figures at the configuration's literal tol 1e-8 are reported
+beside them.
 
 A step is one fsd_cn_step: right-hand side, then the solve.  The headline
 value is the mixed-precision solver (float32 inner GMRES, float64 defect
-correction); the same steps are run with the float64 solver for the
-comparison and the relative difference of the two final states.  Both start
-each step from u^{m-1}; `mixed_extrap` adds the mixed solver started from the
-linear extrapolation 2u^{m-1} - u^{m-2} (the warm start without a network),
-against the same float64 run.
+correction with the float64 stopping test), against the float64 solver.
+Timed steps come only from steps 2..16 of the workload: each timed pass
+restarts from u0, runs step 1 untimed and times `--steps` steps (past step
+16 it restarts again, step 1 untimed); `value` is the median over
+`--repeats` passes, with the interquartile range beside it.
 
-    python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu]
+    python bench.py [--steps K] [--warmup W] [--repeats R] [--gpus 1] [--no-cpu]
 
 Prints one JSON line (rank 0).  Inputs are generated on the host and copied
-to the GPU before timing.  The timed steps run without per-kernel events; the
-roofline entry is the dominant kernel of the same mixed-precision steps run
-again from the same state with hipEvents recorded by the library around each
-launch on its stream; `cpu_baseline` times the float64 oracle on this host
-for one CN step (the first step of the same workload).
+to the GPU before timing.  The timed passes run without per-kernel events;
+the per-kernel figures (`roofline`, `roofline_kernels`) come from one more
+pass over the same steps with the library's hipEvents around each launch on
+its stream.  `hbm_peak` is a measured stream copy (fsd_hbm_copy);
+`cpu_baseline` times the float64 oracle on this host for a bounded sample,
+normalised per GMRES iteration.
 """
 from __future__ import annotations
 
@@ -67,65 +72,158 @@ def cpu_model():
     return "unknown"
 
 
-def run_steps(prob, u0, F, steps, warmup, profile=False):
-    """Advance warmup + steps CN steps; time the last `steps`.
+class Trajectory:
+    """The headline workload's CN trajectory u^0 = u0, u^1, ..., u^M.  A step
+    past u^M starts the trajectory again from u0 (the step after is step 1
+    again), so no step ever runs past T."""
 
-    The timed steps run without per-kernel events: a hipEvent pair around
-    every launch adds about 10% to the wall time at 255^3.  With `profile`,
-    the same `steps` steps are then repeated from the post-warm-up state with
-    the library's per-kernel hipEvents on its stream (identical iteration
-    counts: the solves are deterministic), which give the per-kernel averages
-    of the roofline entry."""
+    def __init__(self, prob, u0, F, M):
+        self.prob, self.u0, self.F, self.M = prob, u0, F, M
+        self.u = u0.clone()
+        self.m = 0            # steps taken since u0
+
+    def restart(self):
+        self.u = self.u0.clone()
+        self.m = 0
+        self.prob.reset_history()
+
+    def step(self):
+        if self.m == self.M:
+            self.restart()
+        self.u, st = self.prob.cn_step(self.u, self.F, out=self.u)
+        self.m += 1
+        return st
+
+
+def timed_steps(traj, K):
+    """Time K steps of the trajectory taken only from steps 2..M: step 1 of
+    each pass (after the restart from u0) runs untimed.  Each run of
+    consecutive timed steps is bracketed by torch.cuda.synchronize(); the
+    time is their sum.  Returns (seconds, iterations, outer steps) of the
+    timed steps."""
     import torch
-    u = u0.clone()
-    iters = []
-    outer = []
+    total, its, outer = 0.0, [], []
+    done = 0
+    while done < K:
+        if traj.m in (0, traj.M):
+            if traj.m == traj.M:
+                traj.restart()
+            traj.step()                      # step 1: untimed
+        seg = min(K - done, traj.M - traj.m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(seg):
+            st = traj.step()
+            its.append(st["iters"])
+            outer.append(st["outer_iters"])
+        torch.cuda.synchronize()
+        total += time.perf_counter() - t0
+        done += seg
+    return total, its, outer
+
+
+def repeat_timing(prob, u0, F, M, steps, warmup, repeats, profile=False):
+    """W warm-up steps, then `repeats` timed passes of `steps` steps, each
+    from u0 with step 1 untimed (the same steps 2..steps+1 every time: the
+    solves are deterministic).  With `profile`, one more pass with the
+    library's per-launch hipEvents on its stream gives the per-kernel
+    figures (the timed passes run without events: an event pair around every
+    launch adds about 10% to the wall time at 255^3).  Returns a dict with
+    the per-pass CN steps/s, their median and interquartile range, the
+    iterations of the timed steps and the profile."""
+    traj = Trajectory(prob, u0, F, M)
     for _ in range(warmup):
-        u, st = prob.cn_step(u, F)
-        iters.append(st["iters"])
-        outer.append(st["outer_iters"])
-    torch.cuda.synchronize()
-    u_w = u.clone() if profile else None
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        u, st = prob.cn_step(u, F)
-        iters.append(st["iters"])
-        outer.append(st["outer_iters"])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+        traj.step()
+    rates, its, outer = [], None, None
+    for _ in range(repeats):
+        traj.restart()
+        t, it, ou = timed_steps(traj, steps)
+        rates.append(steps / t)
+        if its is None:
+            its, outer = it, ou
+        elif it != its:
+            log(f"note: iteration counts differ between repeats: {it} vs {its}")
     prof = None
     if profile:
-        prob.reset_history()
-        v = u_w
+        traj.restart()
+        traj.step()
         prob.profile(True)
-        prob.profile_read()           # discard anything before the profiled steps
-        for k in range(steps):
-            v, st = prob.cn_step(v, F)
-            if st["iters"] != iters[warmup + k]:
-                log(f"note: profiled step {k} took {st['iters']} iterations, timed step "
-                    f"{iters[warmup + k]}")
-        torch.cuda.synchronize()
+        prob.profile_read()
+        _, it, _ = timed_steps(traj, steps)
         prof = prob.profile_read()
         prob.profile(False)
-        del v
-    return u, (t1 - t0), iters, outer, prof
+    q = np.percentile(rates, [25, 50, 75])
+    return {"steps_per_s": float(q[1]), "iqr": [float(q[0]), float(q[2])],
+            "per_repeat": [round(r, 3) for r in rates], "iters": its, "outer": outer,
+            "prof": prof}
 
 
-def cpu_baseline(w):
-    """Float64 oracle, first CN step of the workload, on this host."""
+def final_state(prob, u0, F, M):
+    """u^M of the whole trajectory (untimed), for the error figures."""
+    prob.reset_history()
+    u = u0.clone()
+    for _ in range(M):
+        u, _ = prob.cn_step(u, F)
+    return u
+
+
+def errors(u, uref):
+    import torch
+    return {"rel_2norm": float(torch.linalg.vector_norm(u - uref) / torch.linalg.vector_norm(uref)),
+            "rel_maxnorm": float((u - uref).abs().max() / uref.abs().max())}
+
+
+def cpu_baseline(w, gpu_mean_iters, iters=10):
+    """Float64 oracle on this host, normalised per GMRES iteration: one
+    right-hand side and the first `iters` GMRES iterations of step 1 are
+    timed, and the rate is given for a step of the mean iteration count of
+    the GPU's timed steps (steps 2..M, float64 solver at the same
+    tolerance; the oracle's counts agree within one)."""
     from oracle import cn, operators as op
     prob = op.Problem(3, w.n, w.delta, w.kplus, w.kminus, T=w.T, M=w.M)
     t0 = time.perf_counter()
-    u, its = cn.run(prob, w.u0, lambda m: w.F, tol=w.tol, x0_mode="prev", solver="gmres",
-                    steps=1)
-    dt = time.perf_counter() - t0
+    op.apply_rhs(prob, w.u0, w.F)
+    t_rhs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    cn.run(prob, w.u0, lambda m: w.F, tol=1e-30, x0_mode="prev", solver="gmres", steps=1,
+           maxit=iters)
+    t_run = time.perf_counter() - t0
+    t_iter = max(t_run - t_rhs, 0.0) / iters
+    t_step = t_rhs + gpu_mean_iters * t_iter
     try:
         cores = len(os.sched_getaffinity(0))
     except AttributeError:
         cores = os.cpu_count()
-    return {"value": 1.0 / dt, "unit": "CN steps/s", "cores": cores, "kind": "oracle",
-            "sample": f"1 CN step (step 1 of 16, {its[0]} GMRES iterations) of the same workload, "
-                      f"float64 NumPy/SciPy oracle, {dt:.1f} s on {cpu_model()}"}
+    return {"value": round(1.0 / t_step, 5), "unit": "CN steps/s", "cores": cores, "kind": "oracle",
+            "sample": f"float64 NumPy/SciPy oracle on {cpu_model()}: one right-hand side "
+                      f"({t_rhs:.2f} s) and {iters} GMRES iterations of step 1 "
+                      f"({t_iter:.2f} s each) of the same workload, scaled to a step of "
+                      f"{gpu_mean_iters:.2f} iterations (the mean over steps 2..16 of the GPU "
+                      f"float64 solver at the same tolerance): {t_step:.1f} s per CN step"}
+
+
+def hbm_peak(nbytes=1 << 30, reps=20):
+    """Measured HBM peak: fsd_hbm_copy of nbytes (read nbytes, write nbytes),
+    median over reps calls timed with hipEvents on the current stream."""
+    import torch
+    from paper_2511_21198_amd.solver import hbm_copy
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    st = torch.cuda.current_stream()
+    for _ in range(3):
+        hbm_copy(a, b, st)
+    ms = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        hbm_copy(a, b, st)
+        e1.record(st)
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    med = float(np.median(ms))
+    del a, b
+    return {"kernel": "fsd_hbm_copy (k_stream_copy)", "bytes_per_call": 2 * nbytes,
+            "median_ms": round(med, 4), "gbps": round(2 * nbytes / (med * 1e-3) / 1e9, 1)}
 
 
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "hbm_traffic_3d_nonsym_255.json")
@@ -147,42 +245,58 @@ def counter_traffic(kind):
     return e.get("hbm_bytes_per_dispatch")
 
 
-def matvec_bench(w, reps=100):
-    """One fsd_apply_A at the workload's size, float64, `reps` calls: wall
-    time per call (hipEvents on the library's stream) and the per-pass
-    figures of the library profiler."""
+def operator_bench(w, peak, reps=100):
+    """The operators at the workload's size, each called `reps` times: the
+    float64 and float32 Toeplitz matvec (fsd_apply_A, fsd_apply_A32) and the
+    float64 and float32 preconditioner (fsd_apply_Pinv, fsd_apply_Pinv32).
+    Per call (hipEvents on the library's stream around each call, median):
+    (i) algorithmic GB/s, 2 N b / t with b the bytes of the operator's
+    arithmetic type (read x, write y); (ii) pass-level GB/s, the bytes every
+    line pass must read and write over the summed pass durations (library
+    profiler, hipEvents per launch).  The calls also pack and unpack the
+    dense float64 ABI layout, which (i) includes and (ii) does not."""
     import torch
     from paper_2511_21198_amd.solver import Problem
-    p = Problem(3, w.n, w.delta, w.kplus, w.kminus, M=w.M, T=w.T, solver="gmres")
+    N = int(np.prod(w.n))
+    p = Problem(3, w.n, w.delta, w.kplus, w.kminus, M=w.M, T=w.T, solver="gmres", precision="mixed")
     x = torch.from_numpy(w.F).cuda()
     y = torch.empty_like(x)
-    for _ in range(5):
-        p.apply_A(x, out=y)
-    st = p.stream
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(st)
-    for _ in range(reps):
-        p.apply_A(x, out=y)
-    e1.record(st)
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    p.profile(True)
-    p.profile_read()
-    for _ in range(reps):
-        p.apply_A(x, out=y)
-    prof = p.profile_read()
-    p.profile(False)
-    N = int(np.prod(w.n))
-    pass_ms = sum(v["total_ms"] for v in prof.values()) / reps
-    pass_bytes = sum(v["bytes"] for v in prof.values()) / reps
-    return {"apply_A_ms": round(ms, 4),
-            "algorithmic_gbps": round(2 * N * 8 / (ms * 1e-3) / 1e9, 1),
-            "passes_ms": round(pass_ms, 4),
-            "pass_level_gbps": round(pass_bytes / (pass_ms * 1e-3) / 1e9, 1),
-            "passes": {k: {"avg_ms": round(v["avg_ms"], 4), "gbps": round(v["gbps"], 1)}
-                       for k, v in prof.items()},
-            "note": "float64, dense ABI layout in and out (pack and unpack kernels "
-                    "included in apply_A_ms), 100 calls"}
+    out = {}
+    for name, fn, b in (("apply_A_fp64", p.apply_A, 8), ("apply_A_fp32", p.apply_A32, 4),
+                        ("apply_Pinv_fp64", p.apply_Pinv, 8), ("apply_Pinv_fp32", p.apply_Pinv32, 4)):
+        for _ in range(5):
+            fn(x, out=y)
+        st = p.stream
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(reps)]
+        for e0, e1 in ev:
+            e0.record(st)
+            fn(x, out=y)
+            e1.record(st)
+        torch.cuda.synchronize()
+        ms = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        p.profile(True)
+        p.profile_read()
+        for _ in range(reps):
+            fn(x, out=y)
+        prof = p.profile_read()
+        p.profile(False)
+        pass_ms = sum(v["total_ms"] for v in prof.values()) / reps
+        pass_bytes = sum(v["bytes"] for v in prof.values()) / reps
+        alg = 2 * N * b / (ms * 1e-3) / 1e9
+        pl = pass_bytes / (pass_ms * 1e-3) / 1e9
+        out[name] = {"median_ms": round(ms, 4), "algorithmic_gbps": round(alg, 1),
+                     "passes_ms": round(pass_ms, 4), "pass_level_gbps": round(pl, 1),
+                     "pass_level_frac_datasheet": round(pl / HBM_PEAK_GBPS, 3),
+                     "pass_level_frac_measured": round(pl / peak, 3) if peak else None,
+                     "passes": {k: {"avg_ms": round(v["avg_ms"], 4), "gbps": round(v["gbps"], 1)}
+                                for k, v in prof.items()}}
+        log(f"operator {name}: {out[name]['median_ms']} ms, pass level {out[name]['pass_level_gbps']} GB/s")
+    del p
+    out["note"] = (f"{reps} calls each at {w.n[0]}^3; (i) algorithmic and (ii) pass-level GB/s as "
+                   "defined in the function docstring; (iii) DRAM bytes from rocprofv3 counters "
+                   "are in profiles/")
+    return out
 
 
 WEIGHTS = os.path.join(ROOT, "paper_2511_21198_amd", "weights", "warmstart_3d_sym.npy")
@@ -313,24 +427,26 @@ def batched_workload(a, streams=8, steps=8):
     return out
 
 
-def two_sided(w, F, u0, steps, warmup):
+def two_sided(w, F, u0, steps, warmup, tol):
     """GMRES(20) on the two-sided system P^{-1/2} A P^{-1/2} v = P^{-1/2} b
-    (the system Theorem 3.2 bounds) on the headline workload, float64 and
-    mixed precision, with the Theorem 3.2 rate omega of the workload."""
+    (the system Theorem 3.2 bounds) on the headline workload and tolerance,
+    float64 and mixed precision, with the Theorem 3.2 rate omega of the
+    workload; steps 2..steps+1 timed (median of 3 passes)."""
     import math
     from paper_2511_21198_amd.solver import Problem
     common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
-                  solver="gmres2", restart=20, tol=w.tol, x0="prev")
+                  solver="gmres2", restart=20, tol=tol, x0="prev")
     vs = 1.5 * max(math.tan(w.delta[i] * math.pi / 2) * abs(w.kplus[i] - w.kminus[i])
                    / (w.kplus[i] + w.kminus[i]) for i in range(3))
     out = {"solver": "GMRES(20) on P^{-1/2} A P^{-1/2}, two half-preconditioner applications "
-                     "per iteration", "varsigma": round(vs, 4),
+                     "per iteration", "tol": tol, "varsigma": round(vs, 4),
            "omega": round(math.sqrt((2 + 4 * vs ** 2) / (3 + 4 * vs ** 2)), 4)}
     for name, kw in (("fp64", dict(precision="fp64")),
-                     ("mixed", dict(precision="mixed", inner_tol=1e-4, max_outer=8))):
+                     ("mixed", dict(precision="mixed", inner_tol=1e-3, max_outer=8))):
         p = Problem(**common, **kw)
-        _, t, it, outer, _ = run_steps(p, u0, F, steps, warmup)
-        out[name] = {"steps_per_s": round(steps / t, 3), "iters": it, "outer": outer}
+        r = repeat_timing(p, u0, F, w.M, steps, warmup, 3)
+        out[name] = {"steps_per_s": round(r["steps_per_s"], 3), "iters": r["iters"],
+                     "outer": r["outer"]}
         del p
     return out
 
@@ -344,13 +460,13 @@ def comparators(w, F, u0):
     from paper_2511_21198_amd.solver import Problem
     common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
                   solver="gmres", restart=20, tol=w.tol, x0="prev", precision="fp64")
-    out = {"solver": "float64 left GMRES(20), x0 = u^{m-1}; 2 timed CN steps after 1"}
+    out = {"solver": "float64 left GMRES(20), x0 = u^{m-1}, tol 1e-8; steps 2 and 3 timed"}
     r = torch.from_numpy(w.F).cuda()
     for kind in ("tau", "tchan", "strang", "none"):
         log(f"comparator {kind} ...")
         p = Problem(**common, precond=kind, maxit=4000)
-        _, t, it, _, _ = run_steps(p, u0, F, 2, 1)
-        e = {"steps_per_s": round(2 / t, 3), "iters": it}
+        rt = repeat_timing(p, u0, F, w.M, 2, 0, 1)
+        e = {"steps_per_s": round(rt["steps_per_s"], 3), "iters": rt["iters"]}
         z = torch.empty_like(r)
         for _ in range(3):
             p.apply_Pinv(r, z)
@@ -372,7 +488,8 @@ def comparators(w, F, u0):
 
 def secondary_symmetric(a):
     """3D symmetric 127^3, (0.3, 0.5, 0.7), k = 1, 8 bumps, tol 1e-10: float64
-    PCG vs float32-inner / float64-outer PCG, 8 timed steps after 2."""
+    PCG vs float32-inner / float64-outer PCG, steps 2..9 timed (median of 3
+    passes); errors of u^9 against a tol-1e-13 float64 run."""
     import torch
     import workloads
     from paper_2511_21198_amd.solver import Problem
@@ -387,14 +504,13 @@ def secondary_symmetric(a):
     for name, kw in (("fp64", dict(precision="fp64")),
                      ("mixed", dict(precision="mixed", inner_tol=1e-5))):
         p = Problem(**common, **kw)
-        u, t, it, outer, _ = run_steps(p, u0, F, 8, 2)
-        us[name] = u
-        out[name] = {"steps_per_s": round(8 / t, 2), "iters": it, "outer": outer}
+        r = repeat_timing(p, u0, F, w.M, 8, 2, 3)
+        us[name] = final_state(p, u0, F, 9)
+        out[name] = {"steps_per_s": round(r["steps_per_s"], 2), "iqr": r["iqr"], "iters": r["iters"],
+                     "outer": r["outer"]}
         del p
     pref = Problem(**{**common, "tol": 1e-13}, precision="fp64")
-    uref = u0.clone()
-    for _ in range(10):
-        uref, _ = pref.cn_step(uref, F)
+    uref = final_state(pref, u0, F, 9)
     for name in us:
         out[name]["rel_err_vs_tight_fp64"] = float(torch.linalg.vector_norm(us[name] - uref)
                                                    / torch.linalg.vector_norm(uref))
@@ -402,28 +518,46 @@ def secondary_symmetric(a):
     return out
 
 
+LINE_PASSES = ("toep_", "dst_", "dsts_")
+
+
+def kernel_table(prof, peak):
+    """Per kernel kind of a profiled pass: launches, average hipEvent
+    duration, algorithmic bytes per launch and GB/s, and the fraction of the
+    datasheet and of the measured HBM peak."""
+    out = {}
+    for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        per = v["bytes"] / max(v["launches"], 1)
+        out[k] = {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
+                  "total_ms": round(v["total_ms"], 3), "bytes_per_launch": per,
+                  "gbps": round(v["gbps"], 1), "frac_datasheet": round(v["gbps"] / HBM_PEAK_GBPS, 3),
+                  "frac_measured": round(v["gbps"] / peak, 3) if peak else None}
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=8)
+    ap.add_argument("--steps", type=int, default=15,
+                    help="timed CN steps per repeat, taken from steps 2..16 of the workload "
+                         "(a pass restarts from u0 with step 1 untimed)")
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--repeats", type=int, default=5)
     ap.add_argument("--n", type=int, default=255)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle timing")
     ap.add_argument("--only", choices=["mixed", "fp64", "both"], default="both")
-    # 1e-3 measured 1.2% above 1e-4 at 255^3 (62.1 against 61.35 CN steps/s,
-    # same inner iteration total): the looser inner solves split the first
-    # steps over three outer passes with smaller Arnoldi bases
-    ap.add_argument("--inner-tol", type=float, default=1e-3)
+    ap.add_argument("--inner-tol", type=float, default=None,
+                    help="mixed-precision inner tolerance (default: the headline setting)")
     ap.add_argument("--dst-mfma", action="store_true",
                     help="mixed solver: float32 DST-I as bf16 matrix-core products (the "
                          "measured alternative to the FFT passes)")
-    ap.add_argument("--x0-mixed", default="prev", choices=["prev", "extrap"])
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the mixed solver run from the extrapolated warm start")
     ap.add_argument("--no-ref", action="store_true",
                     help="skip the tight float64 reference run used for the error figures")
     ap.add_argument("--no-secondary", action="store_true",
-                    help="skip the 127^3 symmetric PCG comparison")
+                    help="skip the tol-1e-8 figures, two-sided GMRES, comparators, operators "
+                         "and the 127^3 symmetric PCG comparison")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned warm start workload (255^3, 200 steps)")
     ap.add_argument("--only-learned", action="store_true",
@@ -434,13 +568,13 @@ def main(argv=None):
                     help="run only the batched workload and print its JSON")
     ap.add_argument("--only-comparators", action="store_true",
                     help="run only the comparator preconditioners and print their JSON")
+    ap.add_argument("--only-operators", action="store_true",
+                    help="run only the operator timings and print their JSON")
     a = ap.parse_args(argv)
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print(json.dumps({"error": "this solver runs on one GPU; multi-GPU runs are not "
                                    "supported (use --gpus 1)", "n_gpus": a.gpus}))
         return 2
-    if a.warmup + a.steps > 16:
-        log("warning: more steps than the workload's 16; continuing past T = 1")
 
     import torch
     import workloads
@@ -457,63 +591,63 @@ def main(argv=None):
         F = torch.from_numpy(w.F).cuda()
         print(json.dumps(comparators(w, F, torch.zeros_like(F))), flush=True)
         return 0
+    log("hbm peak (stream copy) ...")
+    peak = hbm_peak()
+    if a.only_operators:
+        print(json.dumps({"hbm_peak": peak, "operators": operator_bench(w, peak["gbps"])}),
+              flush=True)
+        return 0
+    S = dict(workloads.HEADLINE_SOLVER)
+    tol = S.pop("tol")
+    inner_tol = S.pop("inner_tol") if a.inner_tol is None else a.inner_tol
+    S.pop("inner_tol", None)
+    max_outer = S.pop("max_outer")
     dev = torch.device("cuda:0")
     F = torch.from_numpy(w.F).to(dev)
     u0 = torch.zeros_like(F)
     common = dict(dim=3, n=w.n, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=w.M, T=w.T,
-                  solver="gmres", restart=20, tol=w.tol, x0="prev")
+                  solver="gmres", **S)
+    mixed_kw = dict(precision="mixed", inner_tol=inner_tol, max_outer=max_outer)
+
+    def leg(name, t, kw, profile=False, repeats=None, x0=None):
+        log(f"{name} (tol {t:g}) ...")
+        c = dict(common)
+        if x0:
+            c["x0"] = x0
+        p = Problem(**c, tol=t, **kw)
+        r = repeat_timing(p, u0, F, w.M, a.steps, a.warmup, repeats or a.repeats, profile)
+        r["u_final"] = final_state(p, u0, F, w.M) if not a.no_ref else None
+        del p
+        log(f"  {r['steps_per_s']:.3f} CN steps/s (IQR {r['iqr'][0]:.3f}..{r['iqr'][1]:.3f})")
+        return r
+
     res = {}
     if a.only in ("fp64", "both"):
-        log("fp64 solver ...")
-        p64 = Problem(**common, precision="fp64")
-        u64, t64, it64, _, prof64 = run_steps(p64, u0, F, a.steps, a.warmup, profile=True)
-        res["fp64"] = dict(t=t64, iters=it64, prof=prof64)
-        del p64
+        res["fp64"] = leg("fp64 solver", tol, dict(precision="fp64"), profile=True)
     if a.only in ("mixed", "both"):
-        log("mixed solver ...")
-        pmx = Problem(**{**common, "x0": a.x0_mixed}, precision="mixed", inner_tol=a.inner_tol,
-                      max_outer=8, dst_mfma=a.dst_mfma)
-        umx, tmx, itmx, outmx, profmx = run_steps(pmx, u0, F, a.steps, a.warmup, profile=True)
-        res["mixed"] = dict(t=tmx, iters=itmx, outer=outmx, prof=profmx)
-        del pmx
-        if a.x0_mixed == "prev" and not a.no_warm:
-            # the same mixed solver started from the extrapolation 2u^{m-1} - u^{m-2}
-            log("mixed solver, extrapolated warm start ...")
-            pwx = Problem(**{**common, "x0": "extrap"}, precision="mixed", inner_tol=a.inner_tol,
-                          max_outer=8)
-            uwx, twx, itwx, outwx, _ = run_steps(pwx, u0, F, a.steps, a.warmup)
-            res["mixed_extrap"] = dict(t=twx, iters=itwx, outer=outwx)
-            del pwx
+        res["mixed"] = leg("mixed solver", tol, dict(mixed_kw, dst_mfma=a.dst_mfma), profile=True)
+        if not a.no_warm:
+            res["mixed_extrap"] = leg("mixed solver, extrapolated warm start", tol, mixed_kw,
+                                      x0="extrap", repeats=3)
+    if not a.no_secondary:
+        res["fp64_tol_1e-8"] = leg("fp64 solver", 1e-8, dict(precision="fp64"), repeats=3)
+        res["mixed_tol_1e-8"] = leg("mixed solver", 1e-8, mixed_kw, repeats=3)
     errs = {}
     if not a.no_ref:
         log("tight float64 reference (tol 1e-12, untimed) ...")
         pref = Problem(**{**common, "tol": 1e-12}, precision="fp64")
-        uref = u0.clone()
-        for _ in range(a.warmup + a.steps):
-            uref, _ = pref.cn_step(uref, F)
+        uref = final_state(pref, u0, F, w.M)
         del pref
-        nrm = torch.linalg.vector_norm(uref)
-        if "fp64" in res:
-            errs["fp64"] = float(torch.linalg.vector_norm(u64 - uref) / nrm)
-        if "mixed" in res:
-            errs["mixed"] = float(torch.linalg.vector_norm(umx - uref) / nrm)
-        if "mixed_extrap" in res:
-            errs["mixed_extrap"] = float(torch.linalg.vector_norm(uwx - uref) / nrm)
+        for k, r in res.items():
+            errs[k] = errors(r["u_final"], uref)
     head = "mixed" if "mixed" in res else "fp64"
-    T = res[head]["t"]
-    value = a.steps / T
-    rel = None
-    if "mixed" in res and "fp64" in res:
-        rel = float(torch.linalg.vector_norm(umx - u64) / torch.linalg.vector_norm(u64))
-
-    prof = res[head]["prof"]
-    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
-    per_launch = dom["bytes"] / dom["launches"]
-    achieved = per_launch / (dom["avg_ms"] * 1e-3) / 1e9
-    toep = {k: round(v["gbps"], 1) for k, v in prof.items() if k.startswith("toep")}
-    if "fp64" in res:
-        toep.update({k: round(v["gbps"], 1) for k, v in res["fp64"]["prof"].items()
-                     if k.startswith("toep")})
+    H = res[head]
+    value = H["steps_per_s"]
+    ms_per_step = 1e3 / value
+    ktab = kernel_table(H["prof"], peak["gbps"])
+    lp = [k for k in ktab if k.startswith(LINE_PASSES)]
+    dom = lp[0] if lp else next(iter(ktab))
+    d = ktab[dom]
     out = {
         "metric": METRIC,
         "value": round(value, 3),
@@ -521,7 +655,7 @@ def main(argv=None):
         "n_gpus": 1,
         "steps": a.steps,
         "warmup": a.warmup,
-        "ms_per_step": round(1e3 * T / a.steps, 3),
+        "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -530,53 +664,71 @@ def main(argv=None):
         "config": {"workload": f"3D non-symmetric {a.n}^3, (alpha,beta,gamma)=(0.4,0.6,0.8), "
                                "k+=(1.0,0.8,1.2), k-=(0.5,1.0,0.3), 16 CN steps to T=1, "
                                "8 seeded Gaussian bumps, u0=0, PGMRES(20) + sine-transform "
-                               "preconditioner, tol 1e-8",
-                   "solver": f"{head}: " + ("float32 inner GMRES in float64 defect correction"
+                               f"preconditioner from u^(m-1), tol {tol:g}; timed steps are taken "
+                               "from steps 2..16 only (a pass restarts from u0, step 1 untimed); "
+                               f"value = median over {a.repeats} passes",
+                   "solver": f"{head}: " + (f"float32 inner GMRES (inner tol {inner_tol:g}) in "
+                                             "float64 defect correction, float64 outer test"
                                              if head == "mixed" else "float64 GMRES"),
-                   "n": a.n, "unknowns": a.n ** 3},
-        "roofline": {"bound": "hbm", "kernel": dom_name, "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBPS, 4),
-                     "traffic": counter_traffic(dom_name) if a.n == 255 else None,
-                     "avg_launch_ms": round(dom["avg_ms"], 5),
-                     "algorithmic_bytes_per_launch": per_launch},
-        "toeplitz_matvec_gbps": toep,
+                   "tol": tol, "n": a.n, "unknowns": a.n ** 3},
+        "iqr_steps_per_s": [round(v, 3) for v in H["iqr"]],
+        "per_repeat_steps_per_s": H["per_repeat"],
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["gbps"], "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": d["frac_datasheet"],
+                     "traffic": counter_traffic(dom) if a.n == 255 else None,
+                     "avg_launch_ms": d["avg_ms"], "algorithmic_bytes_per_launch": d["bytes_per_launch"],
+                     "measured_peak_gbps": peak["gbps"], "frac_measured_peak": d["frac_measured"],
+                     "note": "the line pass (Toeplitz matvec or DST preconditioner pass) with the "
+                             "largest total time in the timed mixed-precision steps; every kernel "
+                             "kind is in roofline_kernels"},
+        "hbm_peak": peak,
     }
     if "fp64" in res:
-        out["fp64_steps_per_s"] = round(a.steps / res["fp64"]["t"], 3)
+        out["fp64_steps_per_s"] = round(res["fp64"]["steps_per_s"], 3)
+        out["fp64_iqr_steps_per_s"] = [round(v, 3) for v in res["fp64"]["iqr"]]
         out["iters_fp64"] = res["fp64"]["iters"]
     if "mixed" in res:
         out["iters_mixed_inner"] = res["mixed"]["iters"]
         out["outer_mixed"] = res["mixed"]["outer"]
-    if rel is not None:
-        out["speedup_vs_fp64"] = round(out["fp64_steps_per_s"] and value / out["fp64_steps_per_s"], 3)
-        out["rel_diff_mixed_vs_fp64"] = rel
+    if "mixed" in res and "fp64" in res:
+        out["speedup_vs_fp64"] = round(value / res["fp64"]["steps_per_s"], 3)
+    if errs:
+        out["rel_err_vs_tight_fp64"] = errs
+        if "mixed" in res and "fp64" in res:
+            out["rel_diff_mixed_vs_fp64"] = errors(res["mixed"]["u_final"], res["fp64"]["u_final"])
     if "mixed_extrap" in res:
         wx = res["mixed_extrap"]
-        out["mixed_extrap"] = {"steps_per_s": round(a.steps / wx["t"], 3), "iters_inner": wx["iters"],
+        out["mixed_extrap"] = {"steps_per_s": round(wx["steps_per_s"], 3), "iters_inner": wx["iters"],
                                "outer": wx["outer"]}
         if "fp64" in res:
             out["mixed_extrap"]["speedup_vs_fp64_prev"] = round(
-                (a.steps / wx["t"]) / out["fp64_steps_per_s"], 3)
-    if errs:
-        out["rel_err_vs_tight_fp64"] = errs
+                wx["steps_per_s"] / res["fp64"]["steps_per_s"], 3)
+    if "mixed_tol_1e-8" in res:
+        m8, f8 = res["mixed_tol_1e-8"], res["fp64_tol_1e-8"]
+        out["tol_1e-8"] = {"note": "both solvers at the configuration's literal tol 1e-8: u^M "
+                                   "misses the 1e-8 error target (rel_err_vs_tight_fp64)",
+                           "mixed_steps_per_s": round(m8["steps_per_s"], 3),
+                           "fp64_steps_per_s": round(f8["steps_per_s"], 3),
+                           "speedup": round(m8["steps_per_s"] / f8["steps_per_s"], 3),
+                           "iters_mixed_inner": m8["iters"], "iters_fp64": f8["iters"]}
+    out["roofline_kernels"] = {"mixed": ktab}
+    if "fp64" in res:
+        out["roofline_kernels"]["fp64"] = kernel_table(res["fp64"]["prof"], peak["gbps"])
     if not a.no_secondary:
         log("two-sided GMRES ...")
-        out["two_sided"] = two_sided(w, F, u0, a.steps, a.warmup)
+        out["two_sided"] = two_sided(w, F, u0, min(a.steps, 8), a.warmup, tol)
         out["comparators"] = comparators(w, F, u0)
-        out["matvec_fp64"] = matvec_bench(w)
+        out["operators"] = operator_bench(w, peak["gbps"])
         out["secondary"] = secondary_symmetric(a)
     if not a.no_learned:
         out["learned"] = learned_workload(a)
     if not a.no_batched:
         out["batched"] = batched_workload(a)
-    out["kernels"] = {k: {"launches": v["launches"], "avg_ms": round(v["avg_ms"], 5),
-                          "gbps": round(v["gbps"], 1), "total_ms": round(v["total_ms"], 3)}
-                      for k, v in prof.items()}
-    if not a.no_cpu:
-        log("cpu baseline (oracle, 1 step) ...")
+    if not a.no_cpu and "fp64" in res:
+        log("cpu baseline (oracle, per-iteration sample) ...")
         wc = workloads.config_3d_nonsymmetric(seed=0, n=a.n, M=16)
-        out["cpu_baseline"] = cpu_baseline(wc)
+        its = res["fp64"]["iters"][:15]
+        out["cpu_baseline"] = cpu_baseline(wc, float(np.mean(its)))
     print(json.dumps(out), flush=True)
     return 0
 

@@ -194,6 +194,14 @@ fsd_status fsd_apply_rhs(fsd_problem prob, const double* d_u, const double* d_F,
 /* z = P^{-1} r = S_N Lambda^{-1} S_N r  (Section 3, ``diag_tau_pre``). */
 fsd_status fsd_apply_Pinv(fsd_problem prob, const double* d_r, double* d_z);
 
+/* y = A x as the float32 inner solve of a FSD_PREC_MIXED problem applies it
+ * (Section 2, ``linear_sys``): x rounded to float32, the three float32
+ * Toeplitz line passes (float32 twiddles and circulant spectra, float32
+ * arithmetic), y widened to float64.  x, y: dense device arrays of N
+ * doubles; must not alias.  Errors: FSD_EINVAL for a float64-only problem
+ * or a null vector, FSD_ENOTBOUND, FSD_EHIP. */
+fsd_status fsd_apply_A32(fsd_problem prob, const double* d_x, double* d_y);
+
 /* z = P^{-1} r as the float32 inner solve of a FSD_PREC_MIXED problem
  * applies it: r rounded to float32, the float32 passes (DST-I by FFT, or by
  * the bf16 matrix-core product on axes with n <= 256 when dst_mfma is set),
@@ -245,6 +253,16 @@ typedef struct {
 
 fsd_status fsd_profile_enable(fsd_problem prob, int on);
 int fsd_profile_read(fsd_problem prob, fsd_profile_entry* out, int max);
+
+/* Streaming device-to-device copy of `bytes` bytes (16-byte vector loads and
+ * stores, four in flight per thread) on `stream` (hipStream_t as void*;
+ * NULL = default stream).  Not part of the method: a plain copy of known
+ * size that measures the HBM bandwidth this device attains (the measured
+ * peak the line passes are compared with, next to the datasheet figure) and
+ * calibrates rocprofv3's FETCH_SIZE / WRITE_SIZE counters.  bytes and both
+ * addresses must be multiples of 16 and the buffers must not overlap
+ * (FSD_EINVAL otherwise).  Returns after enqueueing. */
+fsd_status fsd_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
 
 /* Messages. */
 const char* fsd_status_string(fsd_status s);

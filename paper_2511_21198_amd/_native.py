@@ -89,6 +89,7 @@ SIGNATURES = {
     "fsd_apply_A": (C.c_int, [_VP, _VP, _VP]),
     "fsd_apply_rhs": (C.c_int, [_VP, _VP, _VP, _VP]),
     "fsd_apply_Pinv": (C.c_int, [_VP, _VP, _VP]),
+    "fsd_apply_A32": (C.c_int, [_VP, _VP, _VP]),
     "fsd_apply_Pinv32": (C.c_int, [_VP, _VP, _VP]),
     "fsd_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     "fsd_cn_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)]),
@@ -97,6 +98,7 @@ SIGNATURES = {
     "fsd_reset_history": (C.c_int, [_VP]),
     "fsd_profile_enable": (C.c_int, [_VP, C.c_int]),
     "fsd_profile_read": (C.c_int, [_VP, C.POINTER(ProfileEntry), C.c_int]),
+    "fsd_hbm_copy": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
     "fsd_status_string": (C.c_char_p, [C.c_int]),
     "fsd_last_error": (C.c_char_p, []),
     "fsd_version": (C.c_char_p, []),

@@ -595,9 +595,11 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
 // ------------------------------------------------------------ GMRES
 // Left-preconditioned restarted GMRES (Section 3.2, ``one_side_system``):
 // stop when ||P^{-1}(b - A x_k)||_2 <= tol ||P^{-1} b||_2.
+// w_given (with x0_zero): v.w already holds P^{-1} b (P^{-1/2} b), applied
+// by the caller; the mixed-precision loop passes its float64 P^{-1} r.
 template <typename T>
 fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
-                 double abs_tol, SolveOut& out) {
+                 double abs_tol, SolveOut& out, bool w_given = false) {
     Vecs<T>& v = vecs<T>(P);
     hipStream_t s = P->stream;
     const long Np = P->Np;
@@ -614,7 +616,7 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     // preconditioner application is P^{-1/2}
     const bool split = P->solver == FSD_SOLVER_PGMRES2;
     // ||P^{-1} b|| (||P^{-1/2} b||)
-    FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
+    if (!(w_given && x0_zero)) FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
     HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
     HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s));
     if (x0_zero) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
@@ -728,10 +730,10 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
 // abs_tol): ||r|| vs ||b|| for PCG, ||P^{-1} r|| vs ||P^{-1} b|| for GMRES.
 template <typename T>
 fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
-                  SolveOut& o, double abs_tol = 0.0) {
+                  SolveOut& o, double abs_tol = 0.0, bool w_given = false) {
     P->prof_tag = -1;
     if (P->solver == FSD_SOLVER_PGMRES || P->solver == FSD_SOLVER_PGMRES2)
-        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
+        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o, w_given);
     return pcg<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
 }
 
@@ -747,37 +749,45 @@ fsd_status true_residual(fsd_problem P, const double* x, const double* b, double
     return FSD_OK;
 }
 
-fsd_status norm2(fsd_problem P, const double* b, double* nrm) {
-    hipStream_t s = P->stream;
-    int np = 0;
-    HIP_TRY(ctrl_init(P->ctrl, 0.0, 1, P->restart, s));
-    HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
-    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
-    FSD_TRY(read_ctrl(P));
-    *nrm = std::sqrt(P->h_ctrl->pq);
-    return FSD_OK;
-}
+// The norms of one defect-correction step, read with one host
+// synchronisation: r = b - A x written to r and ||r||; for the
+// preconditioned stopping test of GMRES (pz non-null) also z = P^{-1} r
+// (P^{-1/2} r for the two-sided system) written to pz and ||z||, all in
+// float64; at the start of a solve (start) also ||b|| and, with pz,
+// ||P^{-1} b|| (P^{-1} b goes through pz, which P^{-1} r then overwrites).
+struct OuterNorms {
+    double b = 0.0, pb = 0.0, r = 0.0, pr = 0.0;
+};
 
-// ||b||, ||r|| with r = b - A x written to r, and (with pb) ||pb|| (a
-// float32 vector, float64 accumulation), read with one host
-// synchronisation: the start of the mixed-precision loop.
-fsd_status start_norms(fsd_problem P, const double* x, const double* b, double* r, const float* pb,
-                       double* bnorm, double* rnorm, double* pbnorm) {
+fsd_status outer_norms(fsd_problem P, const double* x, const double* b, double* r, double* pz,
+                       bool start, bool split, OuterNorms& nrm) {
     hipStream_t s = P->stream;
     int np = 0;
     HIP_TRY(ctrl_init(P->ctrl, 0.0, 1, P->restart, s));
-    HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
-    HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_BB, s));
-    if (pb) {
-        HIP_TRY(vec_dot<float>(pb, pb, P->Np, P->partials, nullptr, &np, s));
-        HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RZ, s));
+    if (start) {
+        HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
+        HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_BB, s));
+        if (pz) {
+            FSD_TRY(op_precond<double>(P, b, pz, nullptr, nullptr, nullptr, split));
+            HIP_TRY(vec_dot<double>(pz, pz, P->Np, P->partials, nullptr, &np, s));
+            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RZ, s));
+        }
     }
     FSD_TRY(first_residual<double>(P, x, b, r, nullptr, &np));
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
+    if (pz) {
+        FSD_TRY(op_precond<double>(P, r, pz, nullptr, nullptr, nullptr, split));
+        HIP_TRY(vec_dot<double>(pz, pz, P->Np, P->partials, nullptr, &np, s));
+        HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RR, s));
+    }
     FSD_TRY(read_ctrl(P));
-    *bnorm = std::sqrt(P->h_ctrl->bb);
-    *rnorm = std::sqrt(P->h_ctrl->pq);
-    if (pb) *pbnorm = std::sqrt(P->h_ctrl->rz);
+    const Ctrl& c = *P->h_ctrl;
+    if (start) {
+        nrm.b = std::sqrt(c.bb);
+        if (pz) nrm.pb = std::sqrt(c.rz);
+    }
+    nrm.r = std::sqrt(c.pq);
+    if (pz) nrm.pr = std::sqrt(c.rr);
     return FSD_OK;
 }
 
@@ -797,63 +807,47 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         S.converged = o.status == FSD_OK;
     } else {
         // Defect correction: r = b - A x (float64); solve A d = r in float32
-        // to inner_tol; x += d.  The stopping test is the float64 solver's:
-        // ||b - A x|| <= tol ||b|| for PCG, ||P^{-1}(b - A x)|| <= tol ||P^{-1} b||
-        // for left GMRES.  The inner solve also stops once the outer test
-        // is met (absolute floor abs_tol), so the last correction is no more
-        // accurate than needed; for GMRES its first step, ||P^{-1} r||, is
-        // the outer test of the current iterate.
+        // to inner_tol; x += d.  The stopping test is the float64 solver's,
+        // evaluated in float64 on the true residual: ||b - A x|| <= tol ||b||
+        // for PCG, ||P^{-1}(b - A x)|| <= tol ||P^{-1} b|| for left GMRES
+        // (P^{-1/2} for the two-sided system), both preconditioned norms
+        // with the float64 preconditioner.  The float64 P^{-1} r is also the
+        // first Arnoldi vector of the next inner solve (rounded to float32),
+        // so the inner GMRES does not apply its own preconditioner to r.
+        // The inner solve also stops once the outer test is met (absolute
+        // floor abs_tol), so the last correction is no more accurate than
+        // needed.
         Vecs<float>& f = P->v32;
         double* r = P->v64.r;
-        // GMRES tests the preconditioned residual: P^{-1} r (left), P^{-1/2} r
-        // (two-sided)
+        double* pz = nullptr;
         const bool split = P->solver == FSD_SOLVER_PGMRES2;
         const bool left = P->solver == FSD_SOLVER_PGMRES || split;
+        if (left) pz = P->v64.z;
         if (x0_zero) HIP_TRY(vec_fill<double>(x, P->Np, 0.0, P->stream));
         long iters = 0;
         int outer = 0;
         int status = FSD_ENOTCONV;
-        double relres = 0.0, bnorm = 0.0, pbnorm = 0.0, prec_rel = 0.0;
-        // ||P^{-1} b|| with the float32 preconditioner: the numerator of the
-        // test, ||P^{-1} r||, is the first step of each inner solve, which
-        // applies the same float32 preconditioner
-        if (left) {
-            HIP_TRY((vec_cast<double, float>(b, f.b, P->Np, 1.0, P->stream)));
-            FSD_TRY(op_precond<float>(P, f.b, f.w, nullptr, nullptr, nullptr, split));
-        }
+        double relres = 0.0, prec_rel = 0.0;
+        OuterNorms nrm;
         for (bool start = true;; start = false) {
-            double rnorm = 0.0;
-            if (start)
-                FSD_TRY(start_norms(P, x, b, r, left ? f.w : nullptr, &bnorm, &rnorm, &pbnorm));
-            else
-                FSD_TRY(true_residual(P, x, b, r, &rnorm));
-            relres = bnorm > 0.0 ? rnorm / bnorm : rnorm;
-            if (!std::isfinite(relres)) { status = FSD_ENONFINITE; break; }
-            if (rnorm == 0.0 || (!left && relres <= tol)) { status = FSD_OK; break; }
-            if (outer >= P->p.max_outer || iters >= maxit) {
-                if (left) {
-                    double pr = 0.0;
-                    FSD_TRY(op_precond<double>(P, r, P->v64.z, nullptr, nullptr, nullptr, split));
-                    FSD_TRY(norm2(P, P->v64.z, &pr));
-                    prec_rel = pbnorm > 0.0 ? pr / pbnorm : pr;
-                    if (prec_rel <= tol) status = FSD_OK;
-                }
-                break;
-            }
+            FSD_TRY(outer_norms(P, x, b, r, pz, start, split, nrm));
+            relres = nrm.b > 0.0 ? nrm.r / nrm.b : nrm.r;
+            prec_rel = left ? (nrm.pb > 0.0 ? nrm.pr / nrm.pb : nrm.pr) : relres;
+            if (!std::isfinite(relres) || !std::isfinite(prec_rel)) { status = FSD_ENONFINITE; break; }
+            if (nrm.r == 0.0 || prec_rel <= tol) { status = FSD_OK; break; }
+            if (outer >= P->p.max_outer || iters >= maxit) break;
+            const double rnorm = nrm.r;
             HIP_TRY((vec_cast<double, float>(r, f.b, P->Np, 1.0 / rnorm, P->stream)));
-            const double ref = left ? pbnorm : bnorm;
+            if (left) HIP_TRY((vec_cast<double, float>(pz, f.w, P->Np, 1.0 / rnorm, P->stream)));
+            const double ref = left ? nrm.pb : nrm.b;
             SolveOut o;
             const int saved = P->last_iters;
             const int slot = std::min(outer, 3);
             P->last_iters = P->last_inner_iters[slot];
             FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o,
-                                  tol * ref / rnorm));
+                                  tol * ref / rnorm, left));
             P->last_inner_iters[slot] = P->last_iters;
             P->last_iters = saved;
-            if (left) {
-                prec_rel = pbnorm > 0.0 ? o.bnorm * rnorm / pbnorm : 0.0;
-                if (prec_rel <= tol) { status = FSD_OK; break; }   // x already passes
-            }
             iters += o.iters;
             ++outer;
             if (o.status == FSD_ENONFINITE || o.status == FSD_EBREAKDOWN) { status = o.status; break; }
@@ -1149,6 +1143,18 @@ fsd_status fsd_apply_Pinv(fsd_problem P, const double* d_r, double* d_z) {
     return FSD_OK;
 }
 
+fsd_status fsd_apply_A32(fsd_problem P, const double* d_x, double* d_y) {
+    FSD_TRY(check_bound(P));
+    if (!d_x || !d_y) return fail(FSD_EINVAL, "null vector");
+    if (!P->mixed) return fail(FSD_EINVAL, "float32 operators exist for mixed precision only");
+    Vecs<float>& v = P->v32;
+    HIP_TRY(vec_pack<float>(d_x, v.p, P->ax[0].n, P->P1, P->rows, 1.0, P->stream));
+    MatvecOpts o;
+    FSD_TRY(op_matvec<float>(P, v.p, v.q, o, nullptr, nullptr, nullptr, nullptr, nullptr));
+    HIP_TRY(vec_unpack<float>(v.q, d_y, P->ax[0].n, P->P1, P->rows, P->stream));
+    return FSD_OK;
+}
+
 fsd_status fsd_apply_Pinv32(fsd_problem P, const double* d_r, double* d_z) {
     FSD_TRY(check_bound(P));
     if (!d_r || !d_z) return fail(FSD_EINVAL, "null vector");
@@ -1218,6 +1224,16 @@ fsd_status fsd_cn_step(fsd_problem P, const double* d_u_prev, const double* d_F,
     if (stt == FSD_EHIP) return stt;
     HIP_TRY(vec_unpack<double>(v.x, d_u_next, n1, P->P1, P->rows, s));
     return stt;
+}
+
+fsd_status fsd_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* stream) {
+    if (!d_src || !d_dst) return fail(FSD_EINVAL, "null buffer");
+    if ((bytes & 15) != 0 || ((uintptr_t)d_src & 15) != 0 || ((uintptr_t)d_dst & 15) != 0)
+        return fail(FSD_EINVAL, "bytes and both addresses must be multiples of 16");
+    const uintptr_t a = (uintptr_t)d_src, b = (uintptr_t)d_dst;
+    if (a < b + bytes && b < a + bytes) return fail(FSD_EINVAL, "source and destination overlap");
+    HIP_TRY(stream_copy(d_src, d_dst, bytes, (hipStream_t)stream));
+    return FSD_OK;
 }
 
 fsd_status fsd_reset_history(fsd_problem P) {

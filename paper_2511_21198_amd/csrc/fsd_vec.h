@@ -20,6 +20,7 @@ enum ScalarOp : int {
     SC_STORE = 6,  // pq = S (plain reduction result for the host)
     SC_STORE_BB = 7,  // bb = S (a second plain result, read with the first)
     SC_STORE_RZ = 8,  // rz = S (a third one)
+    SC_STORE_RR = 9,  // rr = S (a fourth one)
 };
 
 int vec_grid(long N);
@@ -48,6 +49,8 @@ template <typename T>
 hipError_t vec_fill(T* x, long N, T v, hipStream_t s);
 template <typename T>
 hipError_t vec_copy(const T* a, T* b, long N, hipStream_t s);
+// Streaming copy of bytes (a multiple of 16; 16-byte aligned pointers).
+hipError_t stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s);
 // have != 0: x <- 2 x - up and up <- old x; have == 0: up <- x.
 hipError_t vec_extrap(double* x, double* up, long N, int have, hipStream_t s);
 // abs2: absolute floor of the stopping threshold, thresh = max(tol2 bb, abs2).

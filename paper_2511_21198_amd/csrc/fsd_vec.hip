@@ -207,6 +207,22 @@ __global__ __launch_bounds__(VT) void k_copy(const T* __restrict__ a, T* __restr
     for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) b[e] = a[e];
 }
 
+// Streaming copy of n 16-byte words: four independent loads per thread
+// before the stores (the HBM bandwidth a plain copy attains).
+__global__ __launch_bounds__(VT) void k_stream_copy(const uint4* __restrict__ a,
+                                                    uint4* __restrict__ b, long n) {
+    const long stride = (long)gridDim.x * VT;
+    long e = blockIdx.x * (long)VT + threadIdx.x;
+    for (; e + 3 * stride < n; e += 4 * stride) {
+        const uint4 v0 = a[e], v1 = a[e + stride], v2 = a[e + 2 * stride], v3 = a[e + 3 * stride];
+        b[e] = v0;
+        b[e + stride] = v1;
+        b[e + 2 * stride] = v2;
+        b[e + 3 * stride] = v3;
+    }
+    for (; e < n; e += stride) b[e] = a[e];
+}
+
 __global__ __launch_bounds__(VT) void k_extrap(double* __restrict__ x, double* __restrict__ up, long N,
                                                int have) {
     for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) {
@@ -282,6 +298,9 @@ __global__ __launch_bounds__(VT) void k_scalar(Ctrl* c, const double* __restrict
             break;
         case SC_STORE_RZ:
             c->rz = S;
+            break;
+        case SC_STORE_RR:
+            c->rr = S;
             break;
         default:
             break;
@@ -363,6 +382,14 @@ hipError_t vec_fill(T* x, long N, T v, hipStream_t s) {
 template <typename T>
 hipError_t vec_copy(const T* a, T* b, long N, hipStream_t s) {
     hipLaunchKernelGGL((k_copy<T>), dim3(vgrid(N)), dim3(VT), 0, s, a, b, N);
+    return hipGetLastError();
+}
+hipError_t stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    const long n = (long)(bytes / 16);
+    if (n == 0) return hipSuccess;
+    const long g = std::min<long>((n + VT - 1) / VT, 8192);
+    hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)g), dim3(VT), 0, s,
+                       reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n);
     return hipGetLastError();
 }
 hipError_t vec_extrap(double* x, double* up, long N, int have, hipStream_t s) {

@@ -124,6 +124,12 @@ class Problem:
         check(lib.fsd_apply_Pinv(self._h, _ptr(r), _ptr(out)), "fsd_apply_Pinv")
         return out
 
+    def apply_A32(self, x: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        """The float32 matvec of the mixed-precision inner solve."""
+        out = self._out(out)
+        check(lib.fsd_apply_A32(self._h, _ptr(x), _ptr(out)), "fsd_apply_A32")
+        return out
+
     def apply_Pinv32(self, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         """The float32 preconditioner of the mixed-precision inner solve."""
         out = self._out(out)
@@ -180,3 +186,18 @@ class Problem:
         eta = C.c_double()
         check(lib.fsd_get_coefficients(self._h, axis, q, lam, C.byref(eta)), "fsd_get_coefficients")
         return list(q), list(lam), eta.value
+
+
+def hbm_copy(src: torch.Tensor, dst: torch.Tensor, stream: Optional[torch.cuda.Stream] = None):
+    """fsd_hbm_copy: streaming copy of src into dst (contiguous CUDA tensors
+    of the same byte size, a multiple of 16) on `stream` (default: the
+    current stream)."""
+    nbytes = src.numel() * src.element_size()
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("expected contiguous CUDA tensors")
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("source and destination sizes differ")
+    st = stream or torch.cuda.current_stream(src.device)
+    check(lib.fsd_hbm_copy(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                           C.c_void_p(st.cuda_stream)), "fsd_hbm_copy")
+    return dst

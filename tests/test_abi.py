@@ -123,6 +123,11 @@ def test_null_and_unbound(nat):
     assert s == nat.OK
     x = C.c_void_p(16)
     assert nat.lib.fsd_apply_A(h, x, x) == nat.ENOTBOUND
+    assert nat.lib.fsd_apply_A32(h, x, x) == nat.ENOTBOUND
+    # argument checks of the stream copy come before any device work
+    assert nat.lib.fsd_hbm_copy(None, x, 16, None) == nat.EINVAL
+    assert nat.lib.fsd_hbm_copy(C.c_void_p(16), C.c_void_p(4096), 24, None) == nat.EINVAL
+    assert nat.lib.fsd_hbm_copy(C.c_void_p(16), C.c_void_p(32), 64, None) == nat.EINVAL
     assert nat.lib.fsd_bind(h, None, 0, None) == nat.EINVAL
     assert nat.lib.fsd_bind(h, C.c_void_p(256), 16, None) == nat.ESMALLWS
     assert nat.lib.fsd_bind(h, C.c_void_p(257), 1 << 40, None) == nat.EINVAL

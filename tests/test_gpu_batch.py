@@ -1,6 +1,6 @@
 """The batched executor (include/fsd_batch.h) on the GPU: every problem's
 result is bitwise the one of its own fsd_cn_step, whatever the lane count;
-small members also match the float64 oracle."""
+small float64 and mixed-precision members also match the float64 oracle."""
 import numpy as np
 import pytest
 
@@ -91,5 +91,48 @@ def test_batch_members_match_oracle(mods):
                          list(kw["kminus"]), T=1.0, M=kw["M"])
         ur, _ = cn.run(orc, u0.cpu().numpy(), lambda m: F.cpu().numpy(), tol=1e-13,
                        solver=kw["solver"])
-        g = ug.cpu().numpy()
-        assert np.linalg.norm(g - ur) / np.linalg.norm(ur) <= 1e-10
+        _close(ug.cpu().numpy(), ur, 1e-10)
+
+
+def _close(a, b, bound):
+    """Relative error in the 2-norm and in the max-norm (max |a-b| / max |b|)."""
+    e2 = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    em = float(np.abs(a - b).max() / np.abs(b).max())
+    assert e2 <= bound and em <= bound, (e2, em, bound)
+
+
+# Mixed-precision members (the float32 inner solves inside float64 defect
+# correction, PCG and left GMRES, 2D and 3D) solved tightly in a batch with a
+# float64 member: each against the oracle's tightly solved steps, to the
+# 1e-8 bound of the mixed-precision single-problem runs.
+MIXED_MEMBERS = [
+    dict(dim=2, n=(255, 31), delta=(0.7, 0.2), kplus=(1.5, 0.7), kminus=(0.6, 1.1), M=4,
+         solver="gmres", precision="mixed", tol=1e-12, inner_tol=1e-5),
+    dict(dim=3, n=(47, 47, 23), delta=(0.5, 0.4, 0.3), kplus=(1, 1, 1), kminus=(1, 1, 1), M=4,
+         solver="pcg", precision="mixed", tol=1e-12, inner_tol=1e-5),
+    dict(dim=3, n=(31, 15, 63), delta=(0.3, 0.6, 0.8), kplus=(1, 2, 1), kminus=(2, 1, 1), M=4,
+         solver="gmres", precision="mixed", tol=1e-12, inner_tol=1e-3),
+    dict(dim=2, n=(31, 15), delta=(0.4, 0.8), kplus=(1.2, 0.9), kminus=(0.5, 1.4), M=4,
+         solver="gmres", precision="fp64", tol=1e-13),
+]
+
+
+def test_batch_mixed_members_match_oracle(mods):
+    Batch, _ = mods
+    us, Fs = [], []
+    for i, kw in enumerate(MIXED_MEMBERS):
+        shape = tuple(reversed(kw["n"]))
+        us.append(torch.from_numpy(workloads.random_grid(shape, 400 + i)).cuda())
+        Fs.append(torch.from_numpy(workloads.random_grid(shape, 500 + i)).cuda())
+    bt = Batch(MIXED_MEMBERS, streams=2)
+    u = us
+    for _ in range(4):
+        u, st = bt.cn_step(u, Fs)
+        u = [x.clone() for x in u]
+        assert all(s["converged"] == 1 for s in st)
+    for kw, u0, F, ug in zip(MIXED_MEMBERS, us, Fs, u):
+        orc = op.Problem(kw["dim"], list(kw["n"]), list(kw["delta"]), list(kw["kplus"]),
+                         list(kw["kminus"]), T=1.0, M=kw["M"])
+        ur, _ = cn.run(orc, u0.cpu().numpy(), lambda m: F.cpu().numpy(), tol=1e-13,
+                       solver=kw["solver"])
+        _close(ug.cpu().numpy(), ur, 1e-8 if kw["precision"] == "mixed" else 1e-10)

@@ -94,6 +94,16 @@ def config_3d_nonsymmetric(seed: int = 0, n: int = 255, M: int = 16) -> Workload
                     [0.5, 1.0, 0.3], M, 1.0, 1e-8, "gmres", np.zeros_like(F), F)
 
 
+# Solver settings of the benchmark's headline workload (3D non-symmetric
+# 255^3, left GMRES(20) from u^{m-1}): the relative tolerance of both the
+# float64 and the mixed-precision solvers is the paper's 1e-9 (Section 4),
+# which keeps u^M within 1e-8 of the tightly solved trajectory in the
+# 2-norm and in the max-norm (at 1e-8 the per-step solve errors add up over
+# the 16 steps to 2e-8 in the 2-norm and 7e-8 to 1.2e-7 in the max-norm);
+# inner tolerance and outer-step limit of the float32 solves.
+HEADLINE_SOLVER = dict(tol=1e-9, inner_tol=1e-3, max_outer=8, restart=20, x0="prev")
+
+
 def config_batched(count: int = 64, base_seed: int = 1000,
                    sizes_2d=(127, 255, 511, 1023), sizes_3d=(63, 95, 127)):
     """Batched instances: instance i uses seed base_seed + i; 2D for the first
