@@ -191,6 +191,24 @@ fsd_status fsd_apply_A(fsd_problem prob, const double* d_x, double* d_y);
 fsd_status fsd_apply_rhs(fsd_problem prob, const double* d_u, const double* d_F,
                          double* d_b);
 
+/* y = A x exactly as fsd_apply_A computes it (same kernels, bitwise equal
+ * results), for callers that cannot allocate device memory: the packed
+ * input and output and the pass intermediates are not taken from the
+ * problem's workspace but from a library-owned static device array of
+ * fsd_noalloc_scratch_bytes() bytes (64 MiB), one per GPU, held until the
+ * process ends.  The call allocates nothing (no hipMalloc, no allocating
+ * library routine); it still needs a bound problem (its tables and stream).
+ * Limit: six padded vectors of n1' n2 (n3) doubles must fit the array
+ * (n1' = n1 rounded up to 32; about 1.39 million values, e.g. 95^3 or
+ * 1023 x 1023); larger grids return FSD_EUNSUPPORTED.  Each call clears the
+ * part it uses, so calls are independent; calls that overlap on one GPU
+ * (several streams or threads) share the array and race.  Errors as
+ * fsd_apply_A. */
+fsd_status fsd_apply_A_noalloc(fsd_problem prob, const double* d_x, double* d_y);
+
+/* Bytes of the static scratch array behind fsd_apply_A_noalloc. */
+size_t fsd_noalloc_scratch_bytes(void);
+
 /* z = P^{-1} r = S_N Lambda^{-1} S_N r  (Section 3, ``diag_tau_pre``). */
 fsd_status fsd_apply_Pinv(fsd_problem prob, const double* d_r, double* d_z);
 

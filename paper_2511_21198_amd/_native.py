@@ -90,6 +90,8 @@ SIGNATURES = {
     "fsd_apply_rhs": (C.c_int, [_VP, _VP, _VP, _VP]),
     "fsd_apply_Pinv": (C.c_int, [_VP, _VP, _VP]),
     "fsd_apply_A32": (C.c_int, [_VP, _VP, _VP]),
+    "fsd_apply_A_noalloc": (C.c_int, [_VP, _VP, _VP]),
+    "fsd_noalloc_scratch_bytes": (C.c_size_t, []),
     "fsd_apply_Pinv32": (C.c_int, [_VP, _VP, _VP]),
     "fsd_solve": (C.c_int, [_VP, _VP, _VP, C.POINTER(Stats)]),
     "fsd_cn_step": (C.c_int, [_VP, _VP, _VP, _VP, _VP, C.POINTER(Stats)]),

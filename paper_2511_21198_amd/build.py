@@ -23,7 +23,8 @@ INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = ["fsd_lines_f64.hip", "fsd_lines_f32.hip", "fsd_gdst.hip", "fsd_vec.hip", "fsd_gmres.hip",
            "fsd_circ.hip",
-           "fsd_nn.hip", "fsd_plan.cpp", "fsd_host.cpp", "fsd_nn_host.cpp", "fsd_batch.cpp"]
+           "fsd_nn.hip", "fsd_plan.cpp", "fsd_host.cpp", "fsd_nn_host.cpp", "fsd_batch.cpp",
+           "fsd_noalloc.cpp"]
 
 # Packed FP32 instructions are disabled for all device code: some of their
 # forms have given wrong results now and then on this hardware, with no

@@ -228,12 +228,15 @@ struct MatvecOpts {
     int pro = PRO_NONE;
 };
 
+// tmp: the four pass intermediates (default: the workspace's).
 template <typename T>
 fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, const T* dot_p,
-                     const T* bvec, T* pro_p, const Ctrl* ctrl, int* nparts) {
+                     const T* bvec, T* pro_p, const Ctrl* ctrl, int* nparts,
+                     T* const* tmp = nullptr) {
     Tables<T>& tb = tabs<T>(P);
     Vecs<T>& v = vecs<T>(P);
-    T *c = v.t[0], *a = v.t[1], *d = v.t[2], *e = v.t[3];
+    T* const* t = tmp ? tmp : v.t;
+    T *c = t[0], *a = t[1], *d = t[2], *e = t[3];
     ToepArgs<T> A{};
     A.g = geo_x(P);
     A.u_fft = in;
@@ -933,6 +936,16 @@ fsd_status upload_all(fsd_problem P, Tables<T>& t) {
 }
 
 }  // namespace
+
+namespace fsd {
+// y = A x on the padded internal layout with caller-chosen intermediates
+// (four vectors of Np doubles): the float64 matvec of fsd_apply_A.
+fsd_status matvec64_with(fsd_problem P, const double* x, double* y, double* const tmp[4]) {
+    MatvecOpts o;
+    return op_matvec<double>(P, x, y, o, nullptr, nullptr, nullptr, nullptr, nullptr, tmp);
+}
+fsd_status require_bound(fsd_problem P) { return check_bound(P); }
+}  // namespace fsd
 
 // ====================================================================== ABI
 

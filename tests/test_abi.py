@@ -123,7 +123,9 @@ def test_null_and_unbound(nat):
     assert s == nat.OK
     x = C.c_void_p(16)
     assert nat.lib.fsd_apply_A(h, x, x) == nat.ENOTBOUND
+    assert nat.lib.fsd_apply_A_noalloc(h, x, x) == nat.ENOTBOUND
     assert nat.lib.fsd_apply_A32(h, x, x) == nat.ENOTBOUND
+    assert nat.lib.fsd_noalloc_scratch_bytes() == 64 << 20
     # argument checks of the stream copy come before any device work
     assert nat.lib.fsd_hbm_copy(None, x, 16, None) == nat.EINVAL
     assert nat.lib.fsd_hbm_copy(C.c_void_p(16), C.c_void_p(4096), 24, None) == nat.EINVAL
