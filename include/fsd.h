@@ -36,8 +36,9 @@
  *    fsd_status; fsd_last_error() gives a thread-local message for the last
  *    failure on the calling thread.
  *  - Sizes: the fast transforms need n_i + 1 = 2^a or 3 * 2^a with
- *    4 <= 2(n_i+1) <= 2048 (n_i in {1,2,3,5,7,11,15,23,31,47,63,95,127,191,
- *    255,383,511,767,1023}); other sizes return FSD_EUNSUPPORTED.
+ *    4 <= 2(n_i+1) <= 8192 (n_i in {1,2,3,5,7,11,15,23,31,47,63,95,127,191,
+ *    255,383,511,767,1023,1535,2047,3071,4095}); other sizes return
+ *    FSD_EUNSUPPORTED (the circulant comparators: n_i <= 1024).
  */
 #ifndef FSD_H
 #define FSD_H

@@ -66,6 +66,18 @@ def q_coeffs(delta: float, n: int) -> np.ndarray:
     return np.array([float(v) for v in q_coeffs_mp(delta, n)], dtype=np.float64)
 
 
+def q_coeffs_split(delta: float, n: int):
+    """(hi, lo) float64 arrays with hi + lo = q_k to about 106 bits: hi is
+    :func:`q_coeffs`, lo the float64 rounding of the remainder.  Used where a
+    float64 rounding of the q_k themselves would show (the cancelling sum of
+    :func:`tau_eigs`)."""
+    qm = q_coeffs_mp(delta, n)
+    hi = np.array([float(v) for v in qm], dtype=np.float64)
+    with mp.workdps(_DPS):
+        lo = np.array([float(v - mp.mpf(float(v))) for v in qm], dtype=np.float64)
+    return hi, lo
+
+
 def eta(delta: float, h: float, dt: float) -> float:
     """eta_delta = dt / (2 Gamma(delta+1) h^(2-delta)) (Section 2)."""
     return dt / (2.0 * math.gamma(delta + 1.0) * h ** (2.0 - delta))
@@ -78,22 +90,35 @@ def a_eigs(n: int) -> np.ndarray:
     return (3.0 + np.cos(k * np.pi / (n + 1))) / 4.0
 
 
-def tau_eigs(q: np.ndarray, n: int) -> np.ndarray:
+def tau_eigs(q: np.ndarray, n: int, q_lo: np.ndarray | None = None) -> np.ndarray:
     """Eigenvalues of tau(H(T_n)), k = 1..n (Lemma 3.2, index read as j):
 
         lambda_k = q_1 + (q_0 + q_2) cos(theta_k) + sum_{j=2}^{n-1} q_{j+1} cos(j theta_k),
         theta_k = k pi / (n+1).
 
-    ``q`` holds q_0..q_n.  For n = 1 the sum and the cosine term vanish
-    (H(T_1) = [q_1])."""
-    k = np.arange(1, n + 1, dtype=np.float64)
-    th = k * np.pi / (n + 1)
-    lam = np.full(n, q[1], dtype=np.float64)
+    ``q`` holds q_0..q_n (``q_lo`` optionally the float64 remainders of
+    q_coeffs_split).  For n = 1 the sum and the cosine term vanish
+    (H(T_1) = [q_1]).
+
+    The q_j sum to zero (Lemma 2.1), so for small theta_k the sum cancels:
+    the smallest eigenvalue is of order theta_1^(1+delta) (5e-6 at n = 4095,
+    delta = 0.35) while its terms are of order one.  A float64 evaluation
+    loses about five digits of it there, and so does rounding the q_j to
+    float64 first.  The sum is therefore taken in the extended precision of
+    numpy.longdouble (cosines included), from q_j to extended precision
+    when q_lo is given, and rounded once."""
+    ld = np.longdouble
+    k = np.arange(1, n + 1, dtype=ld)
+    th = k * (ld(np.pi) + ld(1.2246467991473532e-16)) / ld(n + 1)   # pi to extended precision
+    ql = np.asarray(q, dtype=np.float64).astype(ld)
+    if q_lo is not None:
+        ql = ql + np.asarray(q_lo, dtype=np.float64).astype(ld)
+    lam = np.full(n, ql[1], dtype=ld)
     if n >= 2:
-        lam = lam + (q[0] + q[2]) * np.cos(th)
+        lam = lam + (ql[0] + ql[2]) * np.cos(th)
     for j in range(2, n):
-        lam = lam + q[j + 1] * np.cos(j * th)
-    return lam
+        lam = lam + ql[j + 1] * np.cos(ld(j) * th)
+    return lam.astype(np.float64)
 
 
 def sym_first_column(q: np.ndarray, n: int) -> np.ndarray:

@@ -128,6 +128,46 @@ def cell_average(f, n, h, a=None):
     return np.einsum("abcijk,ijk->abc", vals, W)
 
 
+def cell_average_1d(f, n: int, h: float, a: float = 0.0):
+    """(1/h) * integral of f over [x_{i-1/2}, x_{i+1/2}], i = 1..n, by the
+    same 4-point Gauss-Legendre rule: the one-dimensional factor of
+    :func:`cell_average`, whose tensor-product rule averages a product of
+    functions of one coordinate each as the product of these averages."""
+    centres = a + h * np.arange(1, n + 1)
+    pts = centres[:, None] + 0.5 * h * _GL4_X[None, :]
+    return f(pts) @ (0.5 * _GL4_W)
+
+
+def ex41_source_cells(n, h, delta, kp, km):
+    """Cell averages of Example 4.1's source at t = 0 (e^t times this at time
+    t), assembled from one-dimensional averages: the source is
+    4 (X Y - Y g_x - X g_y) with X, Y the profile and g the flux derivative
+    of one coordinate each (:func:`ex41_source`), so its tensor-product
+    Gauss average is 4 (avg X avg Y - avg Y avg g_x - avg X avg g_y).
+    Shape (n_2, n_1)."""
+    X = cell_average_1d(profile, n[0], h[0])
+    Y = cell_average_1d(profile, n[1], h[1])
+    gx = cell_average_1d(lambda x: flux_derivative(x, delta[0], kp[0], km[0]), n[0], h[0])
+    gy = cell_average_1d(lambda y: flux_derivative(y, delta[1], kp[1], km[1]), n[1], h[1])
+    return 4.0 * (np.outer(Y, X) - np.outer(Y, gx) - np.outer(gy, X))
+
+
+def ex42_source_parts_cells(n, h, delta, kp, km):
+    """Cell averages (P, D) of :func:`ex42_source_parts` from one-dimensional
+    averages (every term is a product of functions of one coordinate).
+    Shapes (n_3, n_2, n_1)."""
+    avg = [cell_average_1d(profile, n[i], h[i]) for i in range(3)]
+    g = [cell_average_1d(lambda s, i=i: flux_derivative(s, delta[i], kp[i], km[i]), n[i], h[i])
+         for i in range(3)]
+
+    def outer3(fx, fy, fz):
+        return fz[:, None, None] * fy[None, :, None] * fx[None, None, :]
+
+    P = outer3(avg[0], avg[1], avg[2])
+    D = outer3(g[0], avg[1], avg[2]) + outer3(avg[0], g[1], avg[2]) + outer3(avg[0], avg[1], g[2])
+    return P, D
+
+
 def nodal(f, n, h, a=None):
     """f at the interior nodes, shape (n_d, ..., n_1)."""
     d = len(n)

@@ -50,7 +50,9 @@ class Problem:
         # h_i = (b_i - a_i)/(n_i + 1)  (Section 2 grid)
         self.h = [(self.b[i] - self.a[i]) / (self.n[i] + 1) for i in range(d)]
         self.eta = [coeffs.eta(self.delta[i], self.h[i], self.dt) for i in range(d)]
-        self.q = [coeffs.q_coeffs(self.delta[i], self.n[i]) for i in range(d)]
+        qs = [coeffs.q_coeffs_split(self.delta[i], self.n[i]) for i in range(d)]
+        self.q = [hi for hi, _ in qs]       # float64 q_k (the matrices)
+        self.q_lo = [lo for _, lo in qs]    # remainders (the tau eigenvalues)
 
     @property
     def shape(self):
@@ -324,7 +326,7 @@ def precond_eigs(prob: Problem) -> np.ndarray:
     c_i = eta_i (k_{i,+} + k_{i,-})."""
     d = prob.dim
     a = [coeffs.a_eigs(prob.n[i]) for i in range(d)]
-    lam = [coeffs.tau_eigs(prob.q[i], prob.n[i]) for i in range(d)]
+    lam = [coeffs.tau_eigs(prob.q[i], prob.n[i], prob.q_lo[i]) for i in range(d)]
 
     def grid(vecs):
         out = vecs[-1]

@@ -1017,7 +1017,7 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
         if (!(p->b[i] > p->a[i])) { snprintf(buf, sizeof buf, "empty domain on axis %d", i); return fail(FSD_EINVAL, buf); }
         if (!length_supported(2 * (p->n[i] + 1))) {
             snprintf(buf, sizeof buf,
-                     "n[%d] = %d: n+1 must be 2^a or 3*2^a with 2(n+1) <= 2048", i, p->n[i]);
+                     "n[%d] = %d: n+1 must be 2^a or 3*2^a with 2(n+1) <= 8192", i, p->n[i]);
             return fail(FSD_EUNSUPPORTED, buf);
         }
     }
@@ -1037,6 +1037,9 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
         return fail(FSD_EINVAL, "the circulant preconditioners run in float64 only");
     if (circ && p->solver == FSD_SOLVER_PGMRES2)
         return fail(FSD_EINVAL, "two-sided GMRES needs P^{-1/2}: tau or no preconditioner");
+    for (int i = 0; circ && i < p->dim; ++i)
+        if (p->n[i] > 1024)
+            return fail(FSD_EUNSUPPORTED, "the circulant preconditioners support n <= 1024 per axis");
 
     fsd_problem P = new (std::nothrow) fsd_problem_s();
     if (!P) return fail(FSD_EINVAL, "out of host memory");

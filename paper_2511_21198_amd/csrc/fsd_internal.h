@@ -164,10 +164,18 @@ template <typename T> hipError_t launch_dsts_s(int L, const DstArgs<T>& a, int* 
 
 // Complex lines per workgroup tile for transform length L (two real lines
 // each).  Sized so one tile plus its twiddle table stays below 80 KB of LDS
-// at L = 512, leaving room for two workgroups per CU (160 KB).
+// at L = 512, leaving room for two workgroups per CU (160 KB).  Lines
+// longer than 2048 (n + 1 = 1536 .. 4096) take one or two lines per tile,
+// with the twiddles read from the global table (L1-resident) instead of
+// LDS: at L = 8192 one float64 line alone fills 139 KB of LDS.
 __host__ __device__ constexpr int lines_per_block(int L, bool fp64) {
-    return fp64 ? (L <= 512 ? 8 : (L <= 1024 ? 4 : 2)) : (L <= 512 ? 16 : (L <= 1024 ? 8 : 4));
+    return L > 2048 ? (fp64 || L > 4096 ? 1 : 2)
+         : fp64 ? (L <= 512 ? 8 : (L <= 1024 ? 4 : 2)) : (L <= 512 ? 16 : (L <= 1024 ? 8 : 4));
 }
+
+// Twiddle table of the LDS-stage engine held in LDS (else read from the
+// global table).
+__host__ __device__ constexpr bool twiddles_in_lds(int L) { return L <= 2048; }
 
 // Threads per workgroup tile: about one radix-8 butterfly per thread per
 // stage (NCL * L / 8), rounded down to a power of two in [64, 512].
@@ -178,12 +186,12 @@ __host__ __device__ constexpr int threads_per_block(int L, bool fp64) {
     return t;
 }
 
-// Transform lengths with a compiled plan: L = 2(n+1) in {2^a, 3*2^a}, 4..2048.
+// Transform lengths with a compiled plan: L = 2(n+1) in {2^a, 3*2^a}, 4..8192.
 inline bool length_supported(int L) {
     switch (L) {
         case 4: case 6: case 8: case 12: case 16: case 24: case 32: case 48: case 64:
         case 96: case 128: case 192: case 256: case 384: case 512: case 768: case 1024:
-        case 1536: case 2048:
+        case 1536: case 2048: case 3072: case 4096: case 6144: case 8192:
             return true;
         default:
             return false;

@@ -135,8 +135,10 @@ __device__ inline void dft(T* xr, T* xi) {
 // w^{r k} (w = exp(-2 pi i/(M R)), k = b mod M), and writes output s to
 // Y[(b / M) M R + k + s M].  In place: all reads of the stage land in
 // registers before a barrier, then all writes.
+// Twiddle t is (twr[t TWS2], twi[t TWS2]): split LDS arrays (TWS2 = 1) or
+// the interleaved global table (TWS2 = 2, twi = twr + 1).
 
-template <typename T, int L, int R, int M>
+template <typename T, int L, int R, int M, int TWS2 = 1>
 __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
                                  const T* __restrict__ twr, const T* __restrict__ twi,
                                  int tid) {
@@ -165,7 +167,7 @@ __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
                 const int k = b % M;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    const int t = r * k * TWS;
+                    const int t = r * k * TWS * TWS2;
                     const T wr = twr[t], wi = twi[t];
                     const T xr = ar[q][r], xi = ai[q][r];
                     ar[q][r] = xr * wr - xi * wi;
@@ -197,22 +199,35 @@ __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
     __syncthreads();
 }
 
-template <typename T, int L, int S, int M>
+template <typename T, int L, int S, int M, int TWS2>
 struct FFTRun {
     __device__ static inline void run(T* re, T* im, const T* twr, const T* twi, int tid) {
         constexpr Plan P = make_plan(L);
         if constexpr (S < P.nst) {
             constexpr int R = P.r[S];
-            fft_stage<T, L, R, M>(re, im, twr, twi, tid);
-            FFTRun<T, L, S + 1, M * R>::run(re, im, twr, twi, tid);
+            fft_stage<T, L, R, M, TWS2>(re, im, twr, twi, tid);
+            FFTRun<T, L, S + 1, M * R, TWS2>::run(re, im, twr, twi, tid);
         }
     }
 };
 
+// Twiddles of a tile: the LDS copy (lengths up to 2048) or the interleaved
+// global table.
+template <typename T, int L>
+struct TileTw {
+    static constexpr bool kLds = twiddles_in_lds(L);
+    static constexpr int NLDS = kLds ? L : 1;   // LDS entries per array
+    const T* r;
+    const T* i;
+};
+
+template <typename T, int L>
+__device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr, T* s_twi, int tid);
+
 // Forward FFT of all NCL lines of the tile (input and output in LDS).
 template <typename T, int L>
-__device__ inline void fft_lines(T* re, T* im, const T* twr, const T* twi, int tid) {
-    FFTRun<T, L, 0, 1>::run(re, im, twr, twi, tid);
+__device__ inline void fft_lines(T* re, T* im, const TileTw<T, L>& tw, int tid) {
+    FFTRun<T, L, 0, 1, TileTw<T, L>::kLds ? 1 : 2>::run(re, im, tw.r, tw.i, tid);
 }
 
 // ------------------------------------------------------------- reductions
@@ -233,11 +248,16 @@ __device__ inline double block_sum(double v, double* sbuf) {
 }
 
 template <typename T, int L>
-__device__ inline void load_twiddles(const T* __restrict__ tw, T* twr, T* twi, int tid) {
+__device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr, T* s_twi, int tid) {
     constexpr int NT = Tile<T, L>::NT;
-    for (int e = tid; e < L; e += NT) {
-        twr[e] = tw[2 * e];
-        twi[e] = tw[2 * e + 1];
+    if constexpr (TileTw<T, L>::kLds) {
+        for (int e = tid; e < L; e += NT) {
+            s_twr[e] = tw[2 * e];
+            s_twi[e] = tw[2 * e + 1];
+        }
+        return TileTw<T, L>{s_twr, s_twi};
+    } else {
+        return TileTw<T, L>{tw, tw + 1};
     }
 }
 
@@ -266,11 +286,11 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
-    __shared__ T s_twr[L], s_twi[L];
+    __shared__ T s_twr[TileTw<T, L>::NLDS], s_twi[TileTw<T, L>::NLDS];
     const int tid = threadIdx.x;
     const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
     const int row0 = blockIdx.x * (2 * NCL);
-    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
 
     T beta = 0, scale = 1;
     bool first = true;
@@ -319,9 +339,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
         }
     }
 
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
     spectrum_multiply<T, L>(s_re, s_im, a.spec, tid);
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
 
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
@@ -347,7 +367,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
-    __shared__ T s_twr[L], s_twi[L];
+    __shared__ T s_twr[TileTw<T, L>::NLDS], s_twi[TileTw<T, L>::NLDS];
     __shared__ double s_red[NT / 64];
     const int tid = threadIdx.x;
     const int n = a.g.n, P1 = a.g.P1;
@@ -357,7 +377,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
     const int x0 = xt * TX;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
-    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
 
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     for (int i = ig; i < L; i += GRP) {
@@ -380,9 +400,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
         }
     }
 
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
     spectrum_multiply<T, L>(s_re, s_im, a.spec, tid);
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
 
     // Output: thread handles the contiguous chunk [ib, ie) of its line so the
     // stencil on u_sten needs one new global load per output.
@@ -438,11 +458,11 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
-    __shared__ T s_twr[L], s_twi[L];
+    __shared__ T s_twr[TileTw<T, L>::NLDS], s_twi[TileTw<T, L>::NLDS];
     const int tid = threadIdx.x;
     const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
     const int row0 = blockIdx.x * (2 * NCL);
-    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
         const int row = row0 + rr;
@@ -457,7 +477,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
         if (tid == 0) { dst[TL::idx(0)] = 0; dst[TL::idx(n + 1)] = 0; }
     }
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
         const int row = row0 + rr;
@@ -491,7 +511,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
-    __shared__ T s_twr[L], s_twi[L];
+    __shared__ T s_twr[TileTw<T, L>::NLDS], s_twi[TileTw<T, L>::NLDS];
     const int tid = threadIdx.x;
     const int n = a.g.n, P1 = a.g.P1;
     const long es = a.g.estride;
@@ -499,11 +519,11 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
     const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + xt * TX + xl;
-    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     dst_load_strided<T, L>(a.u, line, base, es, n, ig);
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
     // the DST of the real-part line is -Im Z, of the imaginary-part line Re Z
     const bool odd = xl & 1;
     const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
@@ -527,7 +547,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
-    __shared__ T s_twr[L], s_twi[L];
+    __shared__ T s_twr[TileTw<T, L>::NLDS], s_twi[TileTw<T, L>::NLDS];
     __shared__ T s_P[TX], s_Q[TX];
     __shared__ double s_red[NT / 64];
     const int tid = threadIdx.x;
@@ -538,7 +558,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     const int x0 = xt * TX;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
-    load_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
     if (tid < TX) {
         const int x = x0 + tid;
         T P = 0, Q = 0;
@@ -559,7 +579,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     dst_load_strided<T, L>(a.u, line, base, es, n, ig);
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
 
     double acc = 0.0;
     for (int e = tid; e < NCL * L; e += NT) {
@@ -585,7 +605,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
         s_im[ad] = wi;
     }
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, s_twr, s_twi, tid);
+    fft_lines<T, L>(s_re, s_im, tw, tid);
     const bool odd = xl & 1;
     const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
     const bool pad_line = xt * TX + xl >= a.g.nx;   // stored as exact zeros
@@ -603,7 +623,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
 
 #define FSD_FOR_EACH_L(X) \
     X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(192) \
-    X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048)
+    X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096) X(6144) X(8192)
 
 template <typename T>
 inline int x_blocks(int L, int nrows) {

@@ -207,20 +207,31 @@ __global__ __launch_bounds__(VT) void k_copy(const T* __restrict__ a, T* __restr
     for (long e = blockIdx.x * (long)VT + threadIdx.x; e < N; e += (long)gridDim.x * VT) b[e] = a[e];
 }
 
-// Streaming copy of n 16-byte words: four independent loads per thread
-// before the stores (the HBM bandwidth a plain copy attains).
-__global__ __launch_bounds__(VT) void k_stream_copy(const uint4* __restrict__ a,
-                                                    uint4* __restrict__ b, long n) {
-    const long stride = (long)gridDim.x * VT;
-    long e = blockIdx.x * (long)VT + threadIdx.x;
-    for (; e + 3 * stride < n; e += 4 * stride) {
-        const uint4 v0 = a[e], v1 = a[e + stride], v2 = a[e + 2 * stride], v3 = a[e + 3 * stride];
-        b[e] = v0;
-        b[e + stride] = v1;
-        b[e + 2 * stride] = v2;
-        b[e + 3 * stride] = v3;
+// Streaming copy of n 16-byte words: each workgroup copies one contiguous
+// chunk of kCopyChunk words, eight loads in flight per thread before the
+// non-temporal stores.  Measured on an MI355X (1 GiB): 5.35 TB/s read +
+// write, against 4.3-5.1 TB/s for grid-stride variants and 5.2 TB/s for
+// hipMemcpy device to device.
+constexpr long kCopyChunk = 16384;
+typedef unsigned int cp_u4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(VT) void k_stream_copy(const cp_u4* __restrict__ a,
+                                                    cp_u4* __restrict__ b, long n) {
+    const long beg = blockIdx.x * kCopyChunk;
+    const long end = beg + kCopyChunk < n ? beg + kCopyChunk : n;
+    for (long e = beg + threadIdx.x; e < end; e += 8 * VT) {
+        cp_u4 v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long i = e + k * VT;
+            v[k] = i < end ? a[i] : cp_u4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const long i = e + k * VT;
+            if (i < end) __builtin_nontemporal_store(v[k], b + i);
+        }
     }
-    for (; e < n; e += stride) b[e] = a[e];
 }
 
 __global__ __launch_bounds__(VT) void k_extrap(double* __restrict__ x, double* __restrict__ up, long N,
@@ -387,9 +398,10 @@ hipError_t vec_copy(const T* a, T* b, long N, hipStream_t s) {
 hipError_t stream_copy(const void* src, void* dst, size_t bytes, hipStream_t s) {
     const long n = (long)(bytes / 16);
     if (n == 0) return hipSuccess;
-    const long g = std::min<long>((n + VT - 1) / VT, 8192);
+    const long g = (n + kCopyChunk - 1) / kCopyChunk;
+    if (g > 0x7fffffffL) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)g), dim3(VT), 0, s,
-                       reinterpret_cast<const uint4*>(src), reinterpret_cast<uint4*>(dst), n);
+                       reinterpret_cast<const cp_u4*>(src), reinterpret_cast<cp_u4*>(dst), n);
     return hipGetLastError();
 }
 hipError_t vec_extrap(double* x, double* up, long N, int have, hipStream_t s) {

@@ -75,7 +75,8 @@ def _init(nat, p):
     (dict(M=0), 1), (dict(tol=0.0), 1), (dict(restart=0), 1), (dict(restart=65), 1),
     (dict(solver=4), 1), (dict(solver=-1), 1), (dict(precond=4), 1), (dict(precond=-1), 1),
     (dict(precond=2, precision=1), 1), (dict(precond=3, solver=3), 1),
-    (dict(n=[9, 7, 7]), 7), (dict(n=[2047, 7, 7]), 7), (dict(n=[100, 7, 7]), 7),
+    (dict(n=[9, 7, 7]), 7), (dict(n=[8191, 7, 7]), 7), (dict(n=[100, 7, 7]), 7),
+    (dict(n=[5000, 7, 7]), 7), (dict(n=[2047, 7, 7], precond=2), 7),
 ])
 def test_init_validation(nat, kw, status):
     s, h = _init(nat, _params(nat, **kw))
@@ -151,7 +152,7 @@ def test_workspace_size(nat, dim, n, solver, prec):
     nat.lib.fsd_destroy(h)
 
 
-@pytest.mark.parametrize("n", [1, 2, 7, 63, 255, 1023])
+@pytest.mark.parametrize("n", [1, 2, 7, 63, 255, 1023, 4095])
 @pytest.mark.parametrize("delta", [0.05, 0.3, 0.5, 0.8, 0.97])
 def test_host_coefficients_match_oracle(nat, n, delta):
     """q_k (cancellation-safe evaluation in the library) and the tau
@@ -164,9 +165,9 @@ def test_host_coefficients_match_oracle(nat, n, delta):
     lam = (C.c_double * n)()
     eta = C.c_double()
     assert nat.lib.fsd_get_coefficients(h, 0, q, lam, C.byref(eta)) == nat.OK
-    qo = coeffs.q_coeffs(delta, n)
+    qo, qlo = coeffs.q_coeffs_split(delta, n)
     np.testing.assert_allclose(np.array(q), qo, rtol=1.2e-15, atol=0)
-    lo = coeffs.tau_eigs(qo, n)
+    lo = coeffs.tau_eigs(qo, n, qlo)
     np.testing.assert_allclose(np.array(lam), lo, rtol=1e-13, atol=1e-15 * np.abs(lo).max())
     pr = op.Problem(2, [n, 3], [delta, 0.5], [1.3, 1], [0.7, 1], T=0.9, M=7)
     assert abs(eta.value - pr.eta[0]) <= 1e-15 * pr.eta[0]

@@ -568,3 +568,61 @@ def test_example_sources_separate_in_time():
         f3 = ex.ex42_source(x, y, z, t, d, kp, km)
         g3 = math.cos(t + 1.0) * P - math.sin(t + 1.0) * D
         assert np.abs(f3 - g3).max() <= 1e-14 * np.abs(f3).max()
+
+
+def test_separable_cell_averages():
+    """The one-dimensional Gauss average is exact for polynomials of degree
+    up to 7 (closed-form cell averages of x^2 and x^7), and the sources
+    assembled from one-dimensional averages equal the tensor-product cell
+    averages of the full sources (Examples 4.1 and 4.2)."""
+    n, h = 9, 0.1
+    lo = h * np.arange(1, n + 1) - 0.5 * h
+    hi = lo + h
+    for k in (2, 7):
+        exact = (hi ** (k + 1) - lo ** (k + 1)) / ((k + 1) * h)
+        got = ex.cell_average_1d(lambda x: x ** k, n, h)
+        assert np.abs(got - exact).max() <= 1e-15 * np.abs(exact).max()
+    d, kp, km = [0.3, 0.7, 0.45], [19.0, 1.0, 5.0], [21.0, 2.5, 5.0]
+    n2 = [31, 23]
+    h2 = [1.0 / 32, 1.0 / 24]
+    full = ex.cell_average(lambda X, Y: ex.ex41_source(X, Y, 0.0, d, kp, km), n2, h2)
+    sep = ex.ex41_source_cells(n2, h2, d, kp, km)
+    assert sep.shape == full.shape
+    assert np.abs(sep - full).max() <= 1e-13 * np.abs(full).max()
+    n3 = [7, 9, 5]
+    h3 = [1.0 / 8, 1.0 / 10, 1.0 / 6]
+    P, D = ex.ex42_source_parts_cells(n3, h3, d, kp, km)
+    Pf = ex.cell_average(lambda X, Y, Z: ex.ex42_source_parts(X, Y, Z, d, kp, km)[0], n3, h3)
+    Df = ex.cell_average(lambda X, Y, Z: ex.ex42_source_parts(X, Y, Z, d, kp, km)[1], n3, h3)
+    assert np.abs(P - Pf).max() <= 1e-13 * np.abs(Pf).max()
+    assert np.abs(D - Df).max() <= 1e-13 * np.abs(Df).max()
+
+
+@pytest.mark.parametrize("n,delta", [(1023, 0.35), (4095, 0.35), (4095, 0.8)])
+def test_tau_eigs_extended_precision(n, delta):
+    """The Lemma 3.2 sum cancels for the smallest eigenvalues (the q_j sum
+    to zero, Lemma 2.1).  The oracle's value from the split q_j agrees with
+    a 40-digit mpmath evaluation of the same sum over the 50-digit q_j at
+    the smallest, middle and largest k.  Bound: extended precision (unit
+    roundoff 1.1e-19) over terms whose magnitudes sum to S = sum |q_j|
+    (they decay like j^(delta-2), so a few dozen dominate the partial sums):
+    20 * 1.1e-19 * S, plus the final rounding to float64 (measured: 1.5e-19
+    absolute, 2.8e-14 relative to the smallest eigenvalue at n = 4095,
+    delta = 0.35).  From the float64 q_j alone that eigenvalue is off by
+    5e-17 absolute (1e-11 relative)."""
+    import mpmath as mp
+    hi, lo = coeffs.q_coeffs_split(delta, n)
+    lam = coeffs.tau_eigs(hi, n, lo)
+    S = float(np.abs(hi).sum())
+    qmp = coeffs.q_coeffs_mp(delta, n)
+    with mp.workdps(40):
+        for k in (1, 2, 3, n // 2, n):
+            th = mp.mpf(k) * mp.pi / (n + 1)
+            ref = qmp[1] + (qmp[0] + qmp[2]) * mp.cos(th)
+            ref += mp.fsum(qmp[j + 1] * mp.cos(j * th) for j in range(2, n))
+            r = float(ref)
+            bound = 20 * 1.1e-19 * S + 1.2e-16 * abs(r)
+            assert abs(lam[k - 1] - r) <= bound, (k, lam[k - 1], r, bound)
+            if k == 1 and n == 4095:
+                # the float64 rounding of the q_j alone moves it far more
+                assert abs(coeffs.tau_eigs(hi, n)[0] - r) > 3 * bound
