@@ -1,7 +1,10 @@
 """Train the warm-start network on pairs the solver generates itself.
 
-    python -m paper_2511_21198_amd.train_warmstart [--n 255] [--seeds 1-8]
-        [--steps 200] [--crops 2] [--crop 48] [--iters 3000] [--out FILE]
+    python -m paper_2511_21198_amd.train_warmstart [--n 255] [--seeds 1-100]
+        [--steps 200] [--crops 1] [--crop 48] [--iters 12000] [--out FILE]
+
+Defaults: the configured scale, 20,000 pairs (100 seeds x 200 steps, one
+crop each), validation on seeds 101-102.
 
 Data: for each training seed, the learned-warm-start workload (3D
 symmetric, orders drawn per seed, moving Gaussian bumps, M steps to T = 1)
@@ -140,12 +143,12 @@ def parse_seeds(s):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--n", type=int, default=255)
-    ap.add_argument("--seeds", default="1-8")
-    ap.add_argument("--val-seeds", default="9")
+    ap.add_argument("--seeds", default="1-100")
+    ap.add_argument("--val-seeds", default="101-102")
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--crops", type=int, default=2)
+    ap.add_argument("--crops", type=int, default=1)
     ap.add_argument("--crop", type=int, default=48)
-    ap.add_argument("--iters", type=int, default=3000)
+    ap.add_argument("--iters", type=int, default=12000)
     ap.add_argument("--batch", type=int, default=4)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--margin", type=int, default=4)

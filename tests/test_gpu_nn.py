@@ -207,3 +207,83 @@ def test_guarded_initial_guess():
     assert st_bad["x0_fallback"] == 1
     assert st_bad["iters"] == st_ref["iters"]
     assert torch.equal(bad, ref)
+
+
+def test_trained_network_on_held_out_seed(ws):
+    """What the committed trained network gains over the method without it,
+    on a seed used neither for training (1-100), validation (101-102) nor
+    the benchmark (10001): the learned-warm-start workload (3D symmetric
+    255^3, orders drawn for the seed, moving bumps, float64 PCG, tol 1e-8),
+    first 40 steps.
+
+    Along one trajectory, the initial residual ||b - A x0|| of every step is
+    taken for x0 = u^{m-1} (the method's warm start), the extrapolation
+    2 u^{m-1} - u^{m-2} (the network's base guess) and the network's guess;
+    the network's must be the smallest in total.  The three solvers
+    (PCG from u^{m-1}, from the extrapolation, and from the guarded network
+    guess) are also run and timed, inference included; their iterations and
+    steps/s are printed, not asserted (whether the guess pays for its
+    inference and its residual guard is a measurement, reported by the
+    benchmark)."""
+    import os
+    import time
+    from paper_2511_21198_amd.solver import Problem
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    wpath = os.path.join(root, "paper_2511_21198_amd", "weights", "warmstart_3d_sym.npy")
+    params = torch.from_numpy(np.load(wpath)).cuda()
+    n, M, steps = 255, 200, 40
+    w = workloads.config_learned(10002, n=n, M=M)
+    dt = w.T / w.M
+    dev = torch.device("cuda")
+    Fs = [workloads.bumps_source_torch([n] * 3, w.bumps["c0"] + w.bumps["v"] * ((m - 0.5) * dt),
+                                       w.bumps["width"], dev) for m in range(1, steps + 1)]
+    common = dict(dim=3, n=[n] * 3, delta=w.delta, kplus=w.kplus, kminus=w.kminus, M=M, T=w.T,
+                  solver="pcg", tol=1e-8)
+    net = ws.Net(n, n, n)
+    probe = Problem(**common, x0="prev")
+    eta = [probe.coefficients(i)[2] for i in range(3)]
+    # one trajectory (float64 PCG from u^{m-1}); initial residuals of the
+    # three guesses at every step m >= 2
+    u = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+    up = None
+    res = {"prev": [], "extrap": [], "net": []}
+    b = torch.empty_like(u)
+    Ax = torch.empty_like(u)
+    guess = torch.empty_like(u)
+    for m in range(steps):
+        if up is not None:
+            probe.apply_rhs(u, Fs[m], out=b)
+            net.predict(params, u, Fs[m], dt, eta, u_prev=up, F_prev=Fs[m - 1], out=guess)
+            for name, x0 in (("prev", u), ("extrap", 2.0 * u - up), ("net", guess)):
+                probe.apply_A(x0.contiguous(), out=Ax)
+                res[name].append(float(torch.linalg.vector_norm(b - Ax)))
+        un, _ = probe.cn_step(u, Fs[m])
+        up, u = u, un
+    tot = {k: float(np.sum(v)) for k, v in res.items()}
+    # the three solvers, timed over steps 2..40, inference included
+    stats = {}
+    for name, x0 in (("prev", "prev"), ("extrap", "extrap"), ("net", "guarded")):
+        p = Problem(**common, x0=x0)
+        u = torch.zeros((n, n, n), dtype=torch.float64, device=dev)
+        up = torch.zeros_like(u)
+        g = torch.empty_like(u) if x0 == "guarded" else None
+        its, fb = [], 0
+        t0 = None
+        for m in range(steps):
+            if m == 1:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+            if g is not None:
+                net.predict(params, u, Fs[m], dt, eta, u_prev=up if m > 0 else None,
+                            F_prev=Fs[m - 1] if m > 0 else None, out=g)
+            un, st = p.cn_step(u, Fs[m], guess=g)
+            its.append(st["iters"])
+            fb += st["x0_fallback"]
+            up, u = u, un
+        torch.cuda.synchronize()
+        stats[name] = dict(mean_iters=float(np.mean(its[1:])),
+                           steps_per_s=(steps - 1) / (time.perf_counter() - t0), fallbacks=fb)
+        del p
+    print(f"held-out seed 10002, delta {np.round(w.delta, 3).tolist()}: summed initial residuals "
+          f"{ {k: f'{v:.4e}' for k, v in tot.items()} }; solvers {stats}")
+    assert tot["net"] < tot["extrap"] < tot["prev"], tot
