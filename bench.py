@@ -384,7 +384,8 @@ def batched_workload(a, streams=8, steps=8):
     k+ = k- (PCG) for even instances, PGMRES otherwise; 8 bumps; u0 = 0;
     mixed precision, tol 1e-8), `steps` CN steps each, through the batched
     executor: one lane (problems one after the other on one stream) against
-    the autotuned lane count."""
+    the autotuned lane count and launch mode (direct launches or launch
+    graphs of the Krylov iteration chunks)."""
     import torch
     import workloads
     from paper_2511_21198_amd.batch import Batch
@@ -420,7 +421,8 @@ def batched_workload(a, streams=8, steps=8):
     b.set_lanes(1)
     run("one_lane")
     lanes, ms = b.autotune(u0, Fs)
-    out["autotune_ms_per_lanes"] = {str(k): round(v, 2) for k, v in ms.items()}
+    out["autotune_ms"] = {f"lanes={l},graphs={int(g)}": round(v, 2) for (l, g), v in ms.items()}
+    out["autotuned_config"] = {"lanes": lanes, "graphs": b.graphs}
     run("autotuned")
     out["speedup_vs_one_lane"] = round(out["autotuned"]["instance_steps_per_s"] /
                                        out["one_lane"]["instance_steps_per_s"], 3)

@@ -242,6 +242,17 @@ fsd_status fsd_solve(fsd_problem prob, const double* d_b, double* d_x, fsd_stats
 fsd_status fsd_cn_step(fsd_problem prob, const double* d_u_prev, const double* d_F,
                        const double* d_guess, double* d_u_next, fsd_stats* st);
 
+/* Launch graphs (default off).  When on, each chunk of Krylov iterations
+ * the host enqueues between two convergence checks (every PCG chunk, and
+ * the first chunk of every GMRES cycle) is captured once into a HIP graph on
+ * the bound stream and replayed with a single launch afterwards; results
+ * are bitwise those of the direct launches.  Pays off where kernel launches
+ * dominate (small grids).  Graphs are not used with the kernel profiler on
+ * or on the null stream; they are dropped by fsd_bind and when turned off.
+ * The problem keeps its graphs (a few per precision and chunk length) until
+ * fsd_destroy. */
+fsd_status fsd_set_graphs(fsd_problem prob, int on);
+
 /* Forget the time history used by FSD_X0_EXTRAP (call when the next
  * fsd_cn_step does not continue the previous trajectory). */
 fsd_status fsd_reset_history(fsd_problem prob);

@@ -13,7 +13,9 @@
  * counts of a step feed the estimate of the next one.
  *
  * fsd_batch_autotune times one step for each lane count 1, 2, 4, ... up
- * to the number of streams and keeps the fastest.
+ * to the number of streams, with direct kernel launches and with launch
+ * graphs of the Krylov iteration chunks (fsd_set_graphs), and keeps the
+ * fastest combination.
  *
  * Results are bitwise those of calling fsd_cn_step on each problem alone:
  * the executor changes only which stream and thread run a problem.
@@ -51,6 +53,11 @@ fsd_status fsd_batch_bind(fsd_batch batch, void* d_ws, size_t bytes, void* const
 fsd_status fsd_batch_set_lanes(fsd_batch batch, int lanes);
 int fsd_batch_lanes(fsd_batch batch);
 
+/* Launch graphs for every problem of the batch (fsd_set_graphs), and the
+ * current setting. */
+fsd_status fsd_batch_set_graphs(fsd_batch batch, int on);
+int fsd_batch_graphs(fsd_batch batch);
+
 /* One CN step of every problem: d_u_prev[i], d_F[i] (may be NULL: f = 0),
  * d_guess[i] (read in EXTERNAL / GUARDED mode; the array itself may be
  * NULL otherwise), d_u_next[i]; stats: `count` entries or NULL.  Returns
@@ -60,11 +67,13 @@ fsd_status fsd_batch_cn_step(fsd_batch batch, const double* const* d_u_prev,
                              const double* const* d_F, const double* const* d_guess,
                              double* const* d_u_next, fsd_stats* stats);
 
-/* Try lane counts 1, 2, 4, ... <= nstreams with one CN step each (outputs
- * to d_u_next, inputs unchanged; the time history of FSD_X0_EXTRAP is reset
- * afterwards) and keep the fastest.  ms_out (optional, >= log2(nstreams)+1
- * entries) receives the step time of each candidate; returns the chosen
- * lane count or a negative status. */
+/* Try lane counts 1, 2, 4, ... <= nstreams, first with direct launches and
+ * then with launch graphs, with one CN step each (outputs to d_u_next,
+ * inputs unchanged; the time history of FSD_X0_EXTRAP is reset afterwards)
+ * and keep the fastest combination (fsd_batch_lanes, fsd_batch_graphs).
+ * ms_out (optional, >= 2 (log2(nstreams) + 1) entries) receives the step
+ * time of each candidate, direct launches first; returns the chosen lane
+ * count or a negative status. */
 int fsd_batch_autotune(fsd_batch batch, const double* const* d_u_prev, const double* const* d_F,
                        double* const* d_u_next, double* ms_out);
 

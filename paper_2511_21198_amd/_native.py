@@ -98,6 +98,7 @@ SIGNATURES = {
     "fsd_get_coefficients": (C.c_int, [_VP, C.c_int, C.POINTER(C.c_double),
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fsd_reset_history": (C.c_int, [_VP]),
+    "fsd_set_graphs": (C.c_int, [_VP, C.c_int]),
     "fsd_profile_enable": (C.c_int, [_VP, C.c_int]),
     "fsd_profile_read": (C.c_int, [_VP, C.POINTER(ProfileEntry), C.c_int]),
     "fsd_hbm_copy": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),
@@ -129,6 +130,8 @@ SIGNATURES = {
     "fsd_batch_bind": (C.c_int, [_VP, _VP, C.c_size_t, C.POINTER(_VP), C.c_int]),
     "fsd_batch_set_lanes": (C.c_int, [_VP, C.c_int]),
     "fsd_batch_lanes": (C.c_int, [_VP]),
+    "fsd_batch_set_graphs": (C.c_int, [_VP, C.c_int]),
+    "fsd_batch_graphs": (C.c_int, [_VP]),
     "fsd_batch_cn_step": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP),
                                     C.POINTER(_VP), C.POINTER(Stats)]),
     "fsd_batch_autotune": (C.c_int, [_VP, C.POINTER(_VP), C.POINTER(_VP), C.POINTER(_VP),

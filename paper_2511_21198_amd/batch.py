@@ -68,6 +68,14 @@ class Batch:
     def set_lanes(self, lanes: int):
         check(lib.fsd_batch_set_lanes(self._h, int(lanes)), "fsd_batch_set_lanes")
 
+    @property
+    def graphs(self) -> bool:
+        return bool(lib.fsd_batch_graphs(self._h))
+
+    def set_graphs(self, on: bool):
+        """Launch graphs of the Krylov iteration chunks for every problem."""
+        check(lib.fsd_batch_set_graphs(self._h, int(on)), "fsd_batch_set_graphs")
+
     def empty(self) -> List[torch.Tensor]:
         return [torch.empty(s, dtype=torch.float64, device=self.device) for s in self.shapes]
 
@@ -85,19 +93,22 @@ class Batch:
         return out, [x.as_dict() for x in st]
 
     def autotune(self, u_prev, F=None):
-        """Time one step per lane count 1, 2, 4, ... and keep the fastest;
-        returns (lanes, {lanes: ms})."""
+        """Time one step per lane count 1, 2, 4, ... with direct launches
+        and with launch graphs, and keep the fastest; returns (lanes,
+        {(lanes, graphs): ms}); the chosen launch mode is `graphs`."""
         out = self.empty()
-        ms = (C.c_double * 16)()
+        ms = (C.c_double * 32)()
         torch.cuda.current_stream(self.device).synchronize()
         r = lib.fsd_batch_autotune(self._h, _ptrs(u_prev, self.count), _ptrs(F, self.count),
                                    _ptrs(out, self.count), ms)
         if r < 0:
             raise nat.FsdError(-r, "fsd_batch_autotune")
-        cands, l = {}, 1
+        cands = {}
         k = 0
-        while l <= min(len(self.streams), self.count):
-            cands[l] = ms[k]
-            l *= 2
-            k += 1
+        for g in (False, True):
+            l = 1
+            while l <= min(len(self.streams), self.count):
+                cands[(l, g)] = ms[k]
+                l *= 2
+                k += 1
         return r, cands

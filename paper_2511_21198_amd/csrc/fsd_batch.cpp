@@ -21,6 +21,7 @@ struct fsd_batch_s {
     size_t ws_bytes = 0;
     std::vector<hipStream_t> streams;
     int lanes = 1;
+    int graphs = 0;      // fsd_set_graphs of every problem
     bool bound = false;
 };
 
@@ -167,6 +168,15 @@ fsd_status fsd_batch_set_lanes(fsd_batch b, int lanes) {
 
 int fsd_batch_lanes(fsd_batch b) { return b ? b->lanes : 0; }
 
+fsd_status fsd_batch_set_graphs(fsd_batch b, int on) {
+    if (!b) return set_error(FSD_EINVAL, "null batch");
+    b->graphs = on != 0;
+    for (fsd_problem p : b->P) fsd_set_graphs(p, b->graphs);
+    return FSD_OK;
+}
+
+int fsd_batch_graphs(fsd_batch b) { return b ? b->graphs : 0; }
+
 fsd_status fsd_batch_cn_step(fsd_batch b, const double* const* d_u_prev, const double* const* d_F,
                              const double* const* d_guess, double* const* d_u_next,
                              fsd_stats* stats) {
@@ -182,26 +192,33 @@ int fsd_batch_autotune(fsd_batch b, const double* const* d_u_prev, const double*
     if (!b->bound) return -(int)set_error(FSD_ENOTBOUND, "fsd_batch_bind() has not been called");
     if (!d_u_prev || !d_u_next) return -(int)set_error(FSD_EINVAL, "null vector array");
     const int maxl = std::min((int)b->streams.size(), (int)b->P.size());
-    int best = 1, k = 0;
+    int best = 1, best_g = 0, k = 0;
     double best_ms = 1e300;
-    // one untimed step first: tables and caches warm, iteration estimates set
-    b->lanes = maxl;
-    fsd_status s = run_step(b, d_u_prev, d_F, nullptr, d_u_next, nullptr);
-    if (s != FSD_OK && s != FSD_ENOTCONV) return -(int)s;
-    for (int l = 1; l <= maxl; l *= 2, ++k) {
-        b->lanes = l;
-        const auto t0 = std::chrono::steady_clock::now();
-        s = run_step(b, d_u_prev, d_F, nullptr, d_u_next, nullptr);
-        const double ms =
-            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    // per launch mode (direct launches, then graphs): one untimed step first
+    // (tables and caches warm, iteration estimates set, graphs captured),
+    // then one timed step per lane count
+    for (int g = 0; g < 2; ++g) {
+        fsd_batch_set_graphs(b, g);
+        b->lanes = maxl;
+        fsd_status s = run_step(b, d_u_prev, d_F, nullptr, d_u_next, nullptr);
         if (s != FSD_OK && s != FSD_ENOTCONV) return -(int)s;
-        if (ms_out) ms_out[k] = ms;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best = l;
+        for (int l = 1; l <= maxl; l *= 2, ++k) {
+            b->lanes = l;
+            const auto t0 = std::chrono::steady_clock::now();
+            s = run_step(b, d_u_prev, d_F, nullptr, d_u_next, nullptr);
+            const double ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (s != FSD_OK && s != FSD_ENOTCONV) return -(int)s;
+            if (ms_out) ms_out[k] = ms;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = l;
+                best_g = g;
+            }
         }
     }
     for (fsd_problem p : b->P) fsd_reset_history(p);
+    fsd_batch_set_graphs(b, best_g);
     b->lanes = best;
     return best;
 }

@@ -528,6 +528,53 @@ struct SolveOut {
     int status = FSD_OK;
 };
 
+// ------------------------------------------------------------ graphs
+// A chunk of Krylov iterations is a fixed sequence of kernel launches with
+// fixed arguments: every PCG iteration enqueues the same kernels, and the
+// first chunk of a GMRES cycle (columns 0..cnt-1) the same ones every
+// cycle.  With P->use_graphs the chunk is captured once per (key, length)
+// into an executable graph on the problem's stream and replayed with one
+// launch instead of about a dozen per iteration: for small grids the
+// launches, not the kernels, are the cost.  Not with the per-launch
+// profiler (its event records are host bookkeeping) or on the null stream
+// (which cannot be captured).  Only kernel launches are captured: no
+// memset or copy nodes.
+template <typename F>
+fsd_status run_chunk(fsd_problem P, int key, F&& enqueue) {
+    if (!P->use_graphs || P->prof_on || !P->stream) return enqueue();
+    for (const auto& kv : P->graphs)
+        if (kv.first == key) {
+            HIP_TRY(hipGraphLaunch(kv.second, P->stream));
+            return FSD_OK;
+        }
+    HIP_TRY(hipStreamBeginCapture(P->stream, hipStreamCaptureModeThreadLocal));
+    const fsd_status st = enqueue();
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(P->stream, &g);
+    if (st != FSD_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (st != FSD_OK) return st;
+        return fail(FSD_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ei = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess) return fail(FSD_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+    P->graphs.emplace_back(key, x);
+    HIP_TRY(hipGraphLaunch(x, P->stream));
+    return FSD_OK;
+}
+
+// Graph key: precision, solver kind, reorthogonalisation pass, chunk length.
+inline int chunk_key(bool f32, int kind, bool reorth, int len) {
+    return (f32 ? 1 << 20 : 0) | (kind << 17) | (reorth ? 1 << 16 : 0) | len;
+}
+
+void drop_graphs(fsd_problem P) {
+    for (auto& kv : P->graphs) (void)hipGraphExecDestroy(kv.second);
+    P->graphs.clear();
+}
+
 // ------------------------------------------------------------ PCG
 // Section 3.1: alpha = (r,z)/(p,Ap), x += alpha p, r -= alpha Ap,
 // z = P^{-1} r, beta = (r_new, z_new)/(r, z), p = z + beta p; stop when
@@ -563,22 +610,33 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
     long enq = 0;
     const size_t rec0 = P->prof.size();
     for (;;) {
-        for (int c = 0; c < chunk && enq < maxit; ++c, ++enq) {
-            P->prof_tag = (int)enq;
-            MatvecOpts o;
-            o.epi = EPI_DOT_P;
-            o.pro = PRO_PUPDATE;
-            FSD_TRY(op_matvec<T>(P, v.z, v.q, o, v.p, nullptr, v.p, P->ctrl, &np));
-            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_ALPHA, s));
-            {
-                ProfScope ps(P, K_PCG_UPDATE, is_f32<T>(), 6.0 * (double)P->N * sizeof(T));
-                HIP_TRY(vec_update_xr<T>(x, v.r, v.p, v.q, Np, P->ctrl, P->partials, &np, s));
+        const long e0 = enq;
+        const int cnt = (int)std::min<long>(chunk, maxit - enq);
+        auto body = [&]() -> fsd_status {
+            for (int c = 0; c < cnt; ++c) {
+                const long it = e0 + c;
+                P->prof_tag = (int)it;
+                MatvecOpts o;
+                o.epi = EPI_DOT_P;
+                o.pro = PRO_PUPDATE;
+                FSD_TRY(op_matvec<T>(P, v.z, v.q, o, v.p, nullptr, v.p, P->ctrl, &np));
+                HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_ALPHA, s));
+                {
+                    ProfScope ps(P, K_PCG_UPDATE, is_f32<T>(), 6.0 * (double)P->N * sizeof(T));
+                    HIP_TRY(vec_update_xr<T>(x, v.r, v.p, v.q, Np, P->ctrl, P->partials, &np, s));
+                }
+                HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_CHECK, s));
+                P->prof_tag = (int)it + 1;   // z for the next direction
+                FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
+                HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_BETA, s));
             }
-            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_CHECK, s));
-            P->prof_tag = (int)enq + 1;   // z for the next direction
-            FSD_TRY(op_precond<T>(P, v.r, v.z, P->ctrl, P->partials, &np));
-            HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_BETA, s));
-        }
+            return FSD_OK;
+        };
+        // the iterate x is a kernel argument: chunks are captured only for
+        // the workspace's own iterate (every solve the library drives)
+        if (cnt > 0 && x == vecs<T>(P).x) FSD_TRY(run_chunk(P, chunk_key(is_f32<T>(), 0, false, cnt), body));
+        else if (cnt > 0) FSD_TRY(body());
+        enq += cnt;
         FSD_TRY(read_ctrl(P));
         if (P->h_ctrl->done || enq >= maxit) break;
         chunk = 2;
@@ -638,50 +696,62 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         int j = 0;
         const size_t rec0 = P->prof.size();
         for (;;) {
-            for (int c = 0; c < chunk && j < m; ++c, ++j) {
-                P->prof_tag = j;
-                T* vj = v.V + (long)j * Np;
-                if (!split) {
-                    // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
-                    MatvecOpts o;
-                    o.pro = PRO_SCALE;
-                    FSD_TRY(op_matvec<T>(P, j == 0 ? v.w : vj, v.q, o, nullptr, nullptr, vj,
-                                         P->ctrl, &np));
-                    FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr));
-                } else {
-                    // w = P^{-1/2} A P^{-1/2} v_j, v_j = scale * (w or V[j])
-                    HIP_TRY(gm_scale<T>(j == 0 ? v.w : vj, vj, Np, P->ctrl, s));
-                    FSD_TRY(op_precond<T>(P, vj, v.z, P->ctrl, nullptr, nullptr, true));
-                    MatvecOpts o;
-                    FSD_TRY(op_matvec<T>(P, v.z, v.q, o, nullptr, nullptr, nullptr, P->ctrl, &np));
-                    FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr, true));
+            const int j0 = j;
+            const int cnt = std::min(chunk, m - j);
+            auto body = [&]() -> fsd_status {
+                for (int jj = j0; jj < j0 + cnt; ++jj) {
+                    P->prof_tag = jj;
+                    T* vj = v.V + (long)jj * Np;
+                    if (!split) {
+                        // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
+                        MatvecOpts o;
+                        o.pro = PRO_SCALE;
+                        FSD_TRY(op_matvec<T>(P, jj == 0 ? v.w : vj, v.q, o, nullptr, nullptr, vj,
+                                             P->ctrl, &np));
+                        FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr));
+                    } else {
+                        // w = P^{-1/2} A P^{-1/2} v_j, v_j = scale * (w or V[j])
+                        HIP_TRY(gm_scale<T>(jj == 0 ? v.w : vj, vj, Np, P->ctrl, s));
+                        FSD_TRY(op_precond<T>(P, vj, v.z, P->ctrl, nullptr, nullptr, true));
+                        MatvecOpts o;
+                        FSD_TRY(op_matvec<T>(P, v.z, v.q, o, nullptr, nullptr, nullptr, P->ctrl, &np));
+                        FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr, true));
+                    }
+                    const double vb = (double)P->N * sizeof(T);
+                    {
+                        ProfScope ps(P, K_GM_MDOT, is_f32<T>(), vb * (jj + 2));
+                        HIP_TRY(gm_mdot<T>(v.V, Np, jj + 1, v.w, Np, P->partials, P->ctrl, &np, s));
+                    }
+                    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_H1, s));
+                    // first Gram-Schmidt pass on the shifted vector:
+                    // v_{j+1} = (w - v_j) - V h1, with V^T v_{j+1} and ||v_{j+1}||^2
+                    // for the reorthogonalisation test
+                    T* vn = v.V + (long)(jj + 1) * Np;
+                    {
+                        ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (jj + 3));
+                        HIP_TRY(gm_maxpy<T>(v.V, Np, jj + 1, v.w, vn, Np, P->ctrl, h2off, MX_DOTS,
+                                            P->partials, &np, s));
+                    }
+                    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_H2, s));
+                    // second pass, in place, only when the test asks for it (never
+                    // with a zero threshold: no launch)
+                    if (eta2 > 0.0) {
+                        ProfScope ps(P, K_GM_REORTH, is_f32<T>(), vb * (jj + 3));
+                        HIP_TRY(gm_maxpy<T>(v.V, Np, jj + 1, vn, vn, Np, P->ctrl, h2off, MX_REORTH,
+                                            P->partials, &np, s));
+                    }
+                    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, jj, GM_STEP, s));
                 }
-                const double vb = (double)P->N * sizeof(T);
-                {
-                    ProfScope ps(P, K_GM_MDOT, is_f32<T>(), vb * (j + 2));
-                    HIP_TRY(gm_mdot<T>(v.V, Np, j + 1, v.w, Np, P->partials, P->ctrl, &np, s));
-                }
-                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H1, s));
-                // first Gram-Schmidt pass on the shifted vector:
-                // v_{j+1} = (w - v_j) - V h1, with V^T v_{j+1} and ||v_{j+1}||^2
-                // for the reorthogonalisation test
-                T* vn = v.V + (long)(j + 1) * Np;
-                {
-                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), vb * (j + 3));
-                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, v.w, vn, Np, P->ctrl, h2off, MX_DOTS,
-                                        P->partials, &np, s));
-                }
-                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, j + 1, j, GM_H2, s));
-                // second pass, in place, only when the test asks for it (never
-                // with a zero threshold: no launch)
-                if (eta2 > 0.0) {
-                    ProfScope ps(P, K_GM_REORTH, is_f32<T>(), vb * (j + 3));
-                    HIP_TRY(gm_maxpy<T>(v.V, Np, j + 1, vn, vn, Np, P->ctrl, h2off, MX_REORTH,
-                                        P->partials, &np, s));
-                }
-                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, j, GM_STEP, s));
-                ++total_enq;
-            }
+                return FSD_OK;
+            };
+            // the first chunk of a cycle starts at column 0: a fixed launch
+            // sequence (the others depend on where they start)
+            if (j0 == 0 && cnt > 0)
+                FSD_TRY(run_chunk(P, chunk_key(is_f32<T>(), split ? 3 : 1, eta2 > 0.0, cnt), body));
+            else
+                FSD_TRY(body());
+            j += cnt;
+            total_enq += cnt;
             FSD_TRY(read_ctrl(P));
             if (P->h_ctrl->done || j >= m) break;
             chunk = 2;
@@ -1085,6 +1155,7 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
 
 void fsd_destroy(fsd_problem P) {
     if (!P) return;
+    drop_graphs(P);
     if (P->h_ctrl) (void)hipHostFree(P->h_ctrl);
     for (hipEvent_t e : P->prof_pool) (void)hipEventDestroy(e);
     delete P;
@@ -1101,6 +1172,7 @@ fsd_status fsd_bind(fsd_problem P, void* d_ws, size_t bytes, void* stream) {
         snprintf(buf, sizeof buf, "workspace has %zu bytes, needs %zu", bytes, P->ws_bytes);
         return fail(FSD_ESMALLWS, buf);
     }
+    drop_graphs(P);   // captured launches hold the previous workspace's addresses
     P->ws = (char*)d_ws;
     P->stream = (hipStream_t)stream;
     layout(P, P->ws);
@@ -1249,6 +1321,13 @@ fsd_status fsd_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* stre
     const uintptr_t a = (uintptr_t)d_src, b = (uintptr_t)d_dst;
     if (a < b + bytes && b < a + bytes) return fail(FSD_EINVAL, "source and destination overlap");
     HIP_TRY(stream_copy(d_src, d_dst, bytes, (hipStream_t)stream));
+    return FSD_OK;
+}
+
+fsd_status fsd_set_graphs(fsd_problem P, int on) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    P->use_graphs = on != 0;
+    if (!P->use_graphs) drop_graphs(P);
     return FSD_OK;
 }
 

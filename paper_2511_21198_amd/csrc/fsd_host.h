@@ -2,6 +2,7 @@
 #pragma once
 
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/fsd.h"
@@ -115,6 +116,11 @@ struct fsd_problem_s {
     double* ctw[3] = {nullptr, nullptr, nullptr};
     double* cea[3] = {nullptr, nullptr, nullptr};
     double* ceb[3] = {nullptr, nullptr, nullptr};
+
+    // executable graphs of Krylov iteration chunks (fsd_set_graphs): key,
+    // graph; captured on first use, dropped when the workspace is rebound
+    bool use_graphs = false;
+    std::vector<std::pair<int, hipGraphExec_t>> graphs;
 
     bool prof_on = false;
     std::vector<fsd::ProfRec> prof;

@@ -154,6 +154,11 @@ class Problem:
             check(s, "fsd_cn_step")
         return out, (st.as_dict() if stats else None)
 
+    def set_graphs(self, on: bool = True):
+        """Replay captured launch graphs of the Krylov iteration chunks
+        (fsd_set_graphs)."""
+        check(lib.fsd_set_graphs(self._h, int(on)), "fsd_set_graphs")
+
     def reset_history(self):
         """Forget the time history used by x0="extrap"."""
         check(lib.fsd_reset_history(self._h), "fsd_reset_history")

@@ -70,7 +70,7 @@ def test_batch_autotune_then_step(mods):
     ref, _ = bt.cn_step(us, Fs)
     ref = [r.clone() for r in ref]
     lanes, ms = bt.autotune(us, Fs)
-    assert lanes in ms and all(v > 0 for v in ms.values())
+    assert (lanes, bt.graphs) in ms and all(v > 0 for v in ms.values())
     out, _ = bt.cn_step(us, Fs)
     for a, b in zip(out, ref):
         assert torch.equal(a, b)
@@ -136,3 +136,32 @@ def test_batch_mixed_members_match_oracle(mods):
         ur, _ = cn.run(orc, u0.cpu().numpy(), lambda m: F.cpu().numpy(), tol=1e-13,
                        solver=kw["solver"])
         _close(ug.cpu().numpy(), ur, 1e-8 if kw["precision"] == "mixed" else 1e-10)
+
+
+@pytest.mark.parametrize("kw", [MEMBERS[1], MEMBERS[3], MEMBERS[4], MEMBERS[5],
+                                dict(MEMBERS[2], reorth_eta2=1.0),
+                                dict(MEMBERS[2], solver="gmres2")],
+                         ids=["gmres-mixed", "pcg-mixed", "pcg-fp64", "gmres-fp64",
+                              "gmres-reorth", "gmres2"])
+def test_graphs_bitwise_equal_direct(mods, kw):
+    """Launch graphs of the Krylov chunks (fsd_set_graphs) replay the same
+    kernels: five CN steps with graphs (every step replays the captured
+    chunks several times, with the solver's own direct launches and host
+    synchronisations in between) give bitwise the states of five steps
+    with direct launches, step by step."""
+    _, Problem = mods
+    shape = tuple(reversed(kw["n"]))
+    u0 = torch.from_numpy(workloads.random_grid(shape, 600)).cuda()
+    F = torch.from_numpy(workloads.random_grid(shape, 601)).cuda()
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        pd = Problem(**kw, stream=st)
+        pg = Problem(**kw, stream=st)
+        pg.set_graphs(True)
+        ud, ug = u0.clone(), u0.clone()
+        for m in range(5):
+            ud, sd = pd.cn_step(ud, F)
+            ug, sg = pg.cn_step(ug, F)
+            st.synchronize()
+            assert sd["iters"] == sg["iters"], (m, sd, sg)
+            assert torch.equal(ud, ug), m
