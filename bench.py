@@ -423,6 +423,14 @@ def batched_workload(a, streams=8, steps=8):
     lanes, ms = b.autotune(u0, Fs)
     out["autotune_ms"] = {f"lanes={l},graphs={int(g)}": round(v, 2) for (l, g), v in ms.items()}
     out["autotuned_config"] = {"lanes": lanes, "graphs": b.graphs}
+    # engines (tile shapes) the autotuner chose: how many problems run each
+    # (pass, precision, length) on each engine
+    from collections import Counter
+    chosen = Counter()
+    for i in range(len(ws)):
+        for item in b.engines(i).split(","):
+            chosen[item] += 1
+    out["autotuned_engines"] = dict(sorted(chosen.items()))
     run("autotuned")
     out["speedup_vs_one_lane"] = round(out["autotuned"]["instance_steps_per_s"] /
                                        out["one_lane"]["instance_steps_per_s"], 3)

@@ -242,6 +242,42 @@ fsd_status fsd_solve(fsd_problem prob, const double* d_b, double* d_x, fsd_stats
 fsd_status fsd_cn_step(fsd_problem prob, const double* d_u_prev, const double* d_F,
                        const double* d_guess, double* d_u_next, fsd_stats* st);
 
+/* Engines (tile shapes) of the line passes.  Every pass of the matvec and
+ * of the preconditioner can run on more than one engine: the wave engine
+ * (lengths 64..512), the column engine (float32 strided passes of length
+ * 512; for DST passes with the DST-I by the odd extension or by the
+ * half-length algorithm), and the LDS-stage engine with its default tile
+ * or half of it.  All give the same operator to rounding.  FSD_ENGINE_AUTO
+ * is the built-in choice per length. */
+enum {
+    FSD_ENGINE_AUTO = 0, FSD_ENGINE_WAVE = 1, FSD_ENGINE_COL = 2, FSD_ENGINE_COLH = 3,
+    FSD_ENGINE_STAGE = 4, FSD_ENGINE_STAGE_HALF = 5
+};
+/* Passes: Toeplitz x / y / z, DST x / y, and the DST-Lambda-DST pass of the
+ * last axis (y in 2D, z in 3D). */
+enum {
+    FSD_PASS_TOEP_X = 0, FSD_PASS_TOEP_Y = 1, FSD_PASS_TOEP_Z = 2, FSD_PASS_DST_X = 3,
+    FSD_PASS_DST_Y = 4, FSD_PASS_DSTS_LAST = 5, FSD_PASS_COUNT = 6
+};
+
+/* Set the engine of one pass for the float64 operators (precision
+ * FSD_PREC_FP64) or the float32 ones of mixed precision (FSD_PREC_MIXED).
+ * Errors: FSD_EINVAL (no such pass in this dimension, unknown engine),
+ * FSD_EUNSUPPORTED (the engine does not run that pass at its length). */
+fsd_status fsd_set_engine(fsd_problem prob, int precision, int pass, int engine);
+
+/* Autotuner: time every engine of every pass of the problem (float64 and,
+ * for mixed precision, float32) on the bound workspace and stream, five
+ * launches each after two untimed ones, and keep the fastest.  Synchronises
+ * the stream; overwrites the workspace's scratch vectors (call between CN
+ * steps, not inside a solve).  Results change only by rounding. */
+fsd_status fsd_autotune(fsd_problem prob);
+
+/* The engine of every pass as "pass_prec(L=..)=engine,...", written to buf
+ * (at most len - 1 characters and a terminating zero); returns the full
+ * length, or -1 on error. */
+int fsd_engines(fsd_problem prob, char* buf, int len);
+
 /* Launch graphs (default off).  When on, each chunk of Krylov iterations
  * the host enqueues between two convergence checks (every PCG chunk, and
  * the first chunk of every GMRES cycle) is captured once into a HIP graph on

@@ -12,10 +12,11 @@
  * each lane runs its problems in that order every step.  The iteration
  * counts of a step feed the estimate of the next one.
  *
- * fsd_batch_autotune times one step for each lane count 1, 2, 4, ... up
- * to the number of streams, with direct kernel launches and with launch
- * graphs of the Krylov iteration chunks (fsd_set_graphs), and keeps the
- * fastest combination.
+ * fsd_batch_autotune tunes the engine (tile shape) of every pass of every
+ * problem (fsd_autotune), then times one step for each lane count 1, 2, 4,
+ * ... up to the number of streams, with direct kernel launches and with
+ * launch graphs of the Krylov iteration chunks (fsd_set_graphs), and keeps
+ * the fastest combination.
  *
  * Results are bitwise those of calling fsd_cn_step on each problem alone:
  * the executor changes only which stream and thread run a problem.
@@ -67,7 +68,8 @@ fsd_status fsd_batch_cn_step(fsd_batch batch, const double* const* d_u_prev,
                              const double* const* d_F, const double* const* d_guess,
                              double* const* d_u_next, fsd_stats* stats);
 
-/* Try lane counts 1, 2, 4, ... <= nstreams, first with direct launches and
+/* Tune the engines of every problem's passes (fsd_autotune), then try lane
+ * counts 1, 2, 4, ... <= nstreams, first with direct launches and
  * then with launch graphs, with one CN step each (outputs to d_u_next,
  * inputs unchanged; the time history of FSD_X0_EXTRAP is reset afterwards)
  * and keep the fastest combination (fsd_batch_lanes, fsd_batch_graphs).

@@ -25,6 +25,9 @@ PREC_FP64, PREC_MIXED = 0, 1
 X0_PREV, X0_ZERO, X0_EXTERNAL, X0_EXTRAP, X0_GUARDED = 0, 1, 2, 3, 4
 # fsd_precond
 PC_TAU, PC_NONE, PC_TCHAN, PC_STRANG = 0, 1, 2, 3
+# engines and passes (fsd_set_engine)
+ENGINES = {"auto": 0, "wave": 1, "col": 2, "colh": 3, "stage": 4, "stage_half": 5}
+PASSES = {"toep_x": 0, "toep_y": 1, "toep_z": 2, "dst_x": 3, "dst_y": 4, "dsts_last": 5}
 
 
 class Params(C.Structure):
@@ -99,6 +102,9 @@ SIGNATURES = {
                                        C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "fsd_reset_history": (C.c_int, [_VP]),
     "fsd_set_graphs": (C.c_int, [_VP, C.c_int]),
+    "fsd_set_engine": (C.c_int, [_VP, C.c_int, C.c_int, C.c_int]),
+    "fsd_autotune": (C.c_int, [_VP]),
+    "fsd_engines": (C.c_int, [_VP, C.c_char_p, C.c_int]),
     "fsd_profile_enable": (C.c_int, [_VP, C.c_int]),
     "fsd_profile_read": (C.c_int, [_VP, C.POINTER(ProfileEntry), C.c_int]),
     "fsd_hbm_copy": (C.c_int, [_VP, _VP, C.c_size_t, _VP]),

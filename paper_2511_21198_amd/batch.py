@@ -76,6 +76,14 @@ class Batch:
         """Launch graphs of the Krylov iteration chunks for every problem."""
         check(lib.fsd_batch_set_graphs(self._h, int(on)), "fsd_batch_set_graphs")
 
+    def engines(self, i: int) -> str:
+        """Problem i's pass engines (fsd_engines)."""
+        h = lib.fsd_batch_problem(self._h, int(i))
+        n = lib.fsd_engines(h, None, 0)
+        buf = C.create_string_buffer(n + 1)
+        lib.fsd_engines(h, buf, n + 1)
+        return buf.value.decode()
+
     def empty(self) -> List[torch.Tensor]:
         return [torch.empty(s, dtype=torch.float64, device=self.device) for s in self.shapes]
 

@@ -194,6 +194,11 @@ int fsd_batch_autotune(fsd_batch b, const double* const* d_u_prev, const double*
     const int maxl = std::min((int)b->streams.size(), (int)b->P.size());
     int best = 1, best_g = 0, k = 0;
     double best_ms = 1e300;
+    // tile shapes first: every problem's passes on their fastest engines
+    for (fsd_problem p : b->P) {
+        const fsd_status s = fsd_autotune(p);
+        if (s != FSD_OK) return -(int)s;
+    }
     // per launch mode (direct launches, then graphs): one untimed step first
     // (tables and caches warm, iteration estimates set, graphs captured),
     // then one timed step per lane count

@@ -369,6 +369,215 @@ void k_col_dst(DstArgs<float> a) {
     }
 }
 
+// ------------------------------------------------- half-length DST-I
+// The unnormalised DST-I of order n = 255, S_k = sum_{j=1}^{255} x_j
+// sin(pi j k / N) with N = n + 1 = 256, from one complex FFT of length N
+// instead of 2N (the odd extension): with x_0 = x_N = 0 and
+//   y_j = sin(pi j / N) (x_j + x_{N-j}) + (x_j - x_{N-j}) / 2,
+// the DFT Y_f = sum_j y_j e^{-2 pi i j f / N} = C_f - i D_f gives
+//   S_{2f} = D_f  and  S_{2f+1} - S_{2f-1} = C_f  (S_{-1} = -S_1),
+// the odd outputs by a prefix sum.  Two real lines share the complex FFT
+// (real and imaginary parts of y) and are separated by the symmetry of a
+// real sequence's DFT, Y1_f = (Z_f + conj Z_{N-f}) / 2 and
+// Y2_f = (Z_f - conj Z_{N-f}) / (2i).  The FFT of length 256 = 16 x 16 runs
+// as the column engine's length-512 transform does: 16-point DFTs over m
+// in registers (thread (p, r) holds points r + 16 m), the twiddles
+// w256^{r k1}, one LDS transpose, 16-point DFTs over r.
+constexpr int HN = 256;
+
+// Forward DFT of length 256: on entry thread (p, r) holds z[r + 16 m] in
+// (zr[m], zi[m]); on exit Z[r + 16 k2] in (zr[k2], zi[k2]).
+__device__ inline void fft256_cols(Smem& S, const Tile& t, float (&zr)[16], float (&zi)[16]) {
+    dft16<16>(zr, zi);   // B_r[k1] over m
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) {
+        const float2 w = S.tw[2 * t.r * k1];   // w256^{r k1} = w512^{2 r k1}
+        const float a = zr[k1], b = zi[k1];
+        S.buf[(k1 * CR + t.r) * CP + t.p] = make_float2(a * w.x - b * w.y, a * w.y + b * w.x);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < CR; ++rr) {
+        const float2 v = S.buf[(t.r * CR + rr) * CP + t.p];
+        zr[rr] = v.x;
+        zi[rr] = v.y;
+    }
+    __syncthreads();
+    dft16<16>(zr, zi);   // over r: Z[k1 + 16 k2] with k1 = r
+}
+
+// Unnormalised DST-I of the tile's line pairs.  On entry S.buf[j * CP + p]
+// holds x_j for j = 0..255 (x_0 = 0) and a barrier has passed; on exit
+// thread (p, t) holds S_k for k = 16 t + q in (sr[q], si[q]), q = 0..15
+// (the real-part line in sr, the imaginary-part line in si; k = 0 gives 0),
+// and the LDS buffer is free.  tot: 16 * CP float2 of LDS.
+__device__ inline void dst256_from_lds(Smem& S, float2* tot, const Tile& t, float (&sr)[16],
+                                       float (&si)[16]) {
+    float zr[16], zi[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int j = t.r + 16 * m;
+        const float2 x = S.buf[j * CP + t.p];
+        const float2 xm = S.buf[((HN - j) & (HN - 1)) * CP + t.p];   // x_{N-j} (x_N = x_0 = 0)
+        const float sn = -S.tw[j].y;                                  // sin(pi j / N)
+        zr[m] = sn * (x.x + xm.x) + 0.5f * (x.x - xm.x);
+        zi[m] = sn * (x.y + xm.y) + 0.5f * (x.y - xm.y);
+    }
+    __syncthreads();
+    fft256_cols(S, t, zr, zi);
+    // Z_f for f = t + 16 k2 in natural order, then Z_{N-f}
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) S.buf[(t.r + 16 * k2) * CP + t.p] = make_float2(zr[k2], zi[k2]);
+    __syncthreads();
+    float br[8], bi[8];
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        const int f = t.r + 16 * k2;
+        const float2 v = S.buf[((HN - f) & (HN - 1)) * CP + t.p];
+        br[k2] = v.x;
+        bi[k2] = v.y;
+    }
+    __syncthreads();
+    // f < 128: C (both lines) to rows 0..127 of the buffer, D to rows 128..255
+#pragma unroll
+    for (int k2 = 0; k2 < 8; ++k2) {
+        const int f = t.r + 16 * k2;
+        const float ar = zr[k2], ai = zi[k2];
+        S.buf[f * CP + t.p] = make_float2(0.5f * (ar + br[k2]), 0.5f * (ai + bi[k2]));
+        S.buf[(128 + f) * CP + t.p] = make_float2(-0.5f * (ai - bi[k2]), 0.5f * (ar - br[k2]));
+    }
+    __syncthreads();
+    // thread t: f = 8 t + i; inclusive prefix of C over its chunk, chunk
+    // totals through LDS
+    float2 pc[8], d[8];
+    float2 acc = make_float2(0.f, 0.f);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float2 c = S.buf[(8 * t.r + i) * CP + t.p];
+        acc.x += c.x;
+        acc.y += c.y;
+        pc[i] = acc;
+        d[i] = S.buf[(128 + 8 * t.r + i) * CP + t.p];
+    }
+    const float2 c0 = S.buf[t.p];
+    tot[t.r * CP + t.p] = acc;
+    __syncthreads();
+    float2 off = make_float2(-0.5f * c0.x, -0.5f * c0.y);   // S_{2f+1} = prefix(f) - C_0 / 2
+    for (int u = 0; u < t.r; ++u) {
+        const float2 v = tot[u * CP + t.p];
+        off.x += v.x;
+        off.y += v.y;
+    }
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        // k = 16 t + 2 i: S_{2f} = D_f (f = 8 t + i; D_0 = 0); k + 1: S_{2f+1}
+        sr[2 * i] = d[i].x;
+        si[2 * i] = d[i].y;
+        sr[2 * i + 1] = off.x + pc[i].x;
+        si[2 * i + 1] = off.y + pc[i].y;
+    }
+    __syncthreads();
+}
+
+// Strided DST-I pass by the half-length algorithm (SCALE = false), or the
+// last-axis pass S Lambda^{-1} S with the Parseval partials of
+// (r, P^{-1} r) (SCALE = true): the scaled spectrum goes back through LDS
+// in natural order and is transformed again.  Sixteen complex values per
+// thread (half the registers of k_col_dst).
+template <bool SCALE>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4)))
+void k_col_dsth(DstArgs<float> a) {
+    __shared__ Smem S;
+    __shared__ float2 s_tot[16 * CP];
+    __shared__ double s_red[NT / 64];
+    if (a.ctrl && a.ctrl->done) return;
+    const Tile t = tile_of(a.g);
+    const long es = a.g.estride;
+    load_tw(S, a.tw);
+    // scale pass: (a_last, lc_last) at k - 1 for k = threadIdx.x (NT = 256 =
+    // HN), staged in LDS between the transforms (in s_tot, free there: 40 KB
+    // of LDS keeps four workgroups on a CU)
+    float2 lam_k = make_float2(0.f, 0.f);
+    if constexpr (SCALE) {
+        const int k = threadIdx.x;
+        if (k >= 1) lam_k = make_float2(a.a_last[k - 1], a.lc_last[k - 1]);
+    }
+    {
+        // x_j = u[j - 1] for j = r + 16 m (x_0 = 0) to LDS in natural order
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = t.r + 16 * m;
+            v[m] = j >= 1 ? *row2(a.u, t.base + (long)(j - 1) * es) : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int m = 0; m < 16; ++m) S.buf[(t.r + 16 * m) * CP + t.p] = v[m];
+    }
+    __syncthreads();
+    const float c = 2.0f * a.c;   // sqrt(2 / N): the orthonormal DST-I
+    float sr[16], si[16];
+    dst256_from_lds(S, s_tot, t, sr, si);
+    if constexpr (SCALE) {
+        float P[2], Q[2];
+        const int o = blockIdx.x / (a.g.P1 / TX);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int x = (int)(t.base - (long)o * a.g.ostride) + cc;
+            P[cc] = 0.f;
+            Q[cc] = 0.f;
+            if (x < a.g.nx) {
+                const float a1 = a.a1[x], l1 = a.lc1[x];
+                if (a.dim == 2) {
+                    P[cc] = a1 + l1;
+                    Q[cc] = a1;
+                } else {
+                    const float a2 = a.a2[o], l2 = a.lc2[o];
+                    P[cc] = a2 * (a1 + l1) + l2 * a1;
+                    Q[cc] = a2 * a1;
+                }
+            }
+        }
+        s_tot[threadIdx.x] = lam_k;
+        __syncthreads();
+        double acc = 0.0;
+        // the scale as a compile-time choice (Lambda^{-1} or, for the
+        // two-sided system, Lambda^{-1/2}): a runtime select evaluates both
+        auto scale_all = [&](auto half_c) {
+            constexpr bool H = decltype(half_c)::value;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int k = 16 * t.r + q;
+                float w0 = 0.f, w1 = 0.f;
+                if (k >= 1) {
+                    const float2 al = s_tot[k];
+                    const float l0 = al.x * P[0] + al.y * Q[0], l1 = al.x * P[1] + al.y * Q[1];
+                    const float inv0 = P[0] != 0.f ? (H ? fast_rsqrt(l0) : fast_rcp(l0)) : 0.f;
+                    const float inv1 = P[1] != 0.f ? (H ? fast_rsqrt(l1) : fast_rcp(l1)) : 0.f;
+                    const float s0 = c * sr[q], s1 = c * si[q];
+                    w0 = s0 * inv0;
+                    w1 = s1 * inv1;
+                    acc += (double)s0 * (double)w0 + (double)s1 * (double)w1;
+                }
+                S.buf[k * CP + t.p] = make_float2(w0, w1);
+            }
+        };
+        if (a.half) scale_all(std::true_type{});
+        else scale_all(std::false_type{});
+        __syncthreads();
+        dst256_from_lds(S, s_tot, t, sr, si);
+        if (a.partials) {
+            const double sum = block_sum<NT>(acc, s_red);
+            if (threadIdx.x == 0) a.partials[blockIdx.x] = sum;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+        const int k = 16 * t.r + q;   // DST index 1..n -> row k - 1
+        if (k >= 1)
+            st_nt2(a.o + t.base + (long)(k - 1) * es, t.pad0 ? 0.f : c * sr[q], t.pad1 ? 0.f : c * si[q]);
+    }
+}
+
 // 32-point DFT of a line whose points 16..31 are zero (zero-padded input):
 // the radix-8 DFTs over n1 (points 4 n1 + n2) have their inputs 4..7 zero.
 __device__ inline void dft32_zin(float (&xr)[32], float (&xi)[32]) {

@@ -248,10 +248,13 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
     A.pro_p = pro_p;
     A.ctrl = ctrl;
     const double nb = (double)P->N * sizeof(T);
-    {
+    const int fp = is_f32<T>() ? 1 : 0;
+    auto runs = [&](int kind) { return P->tune_kind < 0 || P->tune_kind == kind; };
+    auto eng = [&](int kind) { return P->tune_kind == kind ? P->tune_eng : P->eng[fp][kind]; };
+    if (runs(K_TOEP_X)) {
         const int extra = o.pro == PRO_PUPDATE ? 2 : (o.pro == PRO_SCALE ? 1 : 0);
         ProfScope ps(P, K_TOEP_X, is_f32<T>(), nb * (3 + extra));
-        HIP_TRY(launch_toep_x<T>(P->ax[0].L, A, nullptr, P->stream));
+        HIP_TRY(launch_toep_x<T>(P->ax[0].L, A, nullptr, P->stream, eng(K_TOEP_X)));
     }
     const double epi_bytes = o.epi == EPI_ADD_F ? (double)P->N * 8.0
                            : (o.epi == EPI_DOT_P || o.epi == EPI_RESID) ? nb : 0.0;
@@ -271,15 +274,16 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
         Y.dot_p = dot_p;
         Y.b = bvec;
         Y.partials = P->partials;
+        if (!runs(K_TOEP_Y)) return FSD_OK;
         ProfScope ps(P, K_TOEP_Y, is_f32<T>(), nb * 3 + epi_bytes);
-        HIP_TRY(launch_toep_s<T>(P->ax[1].L, Y, nparts, P->stream));
+        HIP_TRY(launch_toep_s<T>(P->ax[1].L, Y, nparts, P->stream, eng(K_TOEP_Y)));
         return FSD_OK;
     }
     Y.o1 = d;
     Y.o2 = e;
-    {
+    if (runs(K_TOEP_Y)) {
         ProfScope ps(P, K_TOEP_Y, is_f32<T>(), nb * 4);
-        HIP_TRY(launch_toep_s<T>(P->ax[1].L, Y, nullptr, P->stream));
+        HIP_TRY(launch_toep_s<T>(P->ax[1].L, Y, nullptr, P->stream, eng(K_TOEP_Y)));
     }
 
     ToepArgs<T> Z{};
@@ -296,8 +300,9 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
     Z.b = bvec;
     Z.partials = P->partials;
     Z.ctrl = ctrl;
+    if (!runs(K_TOEP_Z)) return FSD_OK;
     ProfScope ps(P, K_TOEP_Z, is_f32<T>(), nb * 3 + epi_bytes);
-    HIP_TRY(launch_toep_s<T>(P->ax[2].L, Z, nparts, P->stream));
+    HIP_TRY(launch_toep_s<T>(P->ax[2].L, Z, nparts, P->stream, eng(K_TOEP_Z)));
     return FSD_OK;
 }
 
@@ -398,6 +403,9 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
     Tables<T>& tb = tabs<T>(P);
     Vecs<T>& v = vecs<T>(P);
     const int last = P->dim - 1;
+    const int fp = is_f32<T>() ? 1 : 0;
+    auto runs = [&](int kind) { return P->tune_kind < 0 || P->tune_kind == kind; };
+    auto eng = [&](int kind) { return P->tune_kind == kind ? P->tune_eng : P->eng[fp][kind]; };
     auto mk = [&](int axis, PassGeo g, const T* u, T* o) {
         DstArgs<T> D{};
         D.g = g;
@@ -422,22 +430,24 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
         return G;
     };
     auto x_pass = [&](const T* u, T* o) -> fsd_status {
+        if (!runs(K_DST_X)) return FSD_OK;
         const double nb = 2.0 * (double)P->N * sizeof(T);
         ProfScope ps(P, K_DST_X, is_f32<T>(), nb);
         if (mfma(0)) {
             HIP_TRY(launch_gdst_row(mg(0, geo_x(P), u, o), P->stream));
         } else {
-            HIP_TRY(launch_dst_x<T>(P->ax[0].L, mk(0, geo_x(P), u, o), nullptr, P->stream));
+            HIP_TRY(launch_dst_x<T>(P->ax[0].L, mk(0, geo_x(P), u, o), nullptr, P->stream, eng(K_DST_X)));
         }
         return FSD_OK;
     };
     auto y_pass = [&](const T* u, T* o) -> fsd_status {
+        if (!runs(K_DST_Y)) return FSD_OK;
         const double nb = 2.0 * (double)P->N * sizeof(T);
         ProfScope ps(P, K_DST_Y, is_f32<T>(), nb);
         if (mfma(1)) {
             HIP_TRY(launch_gdst_col(mg(1, geo_y(P), u, o), false, nullptr, P->stream));
         } else {
-            HIP_TRY(launch_dst_s<T>(P->ax[1].L, mk(1, geo_y(P), u, o), nullptr, P->stream));
+            HIP_TRY(launch_dst_s<T>(P->ax[1].L, mk(1, geo_y(P), u, o), nullptr, P->stream, eng(K_DST_Y)));
         }
         return FSD_OK;
     };
@@ -451,7 +461,8 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
         mid = v.t[2];
     }
     // last axis: S, Lambda^{-1}, S with the Parseval partials of (r, P^{-1} r)
-    {
+    const int kl = last == 1 ? K_DSTS_Y : K_DSTS_Z;
+    if (runs(kl)) {
         const PassGeo gl = last == 1 ? geo_y(P) : geo_z(P);
         const double nb = 2.0 * (double)P->N * sizeof(T);
         ProfScope ps(P, last == 1 ? K_DSTS_Y : K_DSTS_Z, is_f32<T>(), nb);
@@ -477,7 +488,7 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
             if (P->dim == 3) { S.a2 = tb.a[1]; S.lc2 = tb.lc[1]; }
             S.partials = partials;
             S.half = half ? 1 : 0;
-            HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream));
+            HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream, eng(kl)));
         }
     }
     cur = mid;
@@ -1005,9 +1016,125 @@ fsd_status upload_all(fsd_problem P, Tables<T>& t) {
     return FSD_OK;
 }
 
+// ------------------------------------------------------------ engines
+// Public pass codes (fsd.h FSD_PASS_*) -> profiler kinds, per problem
+// dimension (the last axis carries the Lambda-scale pass).
+int pass_kind(fsd_problem P, int pass) {
+    switch (pass) {
+        case FSD_PASS_TOEP_X: return K_TOEP_X;
+        case FSD_PASS_TOEP_Y: return K_TOEP_Y;
+        case FSD_PASS_TOEP_Z: return P->dim == 3 ? K_TOEP_Z : -1;
+        case FSD_PASS_DST_X: return K_DST_X;
+        case FSD_PASS_DST_Y: return P->dim == 3 ? K_DST_Y : -1;
+        case FSD_PASS_DSTS_LAST: return P->dim == 3 ? K_DSTS_Z : K_DSTS_Y;
+        default: return -1;
+    }
+}
+
+// (axis, PassOp) of a pass kind
+void kind_pass(int kind, int& axis, int& op) {
+    switch (kind) {
+        case K_TOEP_X: axis = 0; op = OP_TOEP_X; break;
+        case K_TOEP_Y: axis = 1; op = OP_TOEP_S; break;
+        case K_TOEP_Z: axis = 2; op = OP_TOEP_S; break;
+        case K_DST_X: axis = 0; op = OP_DST_X; break;
+        case K_DST_Y: axis = 1; op = OP_DST_S; break;
+        case K_DSTS_Y: axis = 1; op = OP_DSTS_S; break;
+        default: axis = 2; op = OP_DSTS_S; break;   // K_DSTS_Z
+    }
+}
+
+const char* const kEngineNames[ENG_COUNT] = {"auto", "wave", "col", "colh", "stage", "stage_half"};
+
+// One application of the operator containing pass `kind`, running only
+// that pass with engine `eng`, on the workspace's scratch vectors (their
+// contents do not matter for timing; the zero padding is kept).
+template <typename T>
+fsd_status run_one_pass(fsd_problem P, int kind, int eng) {
+    Vecs<T>& v = vecs<T>(P);
+    P->tune_kind = kind;
+    P->tune_eng = eng;
+    fsd_status st;
+    if (kind == K_TOEP_X || kind == K_TOEP_Y || kind == K_TOEP_Z) {
+        MatvecOpts o;
+        st = op_matvec<T>(P, v.p, v.q, o, nullptr, nullptr, nullptr, nullptr, nullptr);
+    } else {
+        st = op_precond<T>(P, v.p, v.q, nullptr, nullptr, nullptr);
+    }
+    P->tune_kind = -1;
+    return st;
+}
+
+// Average time of `reps` launches of one pass (after two untimed ones).
+template <typename T>
+fsd_status time_pass(fsd_problem P, int kind, int eng, double* ms) {
+    const int reps = 5;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    fsd_status st = FSD_OK;
+    for (int i = 0; i < 2 && st == FSD_OK; ++i) st = run_one_pass<T>(P, kind, eng);
+    if (st == FSD_OK) {
+        (void)hipEventRecord(e0, P->stream);
+        for (int i = 0; i < reps && st == FSD_OK; ++i) st = run_one_pass<T>(P, kind, eng);
+        (void)hipEventRecord(e1, P->stream);
+    }
+    float t = 0.f;
+    hipError_t e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != FSD_OK) return st;
+    if (e != hipSuccess) return fail(FSD_EHIP, std::string("autotune timing: ") + hipGetErrorString(e));
+    *ms = t / reps;
+    return FSD_OK;
+}
+
+template <typename T>
+fsd_status autotune_prec(fsd_problem P) {
+    const int fp = is_f32<T>() ? 1 : 0;
+    for (int pass = 0; pass < FSD_PASS_COUNT; ++pass) {
+        const int kind = pass_kind(P, pass);
+        if (kind < 0) continue;
+        int axis, op;
+        kind_pass(kind, axis, op);
+        int cand[ENG_COUNT];
+        const int nc = pass_engines(op, P->ax[axis].L, is_f32<T>(), cand);
+        int best = ENG_AUTO;
+        double best_ms = 1e300;
+        for (int c = 0; c < nc; ++c) {
+            double ms = 0.0;
+            FSD_TRY(time_pass<T>(P, kind, cand[c], &ms));
+            if (ms < best_ms) { best_ms = ms; best = cand[c]; }
+        }
+        P->eng[fp][kind] = best;
+    }
+    return FSD_OK;
+}
+
 }  // namespace
 
 namespace fsd {
+// Engines that can run a pass (the default first): the wave engine serves
+// lengths 64..512, the column engine float32 strided passes of length 512
+// (its two DST variants for the DST passes), the stage engine every length
+// in two tile shapes where the default tile holds more than one line.
+int pass_engines(int op, int L, bool f32, int* out) {
+    int n = 0;
+    const bool wave = L == 64 || L == 128 || L == 256 || L == 512;
+    const bool strided = op == OP_TOEP_S || op == OP_DST_S || op == OP_DSTS_S;
+    const bool col = f32 && L == 512 && strided;
+    out[n++] = ENG_AUTO;
+    if (col) {
+        if (op == OP_DST_S) out[n++] = ENG_COLH;
+        if (op == OP_DSTS_S) out[n++] = ENG_COL;
+        out[n++] = ENG_WAVE;
+    }
+    if (wave) out[n++] = ENG_STAGE;
+    if (lines_per_block(L, !f32) > 1) out[n++] = ENG_STAGE_HALF;
+    return n;
+}
+
 // y = A x on the padded internal layout with caller-chosen intermediates
 // (four vectors of Np doubles): the float64 matvec of fsd_apply_A.
 fsd_status matvec64_with(fsd_problem P, const double* x, double* y, double* const tmp[4]) {
@@ -1142,7 +1269,8 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
         const int L = P->ax[i].L;
         const long outer = (i == 1) ? (P->dim == 3 ? p->n[2] : 1) : p->n[1];
         for (int f64 = 0; f64 < 2; ++f64) {
-            const int tx = 2 * lines_per_block(L, f64 != 0);
+            // the narrowest tile any engine uses: half the default stage tile
+            const int tx = 2 * std::max(1, lines_per_block(L, f64 != 0) / 2);
             mp = std::max<long>(mp, (long)(P->P1 / tx) * outer);
         }
         mp = std::max<long>(mp, ((long)(P->P1 / 16) * outer + 3) / 4);   // MFMA DST passes
@@ -1322,6 +1450,59 @@ fsd_status fsd_hbm_copy(const void* d_src, void* d_dst, size_t bytes, void* stre
     if (a < b + bytes && b < a + bytes) return fail(FSD_EINVAL, "source and destination overlap");
     HIP_TRY(stream_copy(d_src, d_dst, bytes, (hipStream_t)stream));
     return FSD_OK;
+}
+
+fsd_status fsd_set_engine(fsd_problem P, int precision, int pass, int engine) {
+    if (!P) return fail(FSD_EINVAL, "null problem");
+    if (precision != FSD_PREC_FP64 && precision != FSD_PREC_MIXED)
+        return fail(FSD_EINVAL, "precision: FSD_PREC_FP64 (float64 passes) or FSD_PREC_MIXED (float32)");
+    const int kind = pass_kind(P, pass);
+    if (kind < 0) return fail(FSD_EINVAL, "no such pass for this problem");
+    if (engine < FSD_ENGINE_AUTO || engine > FSD_ENGINE_STAGE_HALF) return fail(FSD_EINVAL, "unknown engine");
+    int axis, op;
+    kind_pass(kind, axis, op);
+    int cand[ENG_COUNT];
+    const int nc = pass_engines(op, P->ax[axis].L, precision == FSD_PREC_MIXED, cand);
+    bool ok = false;
+    for (int c = 0; c < nc; ++c) ok |= cand[c] == engine;
+    if (!ok) return fail(FSD_EUNSUPPORTED, "engine not available for this pass and length");
+    P->eng[precision == FSD_PREC_MIXED ? 1 : 0][kind] = engine;
+    drop_graphs(P);   // captured launches hold the old kernels
+    return FSD_OK;
+}
+
+fsd_status fsd_autotune(fsd_problem P) {
+    FSD_TRY(check_bound(P));
+    if (P->pc != FSD_PC_TAU) return fail(FSD_EINVAL, "the engines are tuned for the tau preconditioner");
+    const bool prof = P->prof_on;
+    P->prof_on = false;
+    fsd_status st = autotune_prec<double>(P);
+    if (st == FSD_OK && P->mixed) st = autotune_prec<float>(P);
+    P->prof_on = prof;
+    drop_graphs(P);
+    return st;
+}
+
+int fsd_engines(fsd_problem P, char* buf, int len) {
+    if (!P || (!buf && len > 0)) { fail(FSD_EINVAL, "null argument"); return -1; }
+    static const char* const pass_names[FSD_PASS_COUNT] = {"toep_x", "toep_y", "toep_z", "dst_x",
+                                                          "dst_y", "dsts_last"};
+    std::string out;
+    for (int fp = 0; fp < (P->mixed ? 2 : 1); ++fp)
+        for (int pass = 0; pass < FSD_PASS_COUNT; ++pass) {
+            const int kind = pass_kind(P, pass);
+            if (kind < 0) continue;
+            int axis, op;
+            kind_pass(kind, axis, op);
+            if (!out.empty()) out += ",";
+            out += std::string(pass_names[pass]) + (fp ? "_f32" : "_f64") + "(L=" +
+                   std::to_string(P->ax[axis].L) + ")=" + kEngineNames[P->eng[fp][kind]];
+        }
+    if (len > 0) {
+        std::strncpy(buf, out.c_str(), (size_t)len - 1);
+        buf[len - 1] = 0;
+    }
+    return (int)out.size();
 }
 
 fsd_status fsd_set_graphs(fsd_problem P, int on) {

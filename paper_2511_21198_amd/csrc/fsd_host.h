@@ -117,6 +117,12 @@ struct fsd_problem_s {
     double* cea[3] = {nullptr, nullptr, nullptr};
     double* ceb[3] = {nullptr, nullptr, nullptr};
 
+    // engine (tile shape) of each line pass, per precision (0: float64,
+    // 1: float32) and pass kind (the profiler's kinds K_TOEP_X..K_DSTS_Z);
+    // ENG_AUTO until fsd_autotune.  tune_kind >= 0 runs only that pass, with
+    // engine tune_eng (the autotuner's timing runs).
+    int eng[2][16] = {};
+    int tune_kind = -1, tune_eng = 0;
     // executable graphs of Krylov iteration chunks (fsd_set_graphs): key,
     // graph; captured on first use, dropped when the workspace is rebound
     bool use_graphs = false;

@@ -154,13 +154,35 @@ hipError_t launch_gdst_col(const GdstArgs& a, bool scale, int* nblocks, hipStrea
 int gdst_col_blocks(const PassGeo& g);
 
 // ---------------------------------------------------------------- launchers
-// Each launcher dispatches on the transform length L = 2(n+1) of the pass.
+// Each launcher dispatches on the transform length L = 2(n+1) of the pass
+// and on the engine (the tile shape) that runs it:
+//   ENG_AUTO        the default choice per length (below);
+//   ENG_WAVE        wave engine (lengths 64..512; fsd_wave.hpp);
+//   ENG_COL         column engine (float32 strided passes of length 512;
+//                   fsd_cols.hpp), the DST by the odd extension;
+//   ENG_COLH        column engine with the half-length DST-I (DST passes);
+//   ENG_STAGE       LDS-stage engine, lines_per_block lines per tile;
+//   ENG_STAGE_HALF  LDS-stage engine, half as many lines per tile.
+// Defaults: column engine for float32 strided passes of length 512 (the
+// half-length DST for the Lambda-scale pass), the wave engine for the
+// other lengths 64..512, the stage engine otherwise.  An engine a length
+// does not have falls back to the default.
+enum Engine : int { ENG_AUTO = 0, ENG_WAVE = 1, ENG_COL = 2, ENG_COLH = 3, ENG_STAGE = 4,
+                    ENG_STAGE_HALF = 5, ENG_COUNT = 6 };
 
-template <typename T> hipError_t launch_toep_x(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s);
-template <typename T> hipError_t launch_toep_s(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s);
-template <typename T> hipError_t launch_dst_x(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s);
-template <typename T> hipError_t launch_dst_s(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s);
-template <typename T> hipError_t launch_dsts_s(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s);
+template <typename T> hipError_t launch_toep_x(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s,
+                                               int eng = ENG_AUTO);
+template <typename T> hipError_t launch_toep_s(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s,
+                                               int eng = ENG_AUTO);
+template <typename T> hipError_t launch_dst_x(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s,
+                                              int eng = ENG_AUTO);
+template <typename T> hipError_t launch_dst_s(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s,
+                                              int eng = ENG_AUTO);
+template <typename T> hipError_t launch_dsts_s(int L, const DstArgs<T>& a, int* nblocks, hipStream_t s,
+                                               int eng = ENG_AUTO);
+// Engines that run a pass of length L (first: the default).
+enum PassOp : int { OP_TOEP_X = 0, OP_TOEP_S = 1, OP_DST_X = 2, OP_DST_S = 3, OP_DSTS_S = 4 };
+int pass_engines(int op, int L, bool f32, int* out);
 
 // Complex lines per workgroup tile for transform length L (two real lines
 // each).  Sized so one tile plus its twiddle table stays below 80 KB of LDS
@@ -179,11 +201,14 @@ __host__ __device__ constexpr bool twiddles_in_lds(int L) { return L <= 2048; }
 
 // Threads per workgroup tile: about one radix-8 butterfly per thread per
 // stage (NCL * L / 8), rounded down to a power of two in [64, 512].
-__host__ __device__ constexpr int threads_per_block(int L, bool fp64) {
-    int w = lines_per_block(L, fp64) * L / 8;
+__host__ __device__ constexpr int threads_for_lines(int L, int ncl) {
+    int w = ncl * L / 8;
     int t = 64;
     while (t * 2 <= w && t < 512) t *= 2;
     return t;
+}
+__host__ __device__ constexpr int threads_per_block(int L, bool fp64) {
+    return threads_for_lines(L, lines_per_block(L, fp64));
 }
 
 // Transform lengths with a compiled plan: L = 2(n+1) in {2^a, 3*2^a}, 4..8192.

@@ -53,11 +53,12 @@ __host__ __device__ constexpr Plan make_plan(int L) {
     return p;
 }
 
-template <typename T, int L>
+// NC: complex lines per tile (the tile shape; default lines_per_block).
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
 struct Tile {
     static constexpr bool kF64 = sizeof(T) == 8;
-    static constexpr int NCL = lines_per_block(L, kF64);
-    static constexpr int NT = threads_per_block(L, kF64);
+    static constexpr int NCL = NC;
+    static constexpr int NT = threads_for_lines(L, NC);
     static constexpr int TX = 2 * NCL;          // real lines per tile
     static constexpr int SH = kF64 ? 4 : 5;     // LDS padding: one slot per 2^SH
     static constexpr int LP = L + (L >> SH) + 1; // padded line pitch in LDS
@@ -138,11 +139,11 @@ __device__ inline void dft(T* xr, T* xi) {
 // Twiddle t is (twr[t TWS2], twi[t TWS2]): split LDS arrays (TWS2 = 1) or
 // the interleaved global table (TWS2 = 2, twi = twr + 1).
 
-template <typename T, int L, int R, int M, int TWS2 = 1>
+template <typename T, int L, int R, int M, int TWS2, int NC>
 __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
                                  const T* __restrict__ twr, const T* __restrict__ twi,
                                  int tid) {
-    using TL = Tile<T, L>;
+    using TL = Tile<T, L, NC>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
     constexpr int NBL = L / R;
     constexpr int NB = NCL * NBL;
@@ -199,14 +200,14 @@ __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
     __syncthreads();
 }
 
-template <typename T, int L, int S, int M, int TWS2>
+template <typename T, int L, int S, int M, int TWS2, int NC>
 struct FFTRun {
     __device__ static inline void run(T* re, T* im, const T* twr, const T* twi, int tid) {
         constexpr Plan P = make_plan(L);
         if constexpr (S < P.nst) {
             constexpr int R = P.r[S];
-            fft_stage<T, L, R, M, TWS2>(re, im, twr, twi, tid);
-            FFTRun<T, L, S + 1, M * R, TWS2>::run(re, im, twr, twi, tid);
+            fft_stage<T, L, R, M, TWS2, NC>(re, im, twr, twi, tid);
+            FFTRun<T, L, S + 1, M * R, TWS2, NC>::run(re, im, twr, twi, tid);
         }
     }
 };
@@ -221,13 +222,13 @@ struct TileTw {
     const T* i;
 };
 
-template <typename T, int L>
+template <typename T, int L, int NC>
 __device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr, T* s_twi, int tid);
 
 // Forward FFT of all NCL lines of the tile (input and output in LDS).
-template <typename T, int L>
+template <typename T, int L, int NC>
 __device__ inline void fft_lines(T* re, T* im, const TileTw<T, L>& tw, int tid) {
-    FFTRun<T, L, 0, 1, TileTw<T, L>::kLds ? 1 : 2>::run(re, im, tw.r, tw.i, tid);
+    FFTRun<T, L, 0, 1, TileTw<T, L>::kLds ? 1 : 2, NC>::run(re, im, tw.r, tw.i, tid);
 }
 
 // ------------------------------------------------------------- reductions
@@ -247,9 +248,9 @@ __device__ inline double block_sum(double v, double* sbuf) {
     return s;
 }
 
-template <typename T, int L>
+template <typename T, int L, int NC>
 __device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr, T* s_twi, int tid) {
-    constexpr int NT = Tile<T, L>::NT;
+    constexpr int NT = Tile<T, L, NC>::NT;
     if constexpr (TileTw<T, L>::kLds) {
         for (int e = tid; e < L; e += NT) {
             s_twr[e] = tw[2 * e];
@@ -262,9 +263,9 @@ __device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr,
 }
 
 // Y = conj(C * Z) for every entry of every line (Toeplitz spectrum multiply).
-template <typename T, int L>
+template <typename T, int L, int NC>
 __device__ inline void spectrum_multiply(T* re, T* im, const T* __restrict__ spec, int tid) {
-    using TL = Tile<T, L>;
+    using TL = Tile<T, L, NC>;
     for (int e = tid; e < TL::NCL * L; e += TL::NT) {
         const int line = e / L, f = e - line * L;
         const int a = line * TL::LP + TL::idx(f);
@@ -279,9 +280,9 @@ __device__ inline void spectrum_multiply(T* re, T* im, const T* __restrict__ spe
 // ------------------------------------------------------------ x-axis pass
 // Lines are rows (contiguous): tile = 2*NCL consecutive rows.
 
-template <typename T, int L>
-__global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
-    using TL = Tile<T, L>;
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
+__global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_toep_x(ToepArgs<T> a) {
+    using TL = Tile<T, L, NC>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
@@ -290,7 +291,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
     const int tid = threadIdx.x;
     const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
     const int row0 = blockIdx.x * (2 * NCL);
-    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
 
     T beta = 0, scale = 1;
     bool first = true;
@@ -339,9 +340,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
         }
     }
 
-    fft_lines<T, L>(s_re, s_im, tw, tid);
-    spectrum_multiply<T, L>(s_re, s_im, a.spec, tid);
-    fft_lines<T, L>(s_re, s_im, tw, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
+    spectrum_multiply<T, L, NC>(s_re, s_im, a.spec, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
 
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
@@ -359,9 +360,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_x(ToepArgs<T> a) {
 // Tile = 2*NCL consecutive x positions at one outer index; element (x, i)
 // of the tile sits at o*ostride + x + i*estride.
 
-template <typename T, int L>
-__global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
-    using TL = Tile<T, L>;
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
+__global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_toep_s(ToepArgs<T> a) {
+    using TL = Tile<T, L, NC>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
     constexpr int GRP = NT / TX;
     if (a.ctrl && a.ctrl->done) return;
@@ -377,7 +378,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
     const int x0 = xt * TX;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
-    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
 
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     for (int i = ig; i < L; i += GRP) {
@@ -400,9 +401,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
         }
     }
 
-    fft_lines<T, L>(s_re, s_im, tw, tid);
-    spectrum_multiply<T, L>(s_re, s_im, a.spec, tid);
-    fft_lines<T, L>(s_re, s_im, tw, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
+    spectrum_multiply<T, L, NC>(s_re, s_im, a.spec, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
 
     // Output: thread handles the contiguous chunk [ib, ie) of its line so the
     // stencil on u_sten needs one new global load per output.
@@ -451,9 +452,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_toep_s(ToepArgs<T> a) {
 // After the FFT, DST(first)_k = -Im Z[k] * c2 and DST(second)_k = Re Z[k] * c2
 // with c2 = sqrt(2/(n+1))/2, k = 1..n.
 
-template <typename T, int L>
-__global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
-    using TL = Tile<T, L>;
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
+__global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dst_x(DstArgs<T> a) {
+    using TL = Tile<T, L, NC>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
@@ -462,7 +463,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
     const int tid = threadIdx.x;
     const int n = a.g.n, P1 = a.g.P1, nrows = a.g.nrows;
     const int row0 = blockIdx.x * (2 * NCL);
-    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
         const int row = row0 + rr;
@@ -477,7 +478,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
         if (tid == 0) { dst[TL::idx(0)] = 0; dst[TL::idx(n + 1)] = 0; }
     }
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, tw, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
         const int row = row0 + rr;
@@ -490,10 +491,10 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_x(DstArgs<T> a) {
     }
 }
 
-template <typename T, int L>
+template <typename T, int L, int NC>
 __device__ inline void dst_load_strided(const T* __restrict__ u, T* line, long base, long es,
                                         int n, int ig) {
-    using TL = Tile<T, L>;
+    using TL = Tile<T, L, NC>;
     constexpr int GRP = TL::NT / TL::TX;
     for (int i = ig; i < n; i += GRP) {
         const T v = u[base + (long)i * es];
@@ -503,9 +504,9 @@ __device__ inline void dst_load_strided(const T* __restrict__ u, T* line, long b
     if (ig == 0) { line[TL::idx(0)] = 0; line[TL::idx(n + 1)] = 0; }
 }
 
-template <typename T, int L>
-__global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
-    using TL = Tile<T, L>;
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
+__global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dst_s(DstArgs<T> a) {
+    using TL = Tile<T, L, NC>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
     constexpr int GRP = NT / TX;
     if (a.ctrl && a.ctrl->done) return;
@@ -519,11 +520,11 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
     const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + xt * TX + xl;
-    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
-    dst_load_strided<T, L>(a.u, line, base, es, n, ig);
+    dst_load_strided<T, L, NC>(a.u, line, base, es, n, ig);
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, tw, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
     // the DST of the real-part line is -Im Z, of the imaginary-part line Re Z
     const bool odd = xl & 1;
     const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
@@ -539,9 +540,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dst_s(DstArgs<T> a) {
 // Lambda on line (x, outer) at frequency k is a_last[k] * P + lc_last[k] * Q:
 //   2D (pass along y): P = a1 + lc1,                Q = a1        (x factors)
 //   3D (pass along z): P = a2 (a1 + lc1) + lc2 a1,  Q = a2 a1     (outer = y)
-template <typename T, int L>
-__global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
-    using TL = Tile<T, L>;
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
+__global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
+    using TL = Tile<T, L, NC>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP, TX = TL::TX;
     constexpr int GRP = NT / TX;
     if (a.ctrl && a.ctrl->done) return;
@@ -558,7 +559,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     const int x0 = xt * TX;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
-    const TileTw<T, L> tw = tile_twiddles<T, L>(a.tw, s_twr, s_twi, tid);
+    const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
     if (tid < TX) {
         const int x = x0 + tid;
         T P = 0, Q = 0;
@@ -577,9 +578,9 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
         s_Q[tid] = Q;
     }
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
-    dst_load_strided<T, L>(a.u, line, base, es, n, ig);
+    dst_load_strided<T, L, NC>(a.u, line, base, es, n, ig);
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, tw, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
 
     double acc = 0.0;
     for (int e = tid; e < NCL * L; e += NT) {
@@ -605,7 +606,7 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
         s_im[ad] = wi;
     }
     __syncthreads();
-    fft_lines<T, L>(s_re, s_im, tw, tid);
+    fft_lines<T, L, NC>(s_re, s_im, tw, tid);
     const bool odd = xl & 1;
     const T* other = (odd ? s_re : s_im) + (xl >> 1) * LP;
     const bool pad_line = xt * TX + xl >= a.g.nx;   // stored as exact zeros
@@ -626,88 +627,15 @@ __global__ __launch_bounds__((Tile<T, L>::NT)) void k_dsts_s(DstArgs<T> a) {
     X(256) X(384) X(512) X(768) X(1024) X(1536) X(2048) X(3072) X(4096) X(6144) X(8192)
 
 template <typename T>
-inline int x_blocks(int L, int nrows) {
-    int ncl = lines_per_block(L, sizeof(T) == 8);
+inline int x_blocks(int L, int nrows, int ncl = 0) {
+    if (ncl <= 0) ncl = lines_per_block(L, sizeof(T) == 8);
     return (nrows + 2 * ncl - 1) / (2 * ncl);
 }
 
 template <typename T>
-inline int s_blocks(int L, int P1, int n_outer) {
-    int ncl = lines_per_block(L, sizeof(T) == 8);
+inline int s_blocks(int L, int P1, int n_outer, int ncl = 0) {
+    if (ncl <= 0) ncl = lines_per_block(L, sizeof(T) == 8);
     return (P1 / (2 * ncl)) * n_outer;
 }
-
-#define FSD_CASE_TOEP_X(LL) \
-    case LL: hipLaunchKernelGGL((k_toep_x<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
-#define FSD_CASE_TOEP_S(LL) \
-    case LL: hipLaunchKernelGGL((k_toep_s<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
-#define FSD_CASE_DST_X(LL) \
-    case LL: hipLaunchKernelGGL((k_dst_x<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
-#define FSD_CASE_DST_S(LL) \
-    case LL: hipLaunchKernelGGL((k_dst_s<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
-#define FSD_CASE_DSTS_S(LL) \
-    case LL: hipLaunchKernelGGL((k_dsts_s<FT, LL>), dim3(g), dim3(Tile<FT, LL>::NT), 0, s, a); break;
-
-#define FSD_DEFINE_LAUNCHERS(T)                                                              \
-    template <>                                                                              \
-    hipError_t launch_toep_x<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
-        using FT = T;                                                                        \
-        const int g = x_blocks<T>(L, a.g.nrows);                                             \
-        if (nb) *nb = g;                                                                     \
-        if (g == 0) return hipSuccess;                                                       \
-        switch (L) {                                                                         \
-            FSD_FOR_EACH_L(FSD_CASE_TOEP_X)                                                  \
-            default: return hipErrorInvalidValue;                                            \
-        }                                                                                    \
-        return hipGetLastError();                                                            \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_toep_s<T>(int L, const ToepArgs<T>& a, int* nb, hipStream_t s) {       \
-        using FT = T;                                                                        \
-        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);                                   \
-        if (nb) *nb = g;                                                                     \
-        if (g == 0) return hipSuccess;                                                       \
-        switch (L) {                                                                         \
-            FSD_FOR_EACH_L(FSD_CASE_TOEP_S)                                                  \
-            default: return hipErrorInvalidValue;                                            \
-        }                                                                                    \
-        return hipGetLastError();                                                            \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_dst_x<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
-        using FT = T;                                                                        \
-        const int g = x_blocks<T>(L, a.g.nrows);                                             \
-        if (nb) *nb = g;                                                                     \
-        if (g == 0) return hipSuccess;                                                       \
-        switch (L) {                                                                         \
-            FSD_FOR_EACH_L(FSD_CASE_DST_X)                                                   \
-            default: return hipErrorInvalidValue;                                            \
-        }                                                                                    \
-        return hipGetLastError();                                                            \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_dst_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {         \
-        using FT = T;                                                                        \
-        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);                                   \
-        if (nb) *nb = g;                                                                     \
-        if (g == 0) return hipSuccess;                                                       \
-        switch (L) {                                                                         \
-            FSD_FOR_EACH_L(FSD_CASE_DST_S)                                                   \
-            default: return hipErrorInvalidValue;                                            \
-        }                                                                                    \
-        return hipGetLastError();                                                            \
-    }                                                                                        \
-    template <>                                                                              \
-    hipError_t launch_dsts_s<T>(int L, const DstArgs<T>& a, int* nb, hipStream_t s) {        \
-        using FT = T;                                                                        \
-        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);                                   \
-        if (nb) *nb = g;                                                                     \
-        if (g == 0) return hipSuccess;                                                       \
-        switch (L) {                                                                         \
-            FSD_FOR_EACH_L(FSD_CASE_DSTS_S)                                                  \
-            default: return hipErrorInvalidValue;                                            \
-        }                                                                                    \
-        return hipGetLastError();                                                            \
-    }
 
 }  // namespace fsd

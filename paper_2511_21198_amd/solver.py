@@ -154,6 +154,26 @@ class Problem:
             check(s, "fsd_cn_step")
         return out, (st.as_dict() if stats else None)
 
+    def set_engine(self, pass_name: str, engine: str, precision: str = "fp64"):
+        """Engine of one line pass (fsd_set_engine): pass_name in
+        nat.PASSES, engine in nat.ENGINES, precision "fp64" (float64
+        passes) or "mixed" (float32 passes)."""
+        prec = nat.PREC_MIXED if precision == "mixed" else nat.PREC_FP64
+        check(lib.fsd_set_engine(self._h, prec, nat.PASSES[pass_name], nat.ENGINES[engine]),
+              "fsd_set_engine")
+
+    def autotune(self) -> str:
+        """Time every engine of every pass and keep the fastest
+        (fsd_autotune); returns the chosen engines."""
+        check(lib.fsd_autotune(self._h), "fsd_autotune")
+        return self.engines()
+
+    def engines(self) -> str:
+        n = lib.fsd_engines(self._h, None, 0)
+        buf = C.create_string_buffer(n + 1)
+        lib.fsd_engines(self._h, buf, n + 1)
+        return buf.value.decode()
+
     def set_graphs(self, on: bool = True):
         """Replay captured launch graphs of the Krylov iteration chunks
         (fsd_set_graphs)."""

@@ -173,3 +173,30 @@ def test_host_coefficients_match_oracle(nat, n, delta):
     assert abs(eta.value - pr.eta[0]) <= 1e-15 * pr.eta[0]
     assert nat.lib.fsd_get_coefficients(h, 2, None, None, None) == nat.EINVAL
     nat.lib.fsd_destroy(h)
+
+
+def test_engine_selection_host(nat):
+    """fsd_set_engine validates pass, engine and length on the host (no
+    device work); fsd_engines reports the choice; fsd_autotune needs a bound
+    workspace."""
+    s, h = _init(nat, _params(nat, dim=3, n=[255, 95, 63], precision=1))
+    assert s == nat.OK
+    assert nat.lib.fsd_autotune(h) == nat.ENOTBOUND
+    # float32 strided pass of length 512 on the x axis is not a column pass
+    assert nat.lib.fsd_set_engine(h, 1, nat.PASSES["toep_x"], nat.ENGINES["col"]) == nat.EUNSUPPORTED
+    assert nat.lib.fsd_set_engine(h, 0, 9, 0) == nat.EINVAL
+    assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["toep_x"], 7) == nat.EINVAL
+    assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["toep_x"], nat.ENGINES["stage"]) == nat.OK
+    assert nat.lib.fsd_set_engine(h, 1, nat.PASSES["dst_x"], nat.ENGINES["stage_half"]) == nat.OK
+    # y axis: n = 95 (length 192): stage engine only
+    assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["toep_y"], nat.ENGINES["wave"]) == nat.EUNSUPPORTED
+    n = nat.lib.fsd_engines(h, None, 0)
+    buf = C.create_string_buffer(n + 1)
+    assert nat.lib.fsd_engines(h, buf, n + 1) == n
+    txt = buf.value.decode()
+    assert "toep_x_f64(L=512)=stage" in txt and "dst_x_f32(L=512)=stage_half" in txt
+    assert "toep_y_f64(L=192)=auto" in txt and "dsts_last_f32(L=128)=auto" in txt
+    nat.lib.fsd_destroy(h)
+    s, h = _init(nat, _params(nat, dim=2, n=[255, 63]))
+    assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["toep_z"], 0) == nat.EINVAL   # 2D: no z pass
+    nat.lib.fsd_destroy(h)

@@ -1,6 +1,8 @@
 """The batched executor (include/fsd_batch.h) on the GPU: every problem's
-result is bitwise the one of its own fsd_cn_step, whatever the lane count;
-small float64 and mixed-precision members also match the float64 oracle."""
+result is bitwise the one of its own fsd_cn_step, whatever the lane count
+(until the autotuner moves passes to other engines: then to the solver
+tolerance); small float64 and mixed-precision members also match the
+float64 oracle."""
 import numpy as np
 import pytest
 
@@ -72,8 +74,14 @@ def test_batch_autotune_then_step(mods):
     lanes, ms = bt.autotune(us, Fs)
     assert (lanes, bt.graphs) in ms and all(v > 0 for v in ms.values())
     out, _ = bt.cn_step(us, Fs)
-    for a, b in zip(out, ref):
-        assert torch.equal(a, b)
+    # the autotuner may move passes to other engines (tile shapes): the
+    # operators then differ by rounding, and each step stops on the same
+    # test, so the results agree to the solver tolerance
+    for kw, a, b in zip(MEMBERS, out, ref):
+        e = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+        assert e <= 100 * kw["tol"], (e, kw)
+    for i in range(len(MEMBERS)):
+        assert "=" in bt.engines(i)
 
 
 def test_batch_members_match_oracle(mods):

@@ -207,6 +207,65 @@ def test_long_line_full_grid(fsd):
         del prob
 
 
+# Every engine (tile shape) of every line pass against the oracle: the wave
+# engine, the column engine with both DST variants, and the LDS-stage engine
+# with its default and its half-width tile, in float64 (1e-12) and float32
+# (1e-5), both norms.  Each run sets one pass's engine, the others default.
+ENGINE_CASES = [
+    (3, [255, 127, 95], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
+    (3, [63, 255, 255], [0.3, 0.5, 0.7], [1, 1, 1], [1, 1, 1]),
+    (2, [383, 255], [0.45, 0.65], [1.5, 0.5], [0.5, 1.5]),
+]
+
+
+@pytest.mark.parametrize("case", ENGINE_CASES, ids=[_ids(c) for c in ENGINE_CASES])
+def test_engines_vs_oracle(fsd, case):
+    from paper_2511_21198_amd import _native as nat
+    dim, n, d, kp, km = case
+    orc = op.Problem(dim, n, d, kp, km, T=0.8, M=7)
+    X = workloads.random_grid(orc.shape, 47)
+    A = op.apply_A(orc, X)
+    Pi = op.apply_Pinv(orc, X)
+    tried = 0
+    for pname in nat.PASSES:
+        for ename in nat.ENGINES:
+            for precision in ("fp64", "mixed"):
+                prob = fsd(dim, n, d, kp, km, M=7, T=0.8, precision=precision)
+                try:
+                    prob.set_engine(pname, ename, precision)
+                except nat.FsdError:
+                    continue   # pass absent in 2D, or engine not available at its length
+                tried += 1
+                x = dev(X)
+                if pname.startswith("toep"):
+                    y = prob.apply_A(x) if precision == "fp64" else prob.apply_A32(x)
+                    close(host(y), A, 1e-12 if precision == "fp64" else 1e-5, (pname, ename, precision))
+                else:
+                    z = prob.apply_Pinv(x) if precision == "fp64" else prob.apply_Pinv32(x)
+                    close(host(z), Pi, 1e-12 if precision == "fp64" else 1e-5, (pname, ename, precision))
+                del prob
+    assert tried >= 20, tried
+
+
+def test_autotuned_engines_cn_run(fsd):
+    """After fsd_autotune (engines chosen by timing) the CN steps still reach
+    the oracle's tightly solved steps (mixed precision, 1e-8; float64,
+    1e-10), and the report names an engine for every pass."""
+    dim, n, d, kp, km = (3, [63, 255, 95], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3])
+    orc = op.Problem(dim, n, d, kp, km, T=1.0, M=4)
+    rng = np.random.default_rng(53)
+    u0 = rng.standard_normal(orc.shape)
+    F = workloads.random_grid(orc.shape, 54)
+    u_ref, _ = cn.run(orc, u0, lambda m: F, tol=1e-13, x0_mode="prev", solver="gmres", steps=2)
+    for precision, bound, tol in (("fp64", 1e-10, 1e-13), ("mixed", 1e-8, 1e-12)):
+        prob = fsd(dim, n, d, kp, km, M=4, T=1.0, tol=tol, solver="gmres", precision=precision,
+                   inner_tol=1e-5)
+        report = prob.autotune()
+        assert len(report.split(",")) == (12 if precision == "mixed" else 6), report
+        u, _ = _run_gpu(prob, u0, lambda m: F, 2)
+        close(u, u_ref, bound, report)
+
+
 def _run_gpu(prob, u0, Fs, steps):
     u = dev(u0)
     its = []
