@@ -337,6 +337,7 @@ def learned_workload(a, seed=10001, n=255, M=200):
     finals = {}
     for name, prec, x0 in variants:
         p = Problem(**common, precision=prec, inner_tol=1e-4, x0=x0)
+        p.autotune()
         eta = [p.coefficients(i)[2] for i in range(3)]
         u = u0.clone()
         un = torch.empty_like(u)
@@ -454,6 +455,7 @@ def two_sided(w, F, u0, steps, warmup, tol):
     for name, kw in (("fp64", dict(precision="fp64")),
                      ("mixed", dict(precision="mixed", inner_tol=1e-3, max_outer=8))):
         p = Problem(**common, **kw)
+        p.autotune()
         r = repeat_timing(p, u0, F, w.M, steps, warmup, 3)
         out[name] = {"steps_per_s": round(r["steps_per_s"], 3), "iters": r["iters"],
                      "outer": r["outer"]}
@@ -514,10 +516,11 @@ def secondary_symmetric(a):
     for name, kw in (("fp64", dict(precision="fp64")),
                      ("mixed", dict(precision="mixed", inner_tol=1e-5))):
         p = Problem(**common, **kw)
+        engines = p.autotune()
         r = repeat_timing(p, u0, F, w.M, 8, 2, 3)
         us[name] = final_state(p, u0, F, 9)
         out[name] = {"steps_per_s": round(r["steps_per_s"], 2), "iqr": r["iqr"], "iters": r["iters"],
-                     "outer": r["outer"]}
+                     "outer": r["outer"], "engines": engines}
         del p
     pref = Problem(**{**common, "tol": 1e-13}, precision="fp64")
     uref = final_state(pref, u0, F, 9)
@@ -625,7 +628,9 @@ def main(argv=None):
         if x0:
             c["x0"] = x0
         p = Problem(**c, tol=t, **kw)
+        engines = p.autotune()   # tile shapes per pass, chosen at setup (untimed)
         r = repeat_timing(p, u0, F, w.M, a.steps, a.warmup, repeats or a.repeats, profile)
+        r["engines"] = engines
         r["u_final"] = final_state(p, u0, F, w.M) if not a.no_ref else None
         del p
         log(f"  {r['steps_per_s']:.3f} CN steps/s (IQR {r['iqr'][0]:.3f}..{r['iqr'][1]:.3f})")
@@ -676,12 +681,14 @@ def main(argv=None):
                                "8 seeded Gaussian bumps, u0=0, PGMRES(20) + sine-transform "
                                f"preconditioner from u^(m-1), tol {tol:g}; timed steps are taken "
                                "from steps 2..16 only (a pass restarts from u0, step 1 untimed); "
-                               f"value = median over {a.repeats} passes",
+                               f"value = median over {a.repeats} passes; line-pass engines from "
+                               "the library's autotuner at setup (untimed)",
                    "solver": f"{head}: " + (f"float32 inner GMRES (inner tol {inner_tol:g}) in "
                                              "float64 defect correction, float64 outer test"
                                              if head == "mixed" else "float64 GMRES"),
                    "tol": tol, "n": a.n, "unknowns": a.n ** 3},
         "iqr_steps_per_s": [round(v, 3) for v in H["iqr"]],
+        "engines": H.get("engines"),
         "per_repeat_steps_per_s": H["per_repeat"],
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": d["gbps"], "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": d["frac_datasheet"],

@@ -244,14 +244,16 @@ fsd_status fsd_cn_step(fsd_problem prob, const double* d_u_prev, const double* d
 
 /* Engines (tile shapes) of the line passes.  Every pass of the matvec and
  * of the preconditioner can run on more than one engine: the wave engine
- * (lengths 64..512), the column engine (float32 strided passes of length
- * 512; for DST passes with the DST-I by the odd extension or by the
- * half-length algorithm), and the LDS-stage engine with its default tile
- * or half of it.  All give the same operator to rounding.  FSD_ENGINE_AUTO
- * is the built-in choice per length. */
+ * (lengths 64..512; for float32 also with one line per lane group instead
+ * of two, FSD_ENGINE_WAVE1, which launches twice the wavefronts), the
+ * column engine (float32 strided passes of length 512; for DST passes with
+ * the DST-I by the odd extension or by the half-length algorithm), and the
+ * LDS-stage engine with its default tile or half of it.  All give the same
+ * operator to rounding.  FSD_ENGINE_AUTO is the built-in choice per
+ * length. */
 enum {
     FSD_ENGINE_AUTO = 0, FSD_ENGINE_WAVE = 1, FSD_ENGINE_COL = 2, FSD_ENGINE_COLH = 3,
-    FSD_ENGINE_STAGE = 4, FSD_ENGINE_STAGE_HALF = 5
+    FSD_ENGINE_STAGE = 4, FSD_ENGINE_STAGE_HALF = 5, FSD_ENGINE_WAVE1 = 6
 };
 /* Passes: Toeplitz x / y / z, DST x / y, and the DST-Lambda-DST pass of the
  * last axis (y in 2D, z in 3D). */

@@ -26,7 +26,7 @@ X0_PREV, X0_ZERO, X0_EXTERNAL, X0_EXTRAP, X0_GUARDED = 0, 1, 2, 3, 4
 # fsd_precond
 PC_TAU, PC_NONE, PC_TCHAN, PC_STRANG = 0, 1, 2, 3
 # engines and passes (fsd_set_engine)
-ENGINES = {"auto": 0, "wave": 1, "col": 2, "colh": 3, "stage": 4, "stage_half": 5}
+ENGINES = {"auto": 0, "wave": 1, "col": 2, "colh": 3, "stage": 4, "stage_half": 5, "wave1": 6}
 PASSES = {"toep_x": 0, "toep_y": 1, "toep_z": 2, "dst_x": 3, "dst_y": 4, "dsts_last": 5}
 
 

@@ -1044,7 +1044,8 @@ void kind_pass(int kind, int& axis, int& op) {
     }
 }
 
-const char* const kEngineNames[ENG_COUNT] = {"auto", "wave", "col", "colh", "stage", "stage_half"};
+const char* const kEngineNames[ENG_COUNT] = {"auto", "wave", "col", "colh", "stage", "stage_half",
+                                             "wave1"};
 
 // One application of the operator containing pass `kind`, running only
 // that pass with engine `eng`, on the workspace's scratch vectors (their
@@ -1116,9 +1117,10 @@ fsd_status autotune_prec(fsd_problem P) {
 
 namespace fsd {
 // Engines that can run a pass (the default first): the wave engine serves
-// lengths 64..512, the column engine float32 strided passes of length 512
-// (its two DST variants for the DST passes), the stage engine every length
-// in two tile shapes where the default tile holds more than one line.
+// lengths 64..512 (for float32 also with one line per lane group), the
+// column engine float32 strided passes of length 512 (its two DST variants
+// for the DST passes), the stage engine every length in two tile shapes
+// where the default tile holds more than one line.
 int pass_engines(int op, int L, bool f32, int* out) {
     int n = 0;
     const bool wave = L == 64 || L == 128 || L == 256 || L == 512;
@@ -1132,6 +1134,7 @@ int pass_engines(int op, int L, bool f32, int* out) {
     }
     if (wave) out[n++] = ENG_STAGE;
     if (lines_per_block(L, !f32) > 1) out[n++] = ENG_STAGE_HALF;
+    if (wave && f32) out[n++] = ENG_WAVE1;
     return n;
 }
 
@@ -1458,7 +1461,7 @@ fsd_status fsd_set_engine(fsd_problem P, int precision, int pass, int engine) {
         return fail(FSD_EINVAL, "precision: FSD_PREC_FP64 (float64 passes) or FSD_PREC_MIXED (float32)");
     const int kind = pass_kind(P, pass);
     if (kind < 0) return fail(FSD_EINVAL, "no such pass for this problem");
-    if (engine < FSD_ENGINE_AUTO || engine > FSD_ENGINE_STAGE_HALF) return fail(FSD_EINVAL, "unknown engine");
+    if (engine < FSD_ENGINE_AUTO || engine > FSD_ENGINE_WAVE1) return fail(FSD_EINVAL, "unknown engine");
     int axis, op;
     kind_pass(kind, axis, op);
     int cand[ENG_COUNT];

@@ -162,13 +162,15 @@ int gdst_col_blocks(const PassGeo& g);
 //                   fsd_cols.hpp), the DST by the odd extension;
 //   ENG_COLH        column engine with the half-length DST-I (DST passes);
 //   ENG_STAGE       LDS-stage engine, lines_per_block lines per tile;
-//   ENG_STAGE_HALF  LDS-stage engine, half as many lines per tile.
+//   ENG_STAGE_HALF  LDS-stage engine, half as many lines per tile;
+//   ENG_WAVE1       wave engine with one complex line per lane group
+//                   (float32; twice the wavefronts of ENG_WAVE).
 // Defaults: column engine for float32 strided passes of length 512 (the
 // half-length DST for the Lambda-scale pass), the wave engine for the
 // other lengths 64..512, the stage engine otherwise.  An engine a length
 // does not have falls back to the default.
 enum Engine : int { ENG_AUTO = 0, ENG_WAVE = 1, ENG_COL = 2, ENG_COLH = 3, ENG_STAGE = 4,
-                    ENG_STAGE_HALF = 5, ENG_COUNT = 6 };
+                    ENG_STAGE_HALF = 5, ENG_WAVE1 = 6, ENG_COUNT = 7 };
 
 template <typename T> hipError_t launch_toep_x(int L, const ToepArgs<T>& a, int* nblocks, hipStream_t s,
                                                int eng = ENG_AUTO);

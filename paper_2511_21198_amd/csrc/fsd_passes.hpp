@@ -1,7 +1,8 @@
 // Per-length dispatch of the line passes: float32 strided passes of length
 // 512 use the column engine (fsd_cols.hpp); lengths 64..512 otherwise use
 // the wave engine (fsd_wave.hpp); the other lengths the LDS-stage engine
-// (fsd_lines.hpp).
+// (fsd_lines.hpp).  A pass set to another engine (fsd_set_engine) runs on
+// it where that engine supports the length.
 #pragma once
 
 #include <type_traits>
@@ -62,27 +63,68 @@ template <typename T, int L, int NC> struct KDstsS { static constexpr auto kerne
 
 inline bool stage_engine(int eng) { return eng == ENG_STAGE || eng == ENG_STAGE_HALF; }
 
+// Lines per lane group of the wave engine: the default, or one for the
+// float passes on ENG_WAVE1.
+template <typename T, int L>
+constexpr int wave_lpl_default() { return WGeo<T, L>::LPL; }
+template <typename T>
+inline bool wave1(int eng) { return std::is_same<T, float>::value && eng == ENG_WAVE1; }
+
+template <typename T, int L, int LPLV>
+hipError_t wave_toep_x(const ToepArgs<T>& a, int* nb, hipStream_t s) {
+    constexpr int rows = 2 * WX<T, L, LPLV>::LINES;
+    constexpr int NT = WX<T, L, LPLV>::NT;
+    const int g = (a.g.nrows + rows - 1) / rows;
+    if (nb) *nb = g;
+    if (!g) return hipSuccess;
+    switch (a.pro) {
+        case PRO_PUPDATE:
+            hipLaunchKernelGGL((k2_toep_x<T, L, PRO_PUPDATE, LPLV>), dim3(g), dim3(NT), 0, s, a);
+            break;
+        case PRO_SCALE:
+            hipLaunchKernelGGL((k2_toep_x<T, L, PRO_SCALE, LPLV>), dim3(g), dim3(NT), 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((k2_toep_x<T, L, PRO_NONE, LPLV>), dim3(g), dim3(NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int L, int LPLV>
+hipError_t wave_dst_x(const DstArgs<T>& a, int* nb, hipStream_t s) {
+    constexpr int rows = 2 * WX<T, L, LPLV>::LINES;
+    const int g = (a.g.nrows + rows - 1) / rows;
+    if (nb) *nb = g;
+    if (g) hipLaunchKernelGGL((k2_dst_x<T, L, LPLV>), dim3(g), dim3(WX<T, L, LPLV>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int L, int LPLV>
+hipError_t wave_toep_s(const ToepArgs<T>& a, int* nb, hipStream_t s) {
+    static_assert(WS<T, L, LPLV>::TX == 2 * lines_per_block(L, sizeof(T) == 8), "tile width");
+    const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
+    if (nb) *nb = g;
+    if (g) hipLaunchKernelGGL((k2_toep_s<T, L, LPLV>), dim3(g), dim3(WS<T, L, LPLV>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int L, bool SCALE, int LPLV>
+hipError_t wave_dst_s(const DstArgs<T>& a, int* nb, hipStream_t s) {
+    static_assert(WS<T, L, LPLV>::TX == 2 * lines_per_block(L, sizeof(T) == 8), "tile width");
+    const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
+    if (nb) *nb = g;
+    if (g)
+        hipLaunchKernelGGL((k2_dst_s<T, L, SCALE, LPLV>), dim3(g), dim3(WS<T, L, LPLV>::NT), 0, s, a);
+    return hipGetLastError();
+}
+
 template <typename T, int L>
 hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s, int eng) {
     if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
     if constexpr (wave_engine_length<L>()) {
         if (!stage_engine(eng)) {
-            constexpr int rows = 2 * WX<T, L>::LINES;
-            const int g = (a.g.nrows + rows - 1) / rows;
-            if (nb) *nb = g;
-            if (g) {
-                switch (a.pro) {
-                    case PRO_PUPDATE:
-                        hipLaunchKernelGGL((k2_toep_x<T, L, PRO_PUPDATE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-                        break;
-                    case PRO_SCALE:
-                        hipLaunchKernelGGL((k2_toep_x<T, L, PRO_SCALE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-                        break;
-                    default:
-                        hipLaunchKernelGGL((k2_toep_x<T, L, PRO_NONE>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-                }
-            }
-            return hipGetLastError();
+            if (wave1<T>(eng)) return wave_toep_x<T, L, 1>(a, nb, s);
+            return wave_toep_x<T, L, wave_lpl_default<T, L>()>(a, nb, s);
         }
     }
     return stage_x_launch<T, L, KToepX>(a, nb, s, eng);
@@ -115,11 +157,8 @@ hipError_t toep_s_one(const ToepArgs<T>& a, int* nb, hipStream_t s, int eng) {
     }
     if constexpr (wave_engine_length<L>()) {
         if (!stage_engine(eng)) {
-            static_assert(WS<T, L>::TX == 2 * lines_per_block(L, sizeof(T) == 8), "tile width");
-            const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
-            if (nb) *nb = g;
-            if (g) hipLaunchKernelGGL((k2_toep_s<T, L>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
-            return hipGetLastError();
+            if (wave1<T>(eng)) return wave_toep_s<T, L, 1>(a, nb, s);
+            return wave_toep_s<T, L, wave_lpl_default<T, L>()>(a, nb, s);
         }
     }
     return stage_s_launch<T, L, KToepS>(a, nb, s, eng);
@@ -130,11 +169,8 @@ hipError_t dst_x_one(const DstArgs<T>& a, int* nb, hipStream_t s, int eng) {
     if (a.g.n != L / 2 - 1) return hipErrorInvalidValue;   // the kernels take n = L/2 - 1
     if constexpr (wave_engine_length<L>()) {
         if (!stage_engine(eng)) {
-            constexpr int rows = 2 * WX<T, L>::LINES;
-            const int g = (a.g.nrows + rows - 1) / rows;
-            if (nb) *nb = g;
-            if (g) hipLaunchKernelGGL((k2_dst_x<T, L>), dim3(g), dim3(WX<T, L>::NT), 0, s, a);
-            return hipGetLastError();
+            if (wave1<T>(eng)) return wave_dst_x<T, L, 1>(a, nb, s);
+            return wave_dst_x<T, L, wave_lpl_default<T, L>()>(a, nb, s);
         }
     }
     return stage_x_launch<T, L, KDstX>(a, nb, s, eng);
@@ -159,10 +195,8 @@ hipError_t dst_s_one(const DstArgs<T>& a, int* nb, hipStream_t s, int eng) {
     }
     if constexpr (wave_engine_length<L>()) {
         if (!stage_engine(eng)) {
-            const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer);
-            if (nb) *nb = g;
-            if (g) hipLaunchKernelGGL((k2_dst_s<T, L, SCALE>), dim3(g), dim3(WS<T, L>::NT), 0, s, a);
-            return hipGetLastError();
+            if (wave1<T>(eng)) return wave_dst_s<T, L, SCALE, 1>(a, nb, s);
+            return wave_dst_s<T, L, SCALE, wave_lpl_default<T, L>()>(a, nb, s);
         }
     }
     if constexpr (SCALE) return stage_s_launch<T, L, KDstsS>(a, nb, s, eng);

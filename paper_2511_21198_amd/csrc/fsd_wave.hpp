@@ -12,8 +12,10 @@
 // is transposed between global rows and lines.
 //
 // Lines per wavefront: LW = 64/G; each lane may carry LPL lines at once
-// (LPL = 2 for float to give the float kernels the register reuse of the
-// double ones).
+// (by default LPL = 2 for float to give the float kernels the register
+// reuse of the double ones; the kernels take LPL as a template parameter,
+// and LPL = 1 for float is the engine with twice as many wavefronts per
+// line count, for grids too small to fill the chip).
 #pragma once
 
 #include "fsd_lines.hpp"
@@ -356,23 +358,23 @@ constexpr bool wave_engine_length() {
 // (2 LPL rows).  No workgroup barrier: loads and stores go straight between
 // global rows and registers.
 
-template <typename T, int L>
+template <typename T, int L, int LPLV = WGeo<T, L>::LPL>
 struct WX {
     using W = WGeo<T, L>;
     static constexpr int NW = 4;
     static constexpr int NT = 64 * NW;
-    static constexpr int LINES = NW * W::LW * W::LPL;   // complex lines per workgroup
+    static constexpr int LINES = NW * W::LW * LPLV;   // complex lines per workgroup
 };
 
 // The prologue (PRO_*) is a template parameter: one lean kernel per mode.
-template <typename T, int L, int PRO>
+template <typename T, int L, int PRO, int LPLV = WGeo<T, L>::LPL>
 __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     using W = WGeo<T, L>;
-    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    constexpr int G = W::G, LW = W::LW, LPL = LPLV, LP = W::LP;
     constexpr int NN = L / 2 - 1;   // line length n; points q >= 4 are the zero padding
     if (a.ctrl && a.ctrl->done) return;
-    __shared__ T s_re[WX<T, L>::LINES * LP];
-    __shared__ T s_im[WX<T, L>::LINES * LP];
+    __shared__ T s_re[WX<T, L, LPLV>::LINES * LP];
+    __shared__ T s_im[WX<T, L, LPLV>::LINES * LP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, tl = lane % G;
     const int P1 = a.g.P1, nrows = a.g.nrows;
@@ -389,7 +391,7 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
         const int slot = wave * LW * LPL + g + LW * p;
         re[p] = s_re + slot * LP;
         im[p] = s_im + slot * LP;
-        const int line = blockIdx.x * WX<T, L>::LINES + slot;
+        const int line = blockIdx.x * WX<T, L, LPLV>::LINES + slot;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = 2 * line + h;
@@ -431,7 +433,7 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
         wave_sync();
 #pragma unroll
         for (int p = 0; p < LPL; ++p) {
-            const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+            const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 const int row = 2 * line + h;
@@ -460,7 +462,7 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     wfft_n<T, L, false, true, LPL>(xr, xi, tl, tw, re, im);
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
-        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+        const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = 2 * line + h;
@@ -480,21 +482,21 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
 // the mirrored half V[L-j] = -V[j] comes back through the line's LDS region
 // (reading it a second time from global memory, in reversed lane order,
 // measured 1.7x slower).
-template <typename T, int L>
+template <typename T, int L, int LPLV = WGeo<T, L>::LPL>
 __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
     using W = WGeo<T, L>;
-    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    constexpr int G = W::G, LW = W::LW, LPL = LPLV, LP = W::LP;
     constexpr int NN = L / 2 - 1;
     if (a.ctrl && a.ctrl->done) return;
-    __shared__ T s_re[WX<T, L>::LINES * LP];
-    __shared__ T s_im[WX<T, L>::LINES * LP];
+    __shared__ T s_re[WX<T, L, LPLV>::LINES * LP];
+    __shared__ T s_im[WX<T, L, LPLV>::LINES * LP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, tl = lane % G;
     const int P1 = a.g.P1, nrows = a.g.nrows;
     T xr[LPL][8], xi[LPL][8];
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
-        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+        const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = 2 * line + h;
@@ -551,7 +553,7 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
     }
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
-        const int line = blockIdx.x * WX<T, L>::LINES + wave * LW * LPL + g + LW * p;
+        const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             const int row = 2 * line + h;
@@ -616,12 +618,12 @@ __device__ inline void line_regs_odd(T (&xr)[8], T (&xi)[8], int tl, const T* re
 // positions (a 128-byte row segment) at one outer index.  Three workgroup
 // barriers: after the row loads, after the A_n stencil, before the row stores.
 
-template <typename T, int L>
+template <typename T, int L, int LPLV = WGeo<T, L>::LPL>
 struct WS {
     using W = WGeo<T, L>;
     static constexpr int NCL = sizeof(T) == 8 ? 8 : 16;
     static constexpr int TX = 2 * NCL;
-    static constexpr int NW = NCL / (W::LW * W::LPL);
+    static constexpr int NW = NCL / (W::LW * LPLV);
     static constexpr int NT = 64 * NW;
     static constexpr int GRP = NT / TX;
     // Minimum wavefronts per SIMD the strided DST pass is compiled for:
@@ -631,11 +633,11 @@ struct WS {
     static constexpr int MINW = sizeof(T) == 8 ? 1 : 4;
 };
 
-template <typename T, int L>
-__global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
+template <typename T, int L, int LPLV = WGeo<T, L>::LPL>
+__global__ __launch_bounds__((WS<T, L, LPLV>::NT)) void k2_toep_s(ToepArgs<T> a) {
     using W = WGeo<T, L>;
-    using S = WS<T, L>;
-    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    using S = WS<T, L, LPLV>;
+    constexpr int G = W::G, LW = W::LW, LPL = LPLV, LP = W::LP;
     constexpr int NCL = S::NCL, TX = S::TX, NT = S::NT, GRP = S::GRP;
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];
@@ -789,12 +791,12 @@ __global__ __launch_bounds__((WS<T, L>::NT)) void k2_toep_s(ToepArgs<T> a) {
 // Parseval partial sums of (r, P^{-1} r).  The tile's LDS allows about four
 // wavefronts per SIMD; for float the register budget is held to that (128
 // VGPRs), or the SCALE variant at L = 512 would drop to one workgroup per CU.
-template <typename T, int L, bool SCALE>
-__global__ __launch_bounds__((WS<T, L>::NT)) __attribute__((amdgpu_waves_per_eu(WS<T, L>::MINW)))
-void k2_dst_s(DstArgs<T> a) {
+template <typename T, int L, bool SCALE, int LPLV = WGeo<T, L>::LPL>
+__global__ __launch_bounds__((WS<T, L, LPLV>::NT))
+__attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs<T> a) {
     using W = WGeo<T, L>;
-    using S = WS<T, L>;
-    constexpr int G = W::G, LW = W::LW, LPL = W::LPL, LP = W::LP;
+    using S = WS<T, L, LPLV>;
+    constexpr int G = W::G, LW = W::LW, LPL = LPLV, LP = W::LP;
     constexpr int NCL = S::NCL, TX = S::TX, NT = S::NT, GRP = S::GRP;
     if (a.ctrl && a.ctrl->done) return;
     __shared__ T s_re[NCL * LP];

@@ -1,7 +1,8 @@
 """Summarise rocprofv3 output of a solver run per kernel kind.
 
     python -m paper_2511_21198_amd.rocprof_summary --trace DIR [--fetch DIR]
-        [--write DIR] --np NP [--json OUT.json] [--md OUT.md] [--cmd "..."]
+        [--write DIR] [--sq DIR] [--mfma DIR] --np NP [--json OUT.json]
+        [--md OUT.md] [--cmd "..."]
 
 DIR is a rocprofv3 ``-d`` directory written with ``-f csv``: ``--trace`` one
 of ``--kernel-trace --stats``, ``--fetch`` / ``--write`` one of
@@ -64,8 +65,8 @@ def source_hash(kind: str | None = None) -> str:
 
 _KINDS = [
     (re.compile(r"k_col_toep\b"), "toep_s"),
-    (re.compile(r"k_col_dst\s*<\s*true"), "dsts"),
-    (re.compile(r"k_col_dst\b"), "dst_y"),
+    (re.compile(r"k_col_dsth?\s*<\s*true"), "dsts"),
+    (re.compile(r"k_col_dsth?\b"), "dst_y"),
     (re.compile(r"k2?_toep_x\b"), "toep_x"),
     (re.compile(r"k2?_toep_s\b"), "toep_s"),
     (re.compile(r"k2?_dst_x\b"), "dst_x"),
@@ -211,6 +212,59 @@ def mfma_summary(mfma_dir, res, dim=3):
     return out
 
 
+SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU",
+               "SQ_ACTIVE_INST_LDS", "SQ_LDS_BANK_CONFLICT", "SQ_BUSY_CYCLES", "SQ_WAVE_CYCLES",
+               "GRBM_GUI_ACTIVE")
+SIMDS = 1024   # 256 compute units x 4 SIMDs
+CUS = 256
+
+
+def sq_summary(sq_dir, dim=3):
+    """Per kind: the shader counters per dispatch, averaged over the
+    dispatches that did their work (those enqueued after the solve had
+    stopped return at once: below a quarter of the kind's largest VALU
+    instruction count), and the fractions derived from them:
+
+      valu_busy  = 4 SQ_ACTIVE_INST_VALU / (SIMDS GRBM_GUI_ACTIVE)
+      lds_busy   = 4 SQ_ACTIVE_INST_LDS  / (SIMDS GRBM_GUI_ACTIVE)
+      bank_conflict = SQ_LDS_BANK_CONFLICT / (CUS GRBM_GUI_ACTIVE)
+
+    (the ACTIVE_INST counters count quad-cycles per SIMD; GRBM_GUI_ACTIVE
+    is the dispatch's GPU-busy cycles), and VALU / LDS instructions per
+    wavefront."""
+    rows = _read(sq_dir, "*counter_collection.csv")
+    key = "Dispatch_Id" if "Dispatch_Id" in rows[0] else "Correlation_Id"
+    by_id = collections.OrderedDict()
+    for r in rows:
+        if r["Counter_Name"] in SQ_COUNTERS:
+            d = by_id.setdefault(r[key], {"Kernel_Name": r["Kernel_Name"]})
+            d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    disp = list(by_id.values())
+    per = collections.defaultdict(list)
+    for d, k in zip(disp, classify(disp, dim)):
+        if k is not None:
+            per[k].append(d)
+    out = {}
+    for k, ds in per.items():
+        top = max(d.get("SQ_INSTS_VALU", 0.0) for d in ds)
+        ds = [d for d in ds if d.get("SQ_INSTS_VALU", 0.0) >= 0.25 * top]
+        if not ds:
+            continue
+        e = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in SQ_COUNTERS}
+        e["dispatches"] = len(ds)
+        g = e["GRBM_GUI_ACTIVE"]
+        w = e["SQ_WAVES"]
+        if g > 0:
+            e["valu_busy"] = 4.0 * e["SQ_ACTIVE_INST_VALU"] / (SIMDS * g)
+            e["lds_busy"] = 4.0 * e["SQ_ACTIVE_INST_LDS"] / (SIMDS * g)
+            e["bank_conflict"] = e["SQ_LDS_BANK_CONFLICT"] / (CUS * g)
+        if w > 0:
+            e["valu_per_wave"] = e["SQ_INSTS_VALU"] / w
+            e["lds_per_wave"] = e["SQ_INSTS_LDS"] / w
+        out[k] = e
+    return out
+
+
 def _stats_table(trace_dir: str, top: int):
     """Markdown rows of the rocprofv3 --stats kernel summary in trace_dir."""
     paths = glob.glob(os.path.join(trace_dir, "**", "*kernel_stats.csv"), recursive=True)
@@ -244,6 +298,7 @@ def main(argv=None):
     ap.add_argument("--cmd", default="", help="the profiled command, recorded in the outputs")
     ap.add_argument("--title", default="")
     ap.add_argument("--mfma", help="rocprofv3 -d directory of a --pmc run of " + " ".join(MFMA_COUNTERS))
+    ap.add_argument("--sq", help="rocprofv3 -d directory of a --pmc run of " + " ".join(SQ_COUNTERS))
     ap.add_argument("--scale-from", help="summary JSON whose k_cast counter scale factors to use "
                                          "when this run launched no k_cast")
     a = ap.parse_args(argv)
@@ -257,6 +312,9 @@ def main(argv=None):
     mf = mfma_summary(a.mfma, res, a.dim) if a.mfma else None
     if mf:
         doc["mfma"] = mf
+    sq = sq_summary(a.sq, a.dim) if a.sq else None
+    if sq:
+        doc["sq"] = sq
     if a.json:
         with open(a.json, "w") as f:
             json.dump(doc, f, indent=1, sort_keys=True)
@@ -290,6 +348,20 @@ def main(argv=None):
             lines.append(f"| {k} | {m:.4g} | {m * 512 / 1e9:.2f} | {e.get('SQ_VALU_MFMA_BUSY_CYCLES', 0):.4g} | "
                          f"{e.get('SQ_BUSY_CYCLES', 0):.4g} | {e.get('GRBM_GUI_ACTIVE', 0):.4g} | "
                          f"{e.get('bf16_tflops', 0):.1f} |")
+    if sq:
+        lines += ["", "Shader counters (per dispatch, averaged over the dispatches that did their "
+                  "work): VALU busy = 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE), LDS "
+                  "busy likewise from SQ_ACTIVE_INST_LDS, bank conflict = SQ_LDS_BANK_CONFLICT / "
+                  "(256 CUs x GRBM_GUI_ACTIVE):", "",
+                  "| kind | waves | VALU instr/wave | LDS instr/wave | VALU busy | LDS busy | bank conflict | GRBM active |",
+                  "|---|---:|---:|---:|---:|---:|---:|---:|"]
+        order = sorted(sq, key=lambda k: -res.get(k, {}).get("total_ms", 0.0))
+        for k in order:
+            e = sq[k]
+            lines.append(f"| {k} | {e['SQ_WAVES']:.0f} | {e.get('valu_per_wave', 0):.0f} | "
+                         f"{e.get('lds_per_wave', 0):.0f} | {e.get('valu_busy', 0):.2f} | "
+                         f"{e.get('lds_busy', 0):.2f} | {e.get('bank_conflict', 0):.3f} | "
+                         f"{e['GRBM_GUI_ACTIVE']:.4g} |")
     stats = _stats_table(a.trace, 25)
     if stats:
         lines += ["", "rocprofv3 `--stats` kernel summary of the same run (`*_kernel_stats.csv`, "

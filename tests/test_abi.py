@@ -190,12 +190,17 @@ def test_engine_selection_host(nat):
     assert nat.lib.fsd_set_engine(h, 1, nat.PASSES["dst_x"], nat.ENGINES["stage_half"]) == nat.OK
     # y axis: n = 95 (length 192): stage engine only
     assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["toep_y"], nat.ENGINES["wave"]) == nat.EUNSUPPORTED
+    assert nat.lib.fsd_set_engine(h, 1, nat.PASSES["toep_y"], nat.ENGINES["wave1"]) == nat.EUNSUPPORTED
+    # one line per lane group: float32 wave-engine lengths only
+    assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["dst_x"], nat.ENGINES["wave1"]) == nat.EUNSUPPORTED
+    assert nat.lib.fsd_set_engine(h, 1, nat.PASSES["toep_z"], nat.ENGINES["wave1"]) == nat.OK
     n = nat.lib.fsd_engines(h, None, 0)
     buf = C.create_string_buffer(n + 1)
     assert nat.lib.fsd_engines(h, buf, n + 1) == n
     txt = buf.value.decode()
     assert "toep_x_f64(L=512)=stage" in txt and "dst_x_f32(L=512)=stage_half" in txt
     assert "toep_y_f64(L=192)=auto" in txt and "dsts_last_f32(L=128)=auto" in txt
+    assert "toep_z_f32(L=128)=wave1" in txt
     nat.lib.fsd_destroy(h)
     s, h = _init(nat, _params(nat, dim=2, n=[255, 63]))
     assert nat.lib.fsd_set_engine(h, 0, nat.PASSES["toep_z"], 0) == nat.EINVAL   # 2D: no z pass
