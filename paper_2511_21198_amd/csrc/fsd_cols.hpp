@@ -173,9 +173,23 @@ __device__ inline Tile tile_of(const PassGeo& g) {
     return t;
 }
 
-__device__ inline void load_tw(Smem& S, const float* __restrict__ tw) {
-    for (int e = threadIdx.x; e < L; e += NT) S.tw[e] = make_float2(tw[2 * e], tw[2 * e + 1]);
+// Table of L values into LDS, L / NT per thread.  The trip count is a
+// constant and the loop unrolled, so every load of a thread is issued
+// before the first LDS store (a loop over threadIdx.x would wait for each
+// load in turn at the start of every workgroup).
+__device__ inline void stage_table(float2* dst, const float* __restrict__ src) {
+    static_assert(L % NT == 0, "table length");
+    float2 v[L / NT];
+#pragma unroll
+    for (int k = 0; k < L / NT; ++k) {
+        const int e = threadIdx.x + k * NT;
+        v[k] = make_float2(src[2 * e], src[2 * e + 1]);
+    }
+#pragma unroll
+    for (int k = 0; k < L / NT; ++k) dst[threadIdx.x + k * NT] = v[k];
 }
+
+__device__ inline void load_tw(Smem& S, const float* __restrict__ tw) { stage_table(S.tw, tw); }
 
 __device__ inline const float2* row2(const float* v, long off) {
     return reinterpret_cast<const float2*>(v + off);
@@ -655,7 +669,7 @@ void k_col_toep(ToepArgs<T> a) {
     const int o = blockIdx.x / (a.g.P1 / TX);
     const int x = (int)(t.base - (long)o * a.g.ostride);
     load_tw(S, a.tw);
-    for (int e = threadIdx.x; e < L; e += NT) s_spec[e] = make_float2(a.spec[2 * e], a.spec[2 * e + 1]);
+    stage_table(s_spec, a.spec);
     float xr[32], xi[32];
     {
         float2 v[16];

@@ -25,7 +25,22 @@ namespace fsd {
 namespace {
 
 typedef short g_s4 __attribute__((ext_vector_type(4)));
+typedef short g_s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 g_bf8 __attribute__((ext_vector_type(8)));
 typedef float g_f4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 32 bf16 product (gfx950) over 16 K values carried twice:
+// the A operand's halves a0 | a1 and the B operand's halves b0 | b1 fill the
+// instruction's 32 K slots in the same order, so D += a0 b0 + a1 b1 with
+// each pair taken over the same 16 K values (the hardware pairs A and B K
+// slots by lane and element alike, whatever order it sums them in).
+__device__ inline g_f4 g_mfma_pair(const g_s4& a0, const g_s4& a1, const g_s4& b0, const g_s4& b1,
+                                   const g_f4& c) {
+    const g_s8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const g_s8 b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(g_bf8, a),
+                                                   __builtin_bit_cast(g_bf8, b), c, 0, 0, 0);
+}
 
 __device__ inline unsigned short g_f2bf(float f) {
     unsigned u = __float_as_uint(f);
@@ -58,29 +73,36 @@ __device__ inline void g_stage(const void* frag, int s, g_s4* lds) {
 }
 
 // ------------------------------------------------------------ x axis
-// One wavefront: 32 rows (two 16-row tiles) x all n16 outputs.  Input rows
-// have pitch P1 >= n16 and zero padding, so the K range needs no guard.
+// One wavefront: MR = 2 16-row tiles x all n16 outputs, so that each S
+// fragment read from LDS feeds two products (one row tile per wavefront
+// runs at higher occupancy but measured slower at n = 255: 71 against
+// 58 us).  Input rows have pitch P1 >= n16 and zero padding, so the K range
+// needs no guard.
+template <int NT>
+constexpr int gdst_row_tiles() { return 2; }
+
 template <int NT>
 __global__ __launch_bounds__(256) void k_gdst_row(GdstArgs a) {
+    constexpr int MR = gdst_row_tiles<NT>();
     __shared__ g_s4 fs[2][NT * 64];
     if (a.ctrl && a.ctrl->done) return;
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const long r0 = wave * 32;
+    const long r0 = wave * 16 * MR;
     const long nrows = a.g.nrows;
     const int P1 = a.g.P1, n = a.g.n;
     const int c = lane & 15, g = lane >> 4;
-    g_f4 acc[2][NT];
+    g_f4 acc[MR][NT];
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[m][t] = g_f4{0.f, 0.f, 0.f, 0.f};
     g_stage<NT>(a.frag, 0, fs[0]);
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
-        g_s4 hi[2], lo[2];
+        g_s4 hi[MR], lo[MR];
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
+        for (int m = 0; m < MR; ++m) {
             const long row = r0 + m * 16 + c;
             float v[4] = {0.f, 0.f, 0.f, 0.f};
             if (row < nrows) {
@@ -96,16 +118,13 @@ __global__ __launch_bounds__(256) void k_gdst_row(GdstArgs a) {
         for (int t = 0; t < NT; ++t) {
             const g_s4 b = F[t * 64];
 #pragma unroll
-            for (int m = 0; m < 2; ++m) {
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(hi[m], b, acc[m][t], 0, 0, 0);
-                acc[m][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(lo[m], b, acc[m][t], 0, 0, 0);
-            }
+            for (int m = 0; m < MR; ++m) acc[m][t] = g_mfma_pair(hi[m], lo[m], b, b, acc[m][t]);
         }
     }
     if (r0 >= nrows) return;
     // D[row][k]: lane holds k = 16 t + c for rows 16 m + 4 g + r
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+    for (int m = 0; m < MR; ++m)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const long row = r0 + m * 16 + 4 * g + r;
@@ -161,8 +180,7 @@ __global__ __launch_bounds__(256) void k_gdst_col(GdstArgs a) {
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
             const g_s4 f = F[t * 64];
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f, hi, acc[t], 0, 0, 0);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f, lo, acc[t], 0, 0, 0);
+            acc[t] = g_mfma_pair(f, f, hi, lo, acc[t]);
         }
     }
     if constexpr (SCALE) {
@@ -211,8 +229,7 @@ __global__ __launch_bounds__(256) void k_gdst_col(GdstArgs a) {
 #pragma unroll
             for (int t = 0; t < NT; ++t) {
                 const g_s4 f = F[t * 64];
-                acc2[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f, hi, acc2[t], 0, 0, 0);
-                acc2[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(f, lo, acc2[t], 0, 0, 0);
+                acc2[t] = g_mfma_pair(f, f, hi, lo, acc2[t]);
             }
         }
 #pragma unroll
@@ -258,11 +275,14 @@ bool gdst_supported(int n) {
 
 hipError_t launch_gdst_row(const GdstArgs& a, hipStream_t s) {
     const int nt = (a.g.n + 15) / 16;
-    const long waves = (a.g.nrows + 31) / 32;
-    const int g = (int)((waves + 3) / 4);
-    if (g == 0) return hipSuccess;
     switch (nt) {
-#define GDST_R(NT_) case NT_: hipLaunchKernelGGL((k_gdst_row<NT_>), dim3(g), dim3(256), 0, s, a); break;
+#define GDST_R(NT_)                                                                         \
+    case NT_: {                                                                             \
+        constexpr long rows = 16L * gdst_row_tiles<NT_>();                                   \
+        const int g = (int)(((a.g.nrows + rows - 1) / rows + 3) / 4);                       \
+        if (g) hipLaunchKernelGGL((k_gdst_row<NT_>), dim3(g), dim3(256), 0, s, a);          \
+        break;                                                                              \
+    }
         GDST_R(1) GDST_R(2) GDST_R(3) GDST_R(4) GDST_R(6) GDST_R(8) GDST_R(12) GDST_R(16)
 #undef GDST_R
         default: return hipErrorInvalidValue;

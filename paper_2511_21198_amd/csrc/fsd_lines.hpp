@@ -65,6 +65,30 @@ struct Tile {
     __device__ static constexpr int idx(int e) { return e + (e >> SH); }
 };
 
+// Strided gather i = i0, i0 + S, ... (i < n <= NMAX): v = ld(i), then
+// st(i, v).  The trip count is bounded by a constant and the loads go in
+// chunks of up to eight per thread before their stores, so a thread waits
+// for memory once per chunk instead of once per element (a plain loop
+// waits for each load before its store).
+template <typename T, int NMAX, int S, typename Ld, typename St>
+__device__ inline void gather_chunked(int i0, int n, Ld&& ld, St&& st) {
+    constexpr int NIT = (NMAX + S - 1) / S;
+    constexpr int CH = NIT < 8 ? NIT : 8;
+    for (int c = 0; c < NIT; c += CH) {
+        T v[CH];
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int i = i0 + (c + k) * S;
+            v[k] = (c + k < NIT && i < n) ? ld(i) : T(0);
+        }
+#pragma unroll
+        for (int k = 0; k < CH; ++k) {
+            const int i = i0 + (c + k) * S;
+            if (c + k < NIT && i < n) st(i, v[k]);
+        }
+    }
+}
+
 // ------------------------------------------------------------ butterflies
 // Forward DFT of size R on (xr, xi), sign exp(-2 pi i r s / R).
 
@@ -252,10 +276,10 @@ template <typename T, int L, int NC>
 __device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr, T* s_twi, int tid) {
     constexpr int NT = Tile<T, L, NC>::NT;
     if constexpr (TileTw<T, L>::kLds) {
-        for (int e = tid; e < L; e += NT) {
-            s_twr[e] = tw[2 * e];
-            s_twi[e] = tw[2 * e + 1];
-        }
+        gather_chunked<T, L, NT>(tid, L, [&](int e) { return tw[2 * e]; },
+                                 [&](int e, T v) { s_twr[e] = v; });
+        gather_chunked<T, L, NT>(tid, L, [&](int e) { return tw[2 * e + 1]; },
+                                 [&](int e, T v) { s_twi[e] = v; });
         return TileTw<T, L>{s_twr, s_twi};
     } else {
         return TileTw<T, L>{tw, tw + 1};
@@ -298,27 +322,34 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_toep_x(ToepArgs<T> a) 
     if (a.pro == PRO_PUPDATE) { first = a.ctrl->first != 0; beta = (T)a.ctrl->beta; }
     if (a.pro == PRO_SCALE) scale = (T)a.ctrl->gm_scale;
 
+    // rows into the tile; all global loads first (LDS stores do not order
+    // them), the prologue's global stores after: pro_p may alias u_fft as
+    // far as the compiler knows, so a store between loads would serialise
+    // them
 #pragma unroll
     for (int rr = 0; rr < 2 * NCL; ++rr) {
         const int row = row0 + rr;
         T* dst = ((rr & 1) ? s_im : s_re) + (rr >> 1) * LP;
         const bool rv = row < nrows;
         const long base = (long)row * P1;
-        for (int i = tid; i < L; i += NT) {
-            T v = 0;
-            if (rv && i < n) {
-                if (a.pro == PRO_PUPDATE) {
-                    const T z = a.u_fft[base + i];
-                    v = first ? z : z + beta * a.pro_p[base + i];
-                    st_nt(a.pro_p + base + i, v);
-                } else if (a.pro == PRO_SCALE) {
-                    v = scale * a.u_fft[base + i];
-                    st_nt(a.pro_p + base + i, v);
-                } else {
-                    v = a.u_fft[base + i];
-                }
+        gather_chunked<T, L, NT>(
+            tid, L, [&](int i) { return (rv && i < n) ? a.u_fft[base + i] : T(0); },
+            [&](int i, T v) { dst[TL::idx(i)] = v; });
+    }
+    if (a.pro == PRO_PUPDATE || a.pro == PRO_SCALE) {
+#pragma unroll
+        for (int rr = 0; rr < 2 * NCL; ++rr) {
+            const int row = row0 + rr;
+            T* dst = ((rr & 1) ? s_im : s_re) + (rr >> 1) * LP;
+            if (row >= nrows) continue;
+            const long base = (long)row * P1;
+            for (int i = tid; i < n; i += NT) {
+                const T z = dst[TL::idx(i)];   // written by this thread above
+                const T v = a.pro == PRO_SCALE ? scale * z
+                          : first ? z : z + beta * a.pro_p[base + i];
+                st_nt(a.pro_p + base + i, v);
+                dst[TL::idx(i)] = v;
             }
-            dst[TL::idx(i)] = v;
         }
     }
     __syncthreads();
@@ -381,11 +412,9 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_toep_s(ToepArgs<T> a) 
     const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
 
     T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
-    for (int i = ig; i < L; i += GRP) {
-        T v = 0;
-        if (i < n) v = a.u_fft[base + (long)i * es];
-        line[TL::idx(i)] = v;
-    }
+    gather_chunked<T, L, GRP>(
+        ig, L, [&](int i) { return i < n ? a.u_fft[base + (long)i * es] : T(0); },
+        [&](int i, T v) { line[TL::idx(i)] = v; });
     __syncthreads();
 
     // Padding lines (x >= n1) share a complex FFT with an interior line, so
@@ -419,26 +448,52 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_toep_s(ToepArgs<T> a) 
         prev = ib > 0 ? a.u_sten[base + (long)(ib - 1) * es] : T(0);
         cur = a.u_sten[base + (long)ib * es];
     }
-    for (int i = ib; i < ie; ++i) {
-        T v = sgn * line[TL::idx(i)];
-        if (has_sten) {
-            const T next = (i + 1 < n) ? a.u_sten[base + (long)(i + 1) * es] : T(0);
-            v += (prev + T(6) * cur + next) * T(0.125);
-            prev = cur;
-            cur = next;
+    // chunks of eight outputs: the chunk's loads (the stencil's next values
+    // and the epilogue operand) go out together before its arithmetic
+    constexpr int CHN = (L / 2 - 1 + GRP - 1) / GRP;   // outputs per thread (n = L/2 - 1)
+    constexpr int OC = CHN < 8 ? CHN : 8;
+    for (int c0 = ib; c0 < ie; c0 += OC) {
+        T nx[OC], ex[OC];
+#pragma unroll
+        for (int k = 0; k < OC; ++k) {
+            const int i = c0 + k;
+            const long gi = base + (long)i * es;
+            nx[k] = (has_sten && i < ie && i + 1 < n) ? a.u_sten[gi + es] : T(0);
+            ex[k] = T(0);
+            if (i < ie) {
+                if (a.epi == EPI_ADD_F) {
+                    if (x < a.g.n1)
+                        ex[k] = (T)(a.dt * a.F[x + (long)a.g.n1 * ((long)i * a.g.fr_i +
+                                                                     (long)o * a.g.fr_o)]);
+                } else if (a.epi == EPI_DOT_P) {
+                    ex[k] = a.dot_p[gi];
+                } else if (a.epi == EPI_RESID) {
+                    ex[k] = a.b[gi];
+                }
+            }
         }
-        const long gi = base + (long)i * es;
-        if (pad_line) v = T(0);
-        if (a.epi == EPI_ADD_F) {
-            if (x < a.g.n1)
-                v += (T)(a.dt * a.F[x + (long)a.g.n1 * ((long)i * a.g.fr_i + (long)o * a.g.fr_o)]);
-        } else if (a.epi == EPI_DOT_P) {
-            acc += (double)a.dot_p[gi] * (double)v;
-        } else if (a.epi == EPI_RESID) {
-            v = a.b[gi] - v;
-            acc += (double)v * (double)v;
+#pragma unroll
+        for (int k = 0; k < OC; ++k) {
+            const int i = c0 + k;
+            if (i >= ie) break;
+            T v = sgn * line[TL::idx(i)];
+            if (has_sten) {
+                v += (prev + T(6) * cur + nx[k]) * T(0.125);
+                prev = cur;
+                cur = nx[k];
+            }
+            const long gi = base + (long)i * es;
+            if (pad_line) v = T(0);
+            if (a.epi == EPI_ADD_F) {
+                v += ex[k];
+            } else if (a.epi == EPI_DOT_P) {
+                acc += (double)ex[k] * (double)v;
+            } else if (a.epi == EPI_RESID) {
+                v = ex[k] - v;
+                acc += (double)v * (double)v;
+            }
+            st_nt(a.o1 + gi, v);
         }
-        st_nt(a.o1 + gi, v);
     }
     if (a.epi == EPI_DOT_P || a.epi == EPI_RESID) {
         const double s = block_sum<NT>(acc, s_red);
@@ -470,11 +525,12 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dst_x(DstArgs<T> a) {
         T* dst = ((rr & 1) ? s_im : s_re) + (rr >> 1) * LP;
         const long base = (long)row * P1;
         const bool rv = row < nrows;
-        for (int i = tid; i < n; i += NT) {
-            const T v = rv ? a.u[base + i] : T(0);
-            dst[TL::idx(i + 1)] = v;
-            dst[TL::idx(L - 1 - i)] = -v;
-        }
+        gather_chunked<T, L / 2, NT>(
+            tid, n, [&](int i) { return rv ? a.u[base + i] : T(0); },
+            [&](int i, T v) {
+                dst[TL::idx(i + 1)] = v;
+                dst[TL::idx(L - 1 - i)] = -v;
+            });
         if (tid == 0) { dst[TL::idx(0)] = 0; dst[TL::idx(n + 1)] = 0; }
     }
     __syncthreads();
@@ -496,11 +552,12 @@ __device__ inline void dst_load_strided(const T* __restrict__ u, T* line, long b
                                         int n, int ig) {
     using TL = Tile<T, L, NC>;
     constexpr int GRP = TL::NT / TL::TX;
-    for (int i = ig; i < n; i += GRP) {
-        const T v = u[base + (long)i * es];
-        line[TL::idx(i + 1)] = v;
-        line[TL::idx(L - 1 - i)] = -v;
-    }
+    gather_chunked<T, L / 2, GRP>(
+        ig, n, [&](int i) { return u[base + (long)i * es]; },
+        [&](int i, T v) {
+            line[TL::idx(i + 1)] = v;
+            line[TL::idx(L - 1 - i)] = -v;
+        });
     if (ig == 0) { line[TL::idx(0)] = 0; line[TL::idx(n + 1)] = 0; }
 }
 
@@ -560,30 +617,55 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
     const TileTw<T, L> tw = tile_twiddles<T, L, NC>(a.tw, s_twr, s_twi, tid);
+    // factor loads before the tile's row loads, LDS stores after them: one
+    // wait for memory per workgroup
+    T fa1 = 0, fl1 = 0, fa2 = 0, fl2 = 0;
+    if (tid < TX && x0 + tid < a.g.nx) {
+        fa1 = a.a1[x0 + tid];
+        fl1 = a.lc1[x0 + tid];
+        if (a.dim == 3) {
+            fa2 = a.a2[o];
+            fl2 = a.lc2[o];
+        }
+    }
+    T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    dst_load_strided<T, L, NC>(a.u, line, base, es, n, ig);
     if (tid < TX) {
-        const int x = x0 + tid;
         T P = 0, Q = 0;
-        if (x < a.g.nx) {
-            const T a1 = a.a1[x], l1 = a.lc1[x];
+        if (x0 + tid < a.g.nx) {
             if (a.dim == 2) {
-                P = a1 + l1;
-                Q = a1;
+                P = fa1 + fl1;
+                Q = fa1;
             } else {
-                const T a2 = a.a2[o], l2 = a.lc2[o];
-                P = a2 * (a1 + l1) + l2 * a1;
-                Q = a2 * a1;
+                P = fa2 * (fa1 + fl1) + fl2 * fa1;
+                Q = fa2 * fa1;
             }
         }
         s_P[tid] = P;
         s_Q[tid] = Q;
     }
-    T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
-    dst_load_strided<T, L, NC>(a.u, line, base, es, n, ig);
     __syncthreads();
     fft_lines<T, L, NC>(s_re, s_im, tw, tid);
 
     double acc = 0.0;
-    for (int e = tid; e < NCL * L; e += NT) {
+    // the factors a_k, lc_k of a chunk of four entries are loaded together
+    // before the chunk's arithmetic (one wait for memory per chunk)
+    constexpr int NE = (NCL * L + NT - 1) / NT, EC = NE < 4 ? NE : 4;
+    for (int c = 0; c < NE; c += EC) {
+      T akc[EC], lkc[EC];
+#pragma unroll
+      for (int q = 0; q < EC; ++q) {
+        const int e = tid + (c + q) * NT;
+        const int f = e % L;
+        const int k = f <= n ? f : L - f;
+        const bool ok = c + q < NE && e < NCL * L && k >= 1 && k <= n;
+        akc[q] = ok ? a.a_last[k - 1] : T(0);
+        lkc[q] = ok ? a.lc_last[k - 1] : T(0);
+      }
+#pragma unroll
+      for (int q = 0; q < EC; ++q) {
+        const int e = tid + (c + q) * NT;
+        if (c + q >= NE || e >= NCL * L) break;
         const int ln = e / L, f = e - ln * L;
         const int ad = ln * LP + TL::idx(f);
         T wr = 0, wi = 0;
@@ -591,7 +673,7 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
         if (k >= 1 && k <= n && f != n + 1) {
             const T P0 = s_P[2 * ln], Q0 = s_Q[2 * ln];
             const T P1v = s_P[2 * ln + 1], Q1v = s_Q[2 * ln + 1];
-            const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
+            const T ak = akc[q], lk = lkc[q];
             const T lam0 = ak * P0 + lk * Q0;
             const T lam1 = ak * P1v + lk * Q1v;
             const T inv0 = P0 != T(0) ? (a.half ? T(1) / sqrt(lam0) : T(1) / lam0) : T(0);
@@ -604,6 +686,7 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
         }
         s_re[ad] = wr;
         s_im[ad] = wi;
+      }
     }
     __syncthreads();
     fft_lines<T, L, NC>(s_re, s_im, tw, tid);

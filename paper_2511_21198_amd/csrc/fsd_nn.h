@@ -3,7 +3,8 @@
 // Activations are bfloat16, channels-last ([batch][z][y][x][c], c fastest)
 // with a channel pitch that is a multiple of 4, so that four consecutive
 // channels of one voxel are one 8-byte load: that is the K-slice one lane
-// feeds to a 16x16x16 bf16 MFMA.  Accumulation is float32.
+// feeds to a 16x16x16 bf16 MFMA, or to one half of a 16x16x32 one (two
+// 16-value K steps per instruction).  Accumulation is float32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,7 +37,9 @@ struct NnDims {
 // 3x3x3 convolution (zero padding, stride 1) as an implicit GEMM on MFMA.
 // out[v][o] = bias[o] + sum_{tap, i} frag(o, tap, i) * in[v + off(tap)][i],
 // K index k = tap * cin_p + i (27 taps, cin_p channels), ks = ceil(27 cin_p / 16)
-// K-steps of 16.  frag holds the A operands: [ks][mb][64 lanes] x 4 bf16.
+// K-steps of 16 (one per 16x16x16 MFMA or two per 16x16x32 MFMA, by layer
+// shape).  frag holds the A operands:
+// [ks][mb][64 lanes] x 4 bf16.
 struct NnConvArgs {
     const bf16_t* in;
     int cin_p, cin_shift;

@@ -8,6 +8,20 @@ namespace fsd {
 namespace {
 
 typedef float nn_f4 __attribute__((ext_vector_type(4)));
+typedef short nn_s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 nn_bf8 __attribute__((ext_vector_type(8)));
+
+// Two consecutive 16-value K steps in one 16 x 16 x 32 bf16 product (gfx950):
+// A = a0 | a1 and B = b0 | b1 fill the instruction's 32 K slots in the same
+// order, so D += a0 b0 + a1 b1 (the hardware pairs A and B K slots by lane
+// and element alike, whatever order it sums them in).
+__device__ inline nn_f4 mfma_k32(const nn_s4& a0, const nn_s4& a1, const nn_s4& b0, const nn_s4& b1,
+                                 const nn_f4& c) {
+    const nn_s8 a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
+    const nn_s8 b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(nn_bf8, a),
+                                                   __builtin_bit_cast(nn_bf8, b), c, 0, 0, 0);
+}
 
 __device__ inline bf16_t f2bf(float f) {
     unsigned u = __float_as_uint(f);
@@ -99,7 +113,7 @@ __device__ constexpr int tap_off(int t) {
     return (((t / 9) * TYH + (t / 3) % 3) * TX + t % 3) * P;
 }
 
-template <int CP, int MB, int R>
+template <int CP, int MB, int R, bool K32>
 __global__ __launch_bounds__(256) void k_nn_conv(NnConvArgs a) {
     extern __shared__ bf16_t tile[];
     constexpr int P = CP + 4, Q4 = CP / 4, TX = 18, TYH = kConvTY + 2, TZH = R + 2;
@@ -179,32 +193,64 @@ __global__ __launch_bounds__(256) void k_nn_conv(NnConvArgs a) {
     // taps, selected by the lane group.
     const nn_s4* fr = a.frag + lane;
     const bf16_t* tw = tile + (w * TX + n) * P + (CP >= 16 ? 4 * g : CP == 8 ? 4 * (g & 1) : 0);
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-        nn_s4 av[MB];
-#pragma unroll
-        for (int m = 0; m < MB; ++m) av[m] = fr[(s * MB + m) * 64];
-        int off;
-        bool tv = true;
+    // LDS offset of this lane's 4 channels at K step s, and whether its tap
+    // exists (the last step may run past tap 26)
+    auto step_off = [&](int s, bool& tv) -> int {
+        tv = true;
         if constexpr (CP >= 16) {
-            off = tap_off<TYH, TX, P>((16 * s) / CP) + (16 * s) % CP;
+            return tap_off<TYH, TX, P>((16 * s) / CP) + (16 * s) % CP;
         } else if constexpr (CP == 8) {
             const int t0 = 2 * s, t1 = 2 * s + 1;
-            off = (g >> 1) ? tap_off<TYH, TX, P>(t1) : tap_off<TYH, TX, P>(t0);
             if (t1 >= 27) tv = (g >> 1) == 0;
+            return (g >> 1) ? tap_off<TYH, TX, P>(t1) : tap_off<TYH, TX, P>(t0);
         } else {
             const int t = 4 * s;
-            off = g == 0 ? tap_off<TYH, TX, P>(t) : g == 1 ? tap_off<TYH, TX, P>(t + 1)
-                : g == 2 ? tap_off<TYH, TX, P>(t + 2) : tap_off<TYH, TX, P>(t + 3);
             if (t + 3 >= 27) tv = t + g < 27;
+            return g == 0 ? tap_off<TYH, TX, P>(t) : g == 1 ? tap_off<TYH, TX, P>(t + 1)
+                 : g == 2 ? tap_off<TYH, TX, P>(t + 2) : tap_off<TYH, TX, P>(t + 3);
         }
+    };
+    // K32: K steps in pairs (s0 = 2 q, s1 = 2 q + 1), one K = 32 product per
+    // pair (an odd last step pairs with zeros); else one K = 16 product per
+    // step
+    if constexpr (!K32) {
+#pragma unroll
+        for (int s0 = 0; s0 < KS; ++s0) {
+            nn_s4 av[MB];
+#pragma unroll
+            for (int m = 0; m < MB; ++m) av[m] = fr[(s0 * MB + m) * 64];
+            bool tv0;
+            const int off0 = step_off(s0, tv0);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                nn_s4 bv = {0, 0, 0, 0};
+                if (tv0) bv = *reinterpret_cast<const nn_s4*>(tw + off0 + r * (TYH * TX * P));
+#pragma unroll
+                for (int m = 0; m < MB; ++m)
+                    acc[r][m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[m], bv, acc[r][m], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int s0 = 0; K32 && s0 < KS; s0 += 2) {
+        const int s1 = s0 + 1;
+        const bool has1 = s1 < KS;
+        nn_s4 av0[MB], av1[MB];
+#pragma unroll
+        for (int m = 0; m < MB; ++m) {
+            av0[m] = fr[(s0 * MB + m) * 64];
+            av1[m] = has1 ? fr[(s1 * MB + m) * 64] : nn_s4{0, 0, 0, 0};
+        }
+        bool tv0, tv1 = false;
+        const int off0 = step_off(s0, tv0);
+        const int off1 = has1 ? step_off(s1, tv1) : 0;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            nn_s4 bv = {0, 0, 0, 0};
-            if (tv) bv = *reinterpret_cast<const nn_s4*>(tw + off + r * (TYH * TX * P));
+            nn_s4 bv0 = {0, 0, 0, 0}, bv1 = {0, 0, 0, 0};
+            if (tv0) bv0 = *reinterpret_cast<const nn_s4*>(tw + off0 + r * (TYH * TX * P));
+            if (has1 && tv1) bv1 = *reinterpret_cast<const nn_s4*>(tw + off1 + r * (TYH * TX * P));
 #pragma unroll
-            for (int m = 0; m < MB; ++m)
-                acc[r][m] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av[m], bv, acc[r][m], 0, 0, 0);
+            for (int m = 0; m < MB; ++m) acc[r][m] = mfma_k32(av0[m], av1[m], bv0, bv1, acc[r][m]);
         }
     }
     const int x = x0 + n, y = y0 + w;
@@ -337,7 +383,8 @@ __global__ void k_nn_pool_bwd_add_mask(const bf16_t* __restrict__ gc, const bf16
 // ---------------------------------------------------------------- wgrad
 
 // One wavefront: a 16 (output channels) x 16 (K columns) tile of dW over one
-// chunk of voxels; each MFMA takes 16 voxels (4 per lane group).
+// chunk of voxels; each MFMA takes 32 voxels (two groups of 16, 4 per lane
+// group each).
 __global__ __launch_bounds__(256) void k_nn_wgrad(NnWgradArgs a, int mbn, int kn, long nwaves) {
     const int lane = threadIdx.x & 63;
     const long wave = (long)blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -355,8 +402,8 @@ __global__ __launch_bounds__(256) void k_nn_wgrad(NnWgradArgs a, int mbn, int kn
     const long v0 = chunk * a.vchunk;
     const long v1 = v0 + a.vchunk < V ? v0 + a.vchunk : V;
     nn_f4 acc = {0.f, 0.f, 0.f, 0.f};
-    for (long vb = v0; vb < v1; vb += 16) {
-        nn_s4 av, bv;
+    // 16 voxels (4 per lane group) of the K range
+    auto load = [&](long vb, nn_s4& av, nn_s4& bv) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const long v = vb + 4 * g + e;
@@ -374,7 +421,13 @@ __global__ __launch_bounds__(256) void k_nn_wgrad(NnWgradArgs a, int mbn, int kn
             av[e] = ga;
             bv[e] = xb;
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc, 0, 0, 0);
+    };
+    // 32 voxels per K = 32 product (voxels past v1 load as zeros)
+    for (long vb = v0; vb < v1; vb += 32) {
+        nn_s4 av0, bv0, av1, bv1;
+        load(vb, av0, bv0);
+        load(vb + 16, av1, bv1);
+        acc = mfma_k32(av0, av1, bv0, bv1, acc);
     }
     // D[row = output channel][col = K column]: lane holds col j, rows 4g + r
     const long pitch = (long)kn * 16;
@@ -599,21 +652,25 @@ hipError_t nn_conv(const NnConvArgs& a, int mb, hipStream_t s) {
                       ((a.d.D + R - 1) / R);
     const size_t lds = (size_t)18 * (kConvTY + 2) * (R + 2) * (a.cin_p + 4) * sizeof(bf16_t);
     const dim3 g((unsigned)nblk);
-#define NN_CONV_CASE(CP_, MB_, R_)                                                              \
+#define NN_CONV_CASE(CP_, MB_, R_, K32_)                                                        \
     if (a.cin_p == CP_ && mb == MB_ && R == R_) {                                               \
-        hipLaunchKernelGGL((k_nn_conv<CP_, MB_, R_>), g, dim3(256), lds, s, a);                  \
+        hipLaunchKernelGGL((k_nn_conv<CP_, MB_, R_, K32_>), g, dim3(256), lds, s, a);            \
         return hipGetLastError();                                                               \
     }
     // the (input pitch, output blocks) pairs of the network's forward and
-    // input-gradient convolutions
-    NN_CONV_CASE(8, 1, 4)
-    NN_CONV_CASE(16, 2, 4)
-    NN_CONV_CASE(32, 4, 4)
-    NN_CONV_CASE(64, 4, 2)
-    NN_CONV_CASE(64, 2, 2)
-    NN_CONV_CASE(32, 1, 4)
-    NN_CONV_CASE(16, 1, 4)
-    NN_CONV_CASE(4, 1, 4)
+    // input-gradient convolutions, with the MFMA shape measured faster at
+    // 255^3 (K = 32 products where the pairing's extra registers cost no
+    // occupancy: 251 against 261 us for 32 -> 16 channels, 112 against 116
+    // and 43 against 57 us at 64 input channels; K = 16 elsewhere, e.g.
+    // 441 against 498 us for 5 -> 16 channels)
+    NN_CONV_CASE(8, 1, 4, false)
+    NN_CONV_CASE(16, 2, 4, false)
+    NN_CONV_CASE(32, 4, 4, false)
+    NN_CONV_CASE(64, 4, 2, true)
+    NN_CONV_CASE(64, 2, 2, true)
+    NN_CONV_CASE(32, 1, 4, true)
+    NN_CONV_CASE(16, 1, 4, false)
+    NN_CONV_CASE(4, 1, 4, false)
 #undef NN_CONV_CASE
     return hipErrorInvalidValue;
 }

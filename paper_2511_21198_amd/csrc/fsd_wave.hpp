@@ -367,6 +367,9 @@ struct WX {
 };
 
 // The prologue (PRO_*) is a template parameter: one lean kernel per mode.
+// Float is held to four wavefronts per SIMD (128 VGPRs): the LDS of a
+// workgroup allows four, and the two-line float kernel would take a few
+// registers more than that budget.
 template <typename T, int L, int PRO, int LPLV = WGeo<T, L>::LPL>
 __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     using W = WGeo<T, L>;
@@ -386,6 +389,10 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     T xr[LPL][8], xi[LPL][8];
     T* re[LPL];
     T* im[LPL];
+    // Every load of the lane is issued before the prologue's first store:
+    // pro_p may alias u_fft as far as the compiler knows, so a store between
+    // two loads would make each load wait for the one before it.
+    T pv[PRO == PRO_PUPDATE ? LPL : 1][2][4];   // PRO_PUPDATE: the old p
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
         const int slot = wave * LW * LPL + g + LW * p;
@@ -400,24 +407,41 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int e = tl + G * q;
-                T v = 0;
+                T z = 0;
                 if (rv && e < NN) {
-                    if constexpr (PRO == PRO_PUPDATE) {
-                        const T z = a.u_fft[base + e];
-                        v = first ? z : z + beta * a.pro_p[base + e];
-                        st_nt(a.pro_p + base + e, v);
-                    } else if constexpr (PRO == PRO_SCALE) {
-                        v = scale * a.u_fft[base + e];
-                        st_nt(a.pro_p + base + e, v);
-                    } else {
-                        v = a.u_fft[base + e];
-                    }
+                    z = a.u_fft[base + e];
+                    if constexpr (PRO == PRO_PUPDATE) pv[p][h][q] = first ? T(0) : a.pro_p[base + e];
+                } else if constexpr (PRO == PRO_PUPDATE) {
+                    pv[p][h][q] = T(0);
                 }
-                if (h == 0) xr[p][q] = v; else xi[p][q] = v;
+                if (h == 0) xr[p][q] = z; else xi[p][q] = z;
             }
         }
 #pragma unroll
         for (int q = 4; q < 8; ++q) { xr[p][q] = T(0); xi[p][q] = T(0); }
+    }
+    if constexpr (PRO != PRO_NONE) {
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+            const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = 2 * line + h;
+                const bool rv = row < nrows;
+                const long base = (long)row * P1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = tl + G * q;
+                    T& v = h == 0 ? xr[p][q] : xi[p][q];
+                    if constexpr (PRO == PRO_PUPDATE) {
+                        if (!first) v += beta * pv[p][h][q];
+                    } else {
+                        v *= scale;
+                    }
+                    if (rv && e < NN) st_nt(a.pro_p + base + e, v);
+                }
+            }
+        }
     }
     if (a.o2) {
         // A_n u along x from natural-order copies of the lines (points 0..n)
@@ -802,6 +826,9 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
     __shared__ T s_P[TX], s_Q[TX];
+    // SCALE: the last axis's factors a_k and lc_k (k = 1..n) in LDS
+    constexpr int NH = SCALE ? L / 2 : 1, NL = (NH + NT - 1) / NT;
+    __shared__ T s_al[NH], s_lc[NH];
     __shared__ double s_red[NT / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -813,25 +840,53 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
     const int x0 = xt * TX;
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
-    if (SCALE && tid < TX) {
+    // The factor loads are issued before the tile's row loads and stored to
+    // LDS after them, so that the workgroup waits for memory once.
+    T fa1 = 0, fl1 = 0, fa2 = 0, fl2 = 0;
+    T al[NL], lc[NL];
+    if constexpr (SCALE) {
         const int x = x0 + tid;
-        T P = 0, Q = 0;
-        if (x < a.g.nx) {
-            const T a1 = a.a1[x], l1 = a.lc1[x];
-            if (a.dim == 2) {
-                P = a1 + l1;
-                Q = a1;
-            } else {
-                const T a2 = a.a2[o], l2 = a.lc2[o];
-                P = a2 * (a1 + l1) + l2 * a1;
-                Q = a2 * a1;
+        if (tid < TX && x < a.g.nx) {
+            fa1 = a.a1[x];
+            fl1 = a.lc1[x];
+            if (a.dim == 3) {
+                fa2 = a.a2[o];
+                fl2 = a.lc2[o];
             }
         }
-        s_P[tid] = P;
-        s_Q[tid] = Q;
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = tid + k * NT;
+            al[k] = e < n ? a.a_last[e] : T(0);
+            lc[k] = e < n ? a.lc_last[e] : T(0);
+        }
     }
     T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     dst_load_strided_w<T, L, GRP>(a.u, rline, base, es, ig);
+    if constexpr (SCALE) {
+        if (tid < TX) {
+            T P = 0, Q = 0;
+            if (x0 + tid < a.g.nx) {
+                if (a.dim == 2) {
+                    P = fa1 + fl1;
+                    Q = fa1;
+                } else {
+                    P = fa2 * (fa1 + fl1) + fl2 * fa1;
+                    Q = fa2 * fa1;
+                }
+            }
+            s_P[tid] = P;
+            s_Q[tid] = Q;
+        }
+#pragma unroll
+        for (int k = 0; k < NL; ++k) {
+            const int e = tid + k * NT;
+            if (e < NH) {
+                s_al[e] = al[k];
+                s_lc[e] = lc[k];
+            }
+        }
+    }
     __syncthreads();
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
@@ -880,7 +935,7 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
                 const int k = f <= n ? f : L - f;
                 T wr = 0, wi = 0;
                 if (k >= 1 && k <= n) {
-                    const T ak = a.a_last[k - 1], lk = a.lc_last[k - 1];
+                    const T ak = s_al[k - 1], lk = s_lc[k - 1];
                     const T inv0 = P0 != T(0) ? lam_inv(ak * P0 + lk * Q0, a.half) : T(0);
                     const T inv1 = P1v != T(0) ? lam_inv(ak * P1v + lk * Q1v, a.half) : T(0);
                     const T s1 = -xi[q] * a.c;

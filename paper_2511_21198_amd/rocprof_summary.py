@@ -71,7 +71,7 @@ _KINDS = [
     (re.compile(r"k2?_toep_s\b"), "toep_s"),
     (re.compile(r"k2?_dst_x\b"), "dst_x"),
     (re.compile(r"k_dsts_s\b"), "dsts"),
-    (re.compile(r"k2_dst_s\b.*(true|, ?1)\s*>"), "dsts"),
+    (re.compile(r"k2_dst_s\s*<\s*\w+\s*,\s*\d+\s*,\s*(true|1)\b"), "dsts"),
     (re.compile(r"k2?_dst_s\b"), "dst_y"),
     (re.compile(r"k_mdot\b"), "gm_mdot"),
     (re.compile(r"k_maxpy\b"), "gm_maxpy"),
@@ -217,6 +217,7 @@ SQ_COUNTERS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_ACTIVE_INST_VALU
                "GRBM_GUI_ACTIVE")
 SIMDS = 1024   # 256 compute units x 4 SIMDs
 CUS = 256
+XCDS = 8       # GRBM_GUI_ACTIVE is summed over the accelerator dies
 
 
 def sq_summary(sq_dir, dim=3):
@@ -225,13 +226,14 @@ def sq_summary(sq_dir, dim=3):
     stopped return at once: below a quarter of the kind's largest VALU
     instruction count), and the fractions derived from them:
 
-      valu_busy  = 4 SQ_ACTIVE_INST_VALU / (SIMDS GRBM_GUI_ACTIVE)
-      lds_busy   = 4 SQ_ACTIVE_INST_LDS  / (SIMDS GRBM_GUI_ACTIVE)
-      bank_conflict = SQ_LDS_BANK_CONFLICT / (CUS GRBM_GUI_ACTIVE)
+      valu_busy  = 4 SQ_ACTIVE_INST_VALU / (SIMDS C)
+      lds_busy   = 4 SQ_ACTIVE_INST_LDS  / (SIMDS C)
+      bank_conflict = SQ_LDS_BANK_CONFLICT / (CUS C)
 
-    (the ACTIVE_INST counters count quad-cycles per SIMD; GRBM_GUI_ACTIVE
-    is the dispatch's GPU-busy cycles), and VALU / LDS instructions per
-    wavefront."""
+    with C = GRBM_GUI_ACTIVE / XCDS the dispatch's busy cycles (the GRBM
+    counter is summed over the 8 dies: it reads about 8 x clock x duration)
+    and the ACTIVE_INST counters in quad-cycles summed over all SIMDs; and
+    VALU / LDS instructions per wavefront."""
     rows = _read(sq_dir, "*counter_collection.csv")
     key = "Dispatch_Id" if "Dispatch_Id" in rows[0] else "Correlation_Id"
     by_id = collections.OrderedDict()
@@ -252,7 +254,7 @@ def sq_summary(sq_dir, dim=3):
             continue
         e = {c: sum(d.get(c, 0.0) for d in ds) / len(ds) for c in SQ_COUNTERS}
         e["dispatches"] = len(ds)
-        g = e["GRBM_GUI_ACTIVE"]
+        g = e["GRBM_GUI_ACTIVE"] / XCDS
         w = e["SQ_WAVES"]
         if g > 0:
             e["valu_busy"] = 4.0 * e["SQ_ACTIVE_INST_VALU"] / (SIMDS * g)
@@ -350,9 +352,9 @@ def main(argv=None):
                          f"{e.get('bf16_tflops', 0):.1f} |")
     if sq:
         lines += ["", "Shader counters (per dispatch, averaged over the dispatches that did their "
-                  "work): VALU busy = 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x GRBM_GUI_ACTIVE), LDS "
-                  "busy likewise from SQ_ACTIVE_INST_LDS, bank conflict = SQ_LDS_BANK_CONFLICT / "
-                  "(256 CUs x GRBM_GUI_ACTIVE):", "",
+                  "work): VALU busy = 4 SQ_ACTIVE_INST_VALU / (1024 SIMDs x C), LDS busy likewise "
+                  "from SQ_ACTIVE_INST_LDS, bank conflict = SQ_LDS_BANK_CONFLICT / (256 CUs x C), "
+                  "with C = GRBM_GUI_ACTIVE / 8 (the GRBM counter sums the 8 dies):", "",
                   "| kind | waves | VALU instr/wave | LDS instr/wave | VALU busy | LDS busy | bank conflict | GRBM active |",
                   "|---|---:|---:|---:|---:|---:|---:|---:|"]
         order = sorted(sq, key=lambda k: -res.get(k, {}).get("total_ms", 0.0))

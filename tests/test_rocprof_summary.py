@@ -24,6 +24,8 @@ def test_classify_matvec_and_preconditioner_passes():
         "void fsd::(anonymous namespace)::k_col_dsth<false>(fsd::DstArgs<float>)",
         "void fsd::k2_dst_s<double, 512, true>(fsd::DstArgs<double>)",
         "void fsd::k2_dst_s<double, 512, false>(fsd::DstArgs<double>)",
+        "void fsd::k2_dst_s<float, 256, true, 1>(fsd::DstArgs<float>)",
+        "void fsd::k2_dst_s<float, 256, false, 1>(fsd::DstArgs<float>)",
         "void fsd::k_dst_s<float, 512, 1>(fsd::DstArgs<float>)",
         "void fsd::k_dsts_s<float, 512, 1>(fsd::DstArgs<float>)",
         "void fsd::k_mdot<float, 4>(fsd::MdotArgs)",
@@ -31,7 +33,8 @@ def test_classify_matvec_and_preconditioner_passes():
     ]
     assert rs.classify(_rows(names)) == [
         "toep_x_f32", "toep_y_f32", "toep_z_f32", "dst_x_f32", "dst_y_f32", "dsts_z_f32",
-        "dst_y_f32", "dsts_z_f64", "dst_y_f64", "dst_y_f32", "dsts_z_f32", "gm_mdot_f32", None]
+        "dst_y_f32", "dsts_z_f64", "dst_y_f64", "dsts_z_f32", "dst_y_f32", "dst_y_f32",
+        "dsts_z_f32", "gm_mdot_f32", None]
 
 
 def test_sq_summary_fractions(tmp_path):
@@ -53,7 +56,8 @@ def test_sq_summary_fractions(tmp_path):
     out = rs.sq_summary(str(tmp_path / "sq"))
     e = out["dst_x_f32"]
     assert e["dispatches"] == 1
-    assert e["valu_busy"] == pytest.approx(4 * 256000 / (1024 * 1000))
-    assert e["lds_busy"] == pytest.approx(4 * 128000 / (1024 * 1000))
-    assert e["bank_conflict"] == pytest.approx(25600 / (256 * 1000))
+    c = 1000 / 8      # busy cycles: the GRBM counter sums the 8 dies
+    assert e["valu_busy"] == pytest.approx(4 * 256000 / (1024 * c))
+    assert e["lds_busy"] == pytest.approx(4 * 128000 / (1024 * c))
+    assert e["bank_conflict"] == pytest.approx(25600 / (256 * c))
     assert e["valu_per_wave"] == pytest.approx(500.0)
