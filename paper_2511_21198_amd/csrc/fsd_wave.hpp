@@ -637,6 +637,43 @@ __device__ inline void line_regs_odd(T (&xr)[8], T (&xi)[8], int tl, const T* re
     }
 }
 
+// Double strided passes of length >= 256 keep the twiddle table (L complex
+// values) in LDS when it fits beside the tile within half the LDS of a CU
+// (two workgroups per CU): the stages then read their twiddles there
+// instead of waiting on the cache.  The table is loaded with the tile's
+// rows (one wait).
+template <typename T, int L>
+struct TwLds {
+    template <int BASE_BYTES>
+    static constexpr bool on() {
+        return sizeof(T) == 8 && L >= 256 && BASE_BYTES + 2 * L * (int)sizeof(T) <= 80 * 1024;
+    }
+};
+
+template <typename T, int L, int NT, bool ON>
+struct TwStager {
+    static constexpr int N = ON ? 2 * L : 1, NI = ON ? (2 * L + NT - 1) / NT : 1;
+    T v[NI];
+    __device__ inline void load(const T* __restrict__ tw, int tid) {
+        if constexpr (ON) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int e = tid + k * NT;
+                v[k] = e < 2 * L ? tw[e] : T(0);
+            }
+        }
+    }
+    __device__ inline void store(T* s_tw, int tid) const {
+        if constexpr (ON) {
+#pragma unroll
+            for (int k = 0; k < NI; ++k) {
+                const int e = tid + k * NT;
+                if (e < 2 * L) s_tw[e] = v[k];
+            }
+        }
+    }
+};
+
 // ------------------------------------------------------ strided y/z passes
 // Tile: NCL = 8 (double) or 16 (float) complex lines = 2 NCL consecutive x
 // positions (a 128-byte row segment) at one outer index.  Three workgroup
@@ -664,8 +701,10 @@ __global__ __launch_bounds__((WS<T, L, LPLV>::NT)) void k2_toep_s(ToepArgs<T> a)
     constexpr int G = W::G, LW = W::LW, LPL = LPLV, LP = W::LP;
     constexpr int NCL = S::NCL, TX = S::TX, NT = S::NT, GRP = S::GRP;
     if (a.ctrl && a.ctrl->done) return;
+    constexpr bool TWL = TwLds<T, L>::template on<2 * NCL * LP * (int)sizeof(T) + NT / 8>();
     __shared__ T s_re[NCL * LP];
     __shared__ T s_im[NCL * LP];
+    __shared__ T s_tw[TwStager<T, L, NT, TWL>::N];
     __shared__ double s_red[NT / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -679,6 +718,8 @@ __global__ __launch_bounds__((WS<T, L, LPLV>::NT)) void k2_toep_s(ToepArgs<T> a)
     const int xl = tid % TX, ig = tid / TX;
     const long base = (long)o * a.g.ostride + x0 + xl;
     T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    TwStager<T, L, NT, TWL> tws;
+    tws.load(a.tw, tid);
     // n = L/2 - 1 (L = 2(n + 1)): constant trip counts, loads issued first
     constexpr int NN = L / 2 - 1, NIT = (NN + GRP - 1) / GRP, NZ = (L - NN + GRP - 1) / GRP;
     {
@@ -699,6 +740,7 @@ __global__ __launch_bounds__((WS<T, L, LPLV>::NT)) void k2_toep_s(ToepArgs<T> a)
             if (i < L) rline[W::idx(i)] = T(0);
         }
     }
+    tws.store(s_tw, tid);
     __syncthreads();
     const bool pad_line = x0 + xl >= a.g.nx;
     if (a.o2) {
@@ -727,7 +769,7 @@ __global__ __launch_bounds__((WS<T, L, LPLV>::NT)) void k2_toep_s(ToepArgs<T> a)
     }
     __syncthreads();
     Twiddles<T, L> tw;
-    tw.load(tl, a.tw);
+    tw.load(tl, TWL ? s_tw : a.tw);
     {
         T* re[LPL];
         T* im[LPL];
@@ -829,6 +871,9 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
     // SCALE: the last axis's factors a_k and lc_k (k = 1..n) in LDS
     constexpr int NH = SCALE ? L / 2 : 1, NL = (NH + NT - 1) / NT;
     __shared__ T s_al[NH], s_lc[NH];
+    constexpr bool TWL = TwLds<T, L>::template on<(2 * NCL * LP + 2 * TX + 2 * NH) * (int)sizeof(T) +
+                                                  NT / 8>();
+    __shared__ T s_tw[TwStager<T, L, NT, TWL>::N];
     __shared__ double s_red[NT / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, wave = tid >> 6;
@@ -861,8 +906,11 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
             lc[k] = e < n ? a.lc_last[e] : T(0);
         }
     }
+    TwStager<T, L, NT, TWL> tws;
+    tws.load(a.tw, tid);
     T* rline = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
     dst_load_strided_w<T, L, GRP>(a.u, rline, base, es, ig);
+    tws.store(s_tw, tid);
     if constexpr (SCALE) {
         if (tid < TX) {
             T P = 0, Q = 0;
@@ -889,7 +937,7 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
     }
     __syncthreads();
     Twiddles<T, L> tw;
-    tw.load(tl, a.tw);
+    tw.load(tl, TWL ? s_tw : a.tw);
     double acc = 0.0;
     if constexpr (!SCALE) {
         // plain DST: the LPL lines of a lane group in lock-step
