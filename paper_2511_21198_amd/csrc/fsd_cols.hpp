@@ -512,9 +512,24 @@ void k_col_dsth(DstArgs<float> a) {
     // HN), staged in LDS between the transforms (in s_tot, free there: 40 KB
     // of LDS keeps four workgroups on a CU)
     float2 lam_k = make_float2(0.f, 0.f);
+    // the line factors (P, Q below) are loaded here too, with the tile
+    float fa1[2] = {0.f, 0.f}, fl1[2] = {0.f, 0.f}, fa2 = 0.f, fl2 = 0.f;
+    const int o = blockIdx.x / (a.g.P1 / TX);
     if constexpr (SCALE) {
         const int k = threadIdx.x;
         if (k >= 1) lam_k = make_float2(a.a_last[k - 1], a.lc_last[k - 1]);
+#pragma unroll
+        for (int cc = 0; cc < 2; ++cc) {
+            const int x = (int)(t.base - (long)o * a.g.ostride) + cc;
+            if (x < a.g.nx) {
+                fa1[cc] = a.a1[x];
+                fl1[cc] = a.lc1[x];
+            }
+        }
+        if (a.dim == 3) {
+            fa2 = a.a2[o];
+            fl2 = a.lc2[o];
+        }
     }
     {
         // x_j = u[j - 1] for j = r + 16 m (x_0 = 0) to LDS in natural order
@@ -533,21 +548,19 @@ void k_col_dsth(DstArgs<float> a) {
     dst256_from_lds(S, s_tot, t, sr, si);
     if constexpr (SCALE) {
         float P[2], Q[2];
-        const int o = blockIdx.x / (a.g.P1 / TX);
 #pragma unroll
         for (int cc = 0; cc < 2; ++cc) {
             const int x = (int)(t.base - (long)o * a.g.ostride) + cc;
             P[cc] = 0.f;
             Q[cc] = 0.f;
             if (x < a.g.nx) {
-                const float a1 = a.a1[x], l1 = a.lc1[x];
+                const float a1 = fa1[cc], l1 = fl1[cc];
                 if (a.dim == 2) {
                     P[cc] = a1 + l1;
                     Q[cc] = a1;
                 } else {
-                    const float a2 = a.a2[o], l2 = a.lc2[o];
-                    P[cc] = a2 * (a1 + l1) + l2 * a1;
-                    Q[cc] = a2 * a1;
+                    P[cc] = fa2 * (a1 + l1) + fl2 * a1;
+                    Q[cc] = fa2 * a1;
                 }
             }
         }
@@ -699,6 +712,20 @@ void k_col_toep(ToepArgs<T> a) {
     float yr2[2][16], yi2[2][16];
     transpose_fwd_half(S, t, 0, xr, xi, yr2[0], yi2[0]);
     transpose_fwd_half(S, t, 1, xr, xi, yr2[1], yi2[1]);
+    // the stencil operand's rows are loaded here, in flight during the
+    // spectral products and the inverse transposes (the offset is made
+    // opaque so that the loads are not hoisted to the top of the kernel,
+    // where their registers would stay live through both transforms)
+    float2 vs[16];
+    if (a.u_sten) {
+        long off = t.base;
+        asm volatile("" : "+v"(off));
+#pragma unroll
+        for (int m = 0; m < 16; ++m) {
+            const int j = t.r + 16 * m;
+            vs[m] = j < NN ? *row2(a.u_sten, off + (long)j * es) : make_float2(0.f, 0.f);
+        }
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int k1 = t.r + 16 * h;
@@ -721,18 +748,7 @@ void k_col_toep(ToepArgs<T> a) {
     // rows j = r + 16 j2 < n: out = conj(Y) [+ A_n u_sten] and the epilogue
     float2 sten[16];
     if (a.u_sten) {
-        // the offset is made opaque here so that these loads are issued after
-        // the transforms instead of being hoisted to the top of the kernel,
-        // where their registers would stay live through both transforms
-        long off = t.base;
-        asm volatile("" : "+v"(off));
-        float2 v[16];
-#pragma unroll
-        for (int m = 0; m < 16; ++m) {
-            const int j = t.r + 16 * m;
-            v[m] = j < NN ? *row2(a.u_sten, off + (long)j * es) : make_float2(0.f, 0.f);
-        }
-        line_stencil(S, t, v, sten);
+        line_stencil(S, t, vs, sten);
     } else {
 #pragma unroll
         for (int m = 0; m < 16; ++m) sten[m] = make_float2(0.f, 0.f);

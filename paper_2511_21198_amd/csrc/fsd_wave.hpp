@@ -348,6 +348,17 @@ __device__ inline void wspec(T (&xr)[8], T (&xi)[8], int tl, const T* __restrict
     }
 }
 
+// The same product with the spectrum values already in registers.
+template <typename T>
+__device__ inline void wspec_regs(T (&xr)[8], T (&xi)[8], const T (&cr)[8], const T (&ci)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const T zr = xr[q], zi = xi[q];
+        xr[q] = cr[q] * zr - ci[q] * zi;
+        xi[q] = -(cr[q] * zi + ci[q] * zr);
+    }
+}
+
 template <int L>
 constexpr bool wave_engine_length() {
     return L == 64 || L == 128 || L == 256 || L == 512;
@@ -480,9 +491,24 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
     }
     Twiddles<T, L> tw;
     tw.load(tl, a.tw);
+    // float: the spectrum at this lane's frequencies is loaded before the
+    // forward transform (the register budget allows it at this occupancy),
+    // so its latency overlaps the transform
+    T cr[8], ci[8];
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const int f = tl + G * q;
+            cr[q] = a.spec[2 * f];
+            ci[q] = a.spec[2 * f + 1];
+        }
+    }
     wfft_n<T, L, true, false, LPL>(xr, xi, tl, tw, re, im);
 #pragma unroll
-    for (int p = 0; p < LPL; ++p) wspec<T, L>(xr[p], xi[p], tl, a.spec);
+    for (int p = 0; p < LPL; ++p) {
+        if constexpr (sizeof(T) == 4) wspec_regs<T>(xr[p], xi[p], cr, ci);
+        else wspec<T, L>(xr[p], xi[p], tl, a.spec);
+    }
     wfft_n<T, L, false, true, LPL>(xr, xi, tl, tw, re, im);
 #pragma unroll
     for (int p = 0; p < LPL; ++p) {
