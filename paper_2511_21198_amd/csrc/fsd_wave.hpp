@@ -542,6 +542,11 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
     __shared__ T s_im[WX<T, L, LPLV>::LINES * LP];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int g = lane / G, tl = lane % G;
+    // the twiddles (float: registers, loaded from global memory) are
+    // requested before the line loads, so both arrive in one wait (measured
+    // faster for this pass only: 35.8 -> 34.4 us at 255^3)
+    Twiddles<T, L> tw;
+    tw.load(tl, a.tw);
     const int P1 = a.g.P1, nrows = a.g.nrows;
     T xr[LPL][8], xi[LPL][8];
 #pragma unroll
@@ -588,8 +593,6 @@ __global__ __launch_bounds__(256) void k2_dst_x(DstArgs<T> a) {
         }
     }
     wave_sync();
-    Twiddles<T, L> tw;
-    tw.load(tl, a.tw);
     {
         T* re[LPL];
         T* im[LPL];

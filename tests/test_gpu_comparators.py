@@ -19,6 +19,12 @@ a step ends within rounding of tol the count moves by one; the paper notes
 the slow convergence of PCG(T) and PCG(S) for small and anisotropic orders.
 Measured: 168 of the 188 entries exact, the largest difference -3.2%
 (PCG(S), (0.1, 0.2), 511^2).
+
+Against the oracle itself at the sizes its own tests do not reach (the
+symmetric circulant rows, 128^2 to 511^2 and 32^3, 64^3; the oracle's
+counts are within 0.74% of the printed ones there): 25 of 40 rows equal in
+every step, all 3D rows among them; every step within 4 iterations and
+every total within 2.5% (measured: 2.4%, (0.1, 0.2) PCG(S) at 511^2).
 """
 import json
 import os
@@ -176,18 +182,29 @@ def _example(tab, dim, orders, M, n1):
     return _SOURCE[key]
 
 
-def _gpu_total(fsd, row):
-    if row not in _TOTALS:
-        tab, dim, orders, M, n1, kind, it = row
+_STEPS = {}   # (table, dim, orders, M, n + 1, kind) -> iterations of each CN step
+
+
+def _run_steps(fsd, key):
+    if key not in _STEPS:
+        tab, dim, orders, M, n1, kind = key
         kp, km, u0, Fs = _example(tab, dim, orders, M, n1)
         prob = fsd(dim, [n1 - 1] * dim, list(orders), kp, km, M=M, T=1.0, tol=1e-9, x0="zero",
                    restart=20, maxit=(n1 - 1) ** 3, precond=kind)
         u = dev(u0)
-        total = 0
+        its = []
         for m in range(M):
             u, st = prob.cn_step(u, dev(Fs[m]))
             assert st["converged"] == 1
-            total += st["iters"]
+            its.append(int(st["iters"]))
+        _STEPS[key] = its
+    return _STEPS[key]
+
+
+def _gpu_total(fsd, row):
+    if row not in _TOTALS:
+        tab, dim, orders, M, n1, kind, it = row
+        total = sum(_run_steps(fsd, (tab, dim, orders, M, n1, kind)))
         _TOTALS[row] = (total, int(round(it * M)))
     return _TOTALS[row]
 
@@ -205,6 +222,43 @@ def test_paper_comparator_counts_gpu(fsd, row):
     excepted) up to the largest grids, 511^2 and 63^3."""
     total, printed = _gpu_total(fsd, row)
     assert abs(total - printed) <= _tolerance(row, printed), (row, total, printed)
+
+
+def _oracle_rows():
+    path = os.path.join(GOLDEN, "oracle_comparator_counts.json")
+    return sorted(json.load(open(path))["rows"].items())
+
+
+def _gpu_steps(fsd, v):
+    return _run_steps(fsd, (v["table"], v["dim"], tuple(v["orders"]), v["M"], v["n_plus_1"],
+                            v["kind"]))
+
+
+@pytest.mark.parametrize("name,v", _oracle_rows(), ids=[k for k, _ in _oracle_rows()])
+def test_comparator_steps_vs_oracle(fsd, name, v):
+    """The circulant-preconditioned CG comparators of the symmetric tables
+    at the sizes the oracle's own tests do not reach (128^2 to 511^2, 32^3
+    and 64^3), step by step against the oracle's counts
+    (golden/oracle_comparator_counts.json, written by the oracle).  Both
+    are float64 CG with the same preconditioner (its application agrees to
+    1e-12 above); where the preconditioned system is ill-conditioned the
+    step at which the residual crosses tol moves with the rounding order:
+    every step within 4 iterations, the total within 2.5%."""
+    its = _gpu_steps(fsd, v)
+    ref = v["iters"]
+    assert len(its) == len(ref)
+    worst = max(abs(a - b) for a, b in zip(its, ref))
+    assert worst <= 4, (name, worst)
+    assert abs(sum(its) - sum(ref)) <= max(2, 0.025 * sum(ref)), (name, sum(its), sum(ref))
+
+
+def test_comparator_steps_vs_oracle_mostly_exact(fsd):
+    """Most of those rows agree with the oracle in every step (every 3D
+    row does)."""
+    rows = _oracle_rows()
+    exact = [k for k, v in rows if _gpu_steps(fsd, v) == v["iters"]]
+    assert len(exact) >= int(0.6 * len(rows)), (len(exact), len(rows))
+    assert all(k in exact for k, v in rows if v["dim"] == 3)
 
 
 def test_paper_comparator_counts_gpu_mostly_exact(fsd):

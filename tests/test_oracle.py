@@ -554,6 +554,27 @@ def test_paper_comparator_counts_mostly_exact():
     assert exact >= int(0.85 * len(rows)), (exact, len(rows))
 
 
+def test_oracle_comparator_golden_matches_paper():
+    """The oracle's stored comparator counts at the larger grids
+    (golden/oracle_comparator_counts.json, written by
+    make_oracle_comparator_counts.py from oracle/ alone) reproduce the
+    printed averages of Tables 1 and 3 to 1% of the total (measured: 0.74%
+    at most, PCG(S) with orders (0.1, 0.2) at 511^2), and every stored row
+    has one count per time step."""
+    rows = json.load(open(os.path.join(GOLDEN, "oracle_comparator_counts.json")))["rows"]
+    printed = {}
+    for tab, dim, orders, M, n1, none, tchan, strang in json.load(
+            open(os.path.join(GOLDEN, "paper_comparator_iterations.json")))["rows"]:
+        printed[(tab, tuple(orders), n1, "tchan")] = (M, tchan)
+        printed[(tab, tuple(orders), n1, "strang")] = (M, strang)
+    assert len(rows) == 40
+    for name, v in rows.items():
+        M, avg = printed[(v["table"], tuple(v["orders"]), v["n_plus_1"], v["kind"])]
+        assert v["M"] == M and len(v["iters"]) == M, name
+        total = sum(v["iters"])
+        assert abs(total - avg * M) <= max(2, 0.01 * avg * M), (name, total, avg * M)
+
+
 def test_example_sources_separate_in_time():
     """Example 4.1's source is e^t f(x, y, 0); Example 4.2's is
     cos(t+1) P - sin(t+1) D with (P, D) from ex42_source_parts, at random
