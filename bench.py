@@ -564,6 +564,10 @@ def main(argv=None):
     ap.add_argument("--dst-mfma", action="store_true",
                     help="mixed solver: float32 DST-I as bf16 matrix-core products (the "
                          "measured alternative to the FFT passes)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in line-pass engines (no fsd_autotune at setup), e.g. "
+                         "for a profiled run whose per-kernel figures should not include the "
+                         "autotuner's timing launches")
     ap.add_argument("--no-warm", action="store_true",
                     help="skip the mixed solver run from the extrapolated warm start")
     ap.add_argument("--no-ref", action="store_true",
@@ -628,7 +632,8 @@ def main(argv=None):
         if x0:
             c["x0"] = x0
         p = Problem(**c, tol=t, **kw)
-        engines = p.autotune()   # tile shapes per pass, chosen at setup (untimed)
+        # tile shapes per pass, chosen at setup (untimed)
+        engines = p.engines() if a.no_autotune else p.autotune()
         r = repeat_timing(p, u0, F, w.M, a.steps, a.warmup, repeats or a.repeats, profile)
         r["engines"] = engines
         r["u_final"] = final_state(p, u0, F, w.M) if not a.no_ref else None

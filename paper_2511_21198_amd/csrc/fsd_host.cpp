@@ -1091,6 +1091,8 @@ fsd_status time_pass(fsd_problem P, int kind, int eng, double* ms) {
     return FSD_OK;
 }
 
+constexpr double kAutotuneMargin = 0.05;
+
 template <typename T>
 fsd_status autotune_prec(fsd_problem P) {
     const int fp = is_f32<T>() ? 1 : 0;
@@ -1101,13 +1103,18 @@ fsd_status autotune_prec(fsd_problem P) {
         kind_pass(kind, axis, op);
         int cand[ENG_COUNT];
         const int nc = pass_engines(op, P->ax[axis].L, is_f32<T>(), cand);
+        // the default (cand[0]) is kept unless another engine is faster by
+        // more than kAutotuneMargin: engines within timing noise of each other
+        // would otherwise flip from run to run
         int best = ENG_AUTO;
-        double best_ms = 1e300;
+        double best_ms = 1e300, auto_ms = 1e300;
         for (int c = 0; c < nc; ++c) {
             double ms = 0.0;
             FSD_TRY(time_pass<T>(P, kind, cand[c], &ms));
+            if (cand[c] == ENG_AUTO) auto_ms = ms;
             if (ms < best_ms) { best_ms = ms; best = cand[c]; }
         }
+        if (best != ENG_AUTO && best_ms > (1.0 - kAutotuneMargin) * auto_ms) best = ENG_AUTO;
         P->eng[fp][kind] = best;
     }
     return FSD_OK;

@@ -163,7 +163,8 @@ class Problem:
               "fsd_set_engine")
 
     def autotune(self) -> str:
-        """Time every engine of every pass and keep the fastest
+        """Time every engine of every pass and keep the fastest (the
+        built-in one unless another is more than 5% faster)
         (fsd_autotune); returns the chosen engines."""
         check(lib.fsd_autotune(self._h), "fsd_autotune")
         return self.engines()
