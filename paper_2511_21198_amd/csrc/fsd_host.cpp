@@ -897,7 +897,8 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         // (P^{-1/2} for the two-sided system), both preconditioned norms
         // with the float64 preconditioner.  The float64 P^{-1} r is also the
         // first Arnoldi vector of the next inner solve (rounded to float32),
-        // so the inner GMRES does not apply its own preconditioner to r.
+        // so the inner GMRES does not apply its own preconditioner to r
+        // (except on outer steps whose test cannot pass, below).
         // The inner solve also stops once the outer test is met (absolute
         // floor abs_tol), so the last correction is no more accurate than
         // needed.
@@ -912,24 +913,38 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
         int outer = 0;
         int status = FSD_ENOTCONV;
         double relres = 0.0, prec_rel = 0.0;
+        // Left GMRES: after an inner solve that reduced its preconditioned
+        // residual by o.relres, the outer one is about prec_rel * o.relres
+        // (no better than float32 allows).  While that prediction is above
+        // kSkipTest * tol the float64 test cannot pass, so the next outer
+        // step computes only r and lets the inner GMRES apply its own float32
+        // preconditioner to it instead of taking the float64 P^{-1} r; the
+        // test itself, when evaluated, is always the float64 one.
+        constexpr double kSkipTest = 100.0, kInnerFloor = 1e-5;
+        double pred = 0.0;
         OuterNorms nrm;
         for (bool start = true;; start = false) {
-            FSD_TRY(outer_norms(P, x, b, r, pz, start, split, nrm));
+            // (never on the last allowed outer step: the reported residual is
+            // then always a measured one)
+            const bool skip = left && !start && pred > kSkipTest * tol &&
+                              outer < P->p.max_outer && iters < maxit;
+            FSD_TRY(outer_norms(P, x, b, r, skip ? nullptr : pz, start, split, nrm));
             relres = nrm.b > 0.0 ? nrm.r / nrm.b : nrm.r;
-            prec_rel = left ? (nrm.pb > 0.0 ? nrm.pr / nrm.pb : nrm.pr) : relres;
+            prec_rel = !left ? relres : skip ? pred : (nrm.pb > 0.0 ? nrm.pr / nrm.pb : nrm.pr);
             if (!std::isfinite(relres) || !std::isfinite(prec_rel)) { status = FSD_ENONFINITE; break; }
-            if (nrm.r == 0.0 || prec_rel <= tol) { status = FSD_OK; break; }
+            if (nrm.r == 0.0 || (!skip && prec_rel <= tol)) { status = FSD_OK; break; }
             if (outer >= P->p.max_outer || iters >= maxit) break;
             const double rnorm = nrm.r;
             HIP_TRY((vec_cast<double, float>(r, f.b, P->Np, 1.0 / rnorm, P->stream)));
-            if (left) HIP_TRY((vec_cast<double, float>(pz, f.w, P->Np, 1.0 / rnorm, P->stream)));
+            if (left && !skip) HIP_TRY((vec_cast<double, float>(pz, f.w, P->Np, 1.0 / rnorm, P->stream)));
             const double ref = left ? nrm.pb : nrm.b;
             SolveOut o;
             const int saved = P->last_iters;
             const int slot = std::min(outer, 3);
             P->last_iters = P->last_inner_iters[slot];
             FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o,
-                                  tol * ref / rnorm, left));
+                                  tol * ref / rnorm, left && !skip));
+            pred = prec_rel * std::max(o.relres, kInnerFloor);
             P->last_inner_iters[slot] = P->last_iters;
             P->last_iters = saved;
             iters += o.iters;
