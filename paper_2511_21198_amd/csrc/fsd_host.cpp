@@ -697,11 +697,13 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     long total_enq = 0;
     for (int cycle = 0; !converged; ++cycle) {
         // r0 = P^{-1}(b - A x)
-        if (!(x0_zero && cycle == 0)) {   // with x = 0, w still holds P^{-1} b
+        // with x = 0, w still holds P^{-1} b and the partials of its norm
+        // are still in place from above
+        if (!(x0_zero && cycle == 0)) {
             FSD_TRY(first_residual<T>(P, x, b, v.r, P->ctrl, &np));
             FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr, split));
+            HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         }
-        HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
         int chunk = std::max(2, P->last_iters - 1);
         int j = 0;
