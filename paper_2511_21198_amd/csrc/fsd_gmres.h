@@ -18,6 +18,8 @@ enum GmOp : int {
                    // added to H[0..j, j] and kept in h2
     GM_STEP = 4,   // H[j+1, j] = ||w||, Givens rotations, residual test
     GM_SOLVE = 5,  // y = R^{-1} g for the k columns of the cycle
+    GM_H2S = 6,    // GM_H2 then GM_STEP in one launch, for a zero reorthogonalisation
+                   // threshold (no second pass between them)
 };
 
 // Offsets inside Ctrl::gm for restart m.

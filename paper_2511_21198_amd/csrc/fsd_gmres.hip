@@ -295,9 +295,11 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
     }
     if (c->done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    // GM_H1 / GM_H2 carry one more row: ||w||^2 / ||w'||^2.  GM_STEP reads
+    // GM_H1 / GM_H2 / GM_H2S carry one more row: ||w||^2 / ||w'||^2.  GM_STEP reads
     // a norm from the partials only after a second Gram-Schmidt pass.
-    const int rows = (op == GM_H1 || op == GM_H2) ? nv + 1 : (op == GM_STEP && !c->gm_reorth) ? 0 : nv;
+    const int rows = (op == GM_H1 || op == GM_H2 || op == GM_H2S) ? nv + 1
+                     : (op == GM_STEP && !c->gm_reorth)          ? 0
+                                                                 : nv;
     for (int i = wv; i < rows; i += ST / 64) {
         double acc = 0.0;
         for (int t = lane; t < nparts; t += 64) acc += partials[(long)i * nparts + t];
@@ -314,7 +316,7 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
             gm[oH + i + (m + 1) * j] = sums[i] + (i == j ? 1.0 : 0.0);
         }
         c->gm_w2 = sums[nv];
-    } else if (op == GM_H2) {
+    } else if (op == GM_H2 || op == GM_H2S) {
         // Daniel-Gragg-Kaufman-Stewart test: keep w' when the first pass
         // removed less than a fraction 1 - gm_eta2 of ||w||^2 (gm_eta2 = 0.5:
         // half); otherwise take the second pass (its coefficients h2 are
@@ -330,6 +332,9 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
             gm[oT + i] = re ? sums[i] : 0.0;
             if (re) gm[oH + i + (m + 1) * j] += sums[i];
         }
+        // the combined op is only issued with a zero threshold (re = 0):
+        // ||w'||^2 is the norm of the next basis vector
+        if (op == GM_H2S) gm[oT] = wp2;
     } else if (op == GM_STEP) {
         gm[oT] = c->gm_reorth ? sums[0] : c->gm_wp2;
     } else {
@@ -354,7 +359,7 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
         gm[oG] = beta;
         c->gm_k = 0;
         c->gm_j = 0;
-    } else if (op == GM_STEP) {
+    } else if (op == GM_STEP || op == GM_H2S) {
         const double S = gm[oT];
         if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
         const double hnext = sqrt(S);

@@ -745,15 +745,20 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
                         HIP_TRY(gm_maxpy<T>(v.V, Np, jj + 1, v.w, vn, Np, P->ctrl, h2off, MX_DOTS,
                                             P->partials, &np, s));
                     }
-                    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_H2, s));
-                    // second pass, in place, only when the test asks for it (never
-                    // with a zero threshold: no launch)
+                    // second pass, in place, only when the test asks for it; with
+                    // a zero threshold there is none, and the test and the
+                    // Givens step share one launch
                     if (eta2 > 0.0) {
-                        ProfScope ps(P, K_GM_REORTH, is_f32<T>(), vb * (jj + 3));
-                        HIP_TRY(gm_maxpy<T>(v.V, Np, jj + 1, vn, vn, Np, P->ctrl, h2off, MX_REORTH,
-                                            P->partials, &np, s));
+                        HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_H2, s));
+                        {
+                            ProfScope ps(P, K_GM_REORTH, is_f32<T>(), vb * (jj + 3));
+                            HIP_TRY(gm_maxpy<T>(v.V, Np, jj + 1, vn, vn, Np, P->ctrl, h2off,
+                                                MX_REORTH, P->partials, &np, s));
+                        }
+                        HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, jj, GM_STEP, s));
+                    } else {
+                        HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_H2S, s));
                     }
-                    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, jj, GM_STEP, s));
                 }
                 return FSD_OK;
             };
