@@ -20,6 +20,13 @@ enum GmOp : int {
     GM_SOLVE = 5,  // y = R^{-1} g for the k columns of the cycle
     GM_H2S = 6,    // GM_H2 then GM_STEP in one launch, for a zero reorthogonalisation
                    // threshold (no second pass between them)
+    // Unnormalised basis (one Gram-Schmidt pass, the update of v_{j+1} fused
+    // into the next matvec's x pass): V_i holds v_i / s_i, s_i = 1/||V_i||
+    // kept in ctrl->gm (s_0 = 1).
+    GM_COEF = 7,   // H[0..j, j] and the coefficients c_i = s_i^2 V_i^T (w - V_j) from
+                   // the multi-dot partials
+    GM_NEXT = 8,   // ||V_j||^2 from the partials (row nv): s_j, H[j, j-1], Givens
+                   // rotations and residual test of column j - 1
 };
 
 // Offsets inside Ctrl::gm for restart m.

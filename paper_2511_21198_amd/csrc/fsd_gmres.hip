@@ -9,6 +9,16 @@
 //   k_maxpy     reads V[0..j], w, writes w       -> w -= V h1, partials of V^T w
 //   k_maxpy     reads V[0..j], w, writes v_{j+1} -> w -= V h2, partial ||w||^2
 // Each kernel loads the nv basis values of an element once into registers.
+//
+// With one Gram-Schmidt pass (zero reorthogonalisation threshold) and the
+// wave engine's x pass, the update of v_{j+1} moves into the prologue of the
+// next matvec (PRO_ARNOLDI): that x pass reads w and V[0..j], writes the new
+// basis vector and the partials of its norm, and transforms it, which saves
+// the k_maxpy launch and two vector passes per step.  The basis is then kept
+// unnormalised (V_i = v_i / s_i, the scales in ctrl->gm): GM_COEF turns the
+// multi-dot into the Hessenberg column and the prologue's coefficients,
+// GM_NEXT the norm into H[j+1, j] and the Givens step, and GM_SOLVE folds the
+// scales into y.
 #include "fsd_gmres.h"
 
 namespace fsd {
@@ -275,14 +285,50 @@ __device__ inline bool gm_isfinite(double v) { return __builtin_isfinite(v); }
 // The nv sums of the partials are spread over the wavefronts (one value per
 // wavefront at a time, a fixed summation order per value).
 constexpr int ST = 1024;
+// Column j of the Hessenberg matrix is complete up to H[j+1, j] = hnext:
+// apply the earlier rotations, form the new one, update g and test.
+__device__ inline void gm_givens(Ctrl* c, double* gm, int m, int j, double hnext) {
+    const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m;
+    double* H = gm + oH + (m + 1) * j;   // column j
+    H[j + 1] = hnext;
+    for (int i = 0; i < j; ++i) {
+        const double cs = gm[oCS + i], sn = gm[oSN + i];
+        const double t = cs * H[i] + sn * H[i + 1];
+        H[i + 1] = -sn * H[i] + cs * H[i + 1];
+        H[i] = t;
+    }
+    const double den = hypot(H[j], H[j + 1]);
+    double cs = 1.0, sn = 0.0;
+    if (den > 0.0) { cs = H[j] / den; sn = H[j + 1] / den; }
+    gm[oCS + j] = cs;
+    gm[oSN + j] = sn;
+    H[j] = den;
+    H[j + 1] = 0.0;
+    gm[oG + j + 1] = -sn * gm[oG + j];
+    gm[oG + j] = cs * gm[oG + j];
+    c->iters += 1;
+    c->gm_k = j + 1;
+    c->gm_j = j + 1;
+    const double res = gm[oG + j + 1];
+    c->rr = res * res;
+    c->gm_hnext = hnext;
+    c->gm_scale = hnext > 0.0 ? 1.0 / hnext : 0.0;
+    if (!gm_isfinite(res)) { c->status = 4; c->done = 1; }
+    else if (res * res <= c->thresh || hnext == 0.0) c->done = 1;
+    else if (c->iters >= c->maxit) { c->status = 2; c->done = 1; }
+    else if (j + 1 >= m) c->done = 2;   // cycle full: restart
+}
+
 __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
                                                   int nparts, int nv, int j, int op) {
     __shared__ double sums[kMaxRestart + 2];
     const int m = c->gm_m;
     const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m, oY = oG + m + 1, oT = oY + m;
+    const int oS = oT + m + 1;   // basis scales s_0 .. s_m
     double* gm = c->gm;
     if (op == GM_SOLVE) {
-        // back substitution R y = g on the rotated Hessenberg matrix
+        // back substitution R y = g on the rotated Hessenberg matrix; the
+        // update takes the stored basis vectors, so y_i carries s_i
         if (threadIdx.x == 0) {
             const int k = c->gm_k;
             for (int i = k - 1; i >= 0; --i) {
@@ -290,24 +336,49 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
                 for (int l = i + 1; l < k; ++l) s -= gm[oH + i + (m + 1) * l] * gm[oY + l];
                 gm[oY + i] = s / gm[oH + i + (m + 1) * i];
             }
+            for (int i = 0; i < k; ++i) gm[oY + i] *= gm[oS + i];
         }
         return;
     }
     if (c->done) return;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     // GM_H1 / GM_H2 / GM_H2S carry one more row: ||w||^2 / ||w'||^2.  GM_STEP reads
-    // a norm from the partials only after a second Gram-Schmidt pass.
+    // a norm from the partials only after a second Gram-Schmidt pass.  GM_NEXT
+    // reads the single row nv.
     const int rows = (op == GM_H1 || op == GM_H2 || op == GM_H2S) ? nv + 1
                      : (op == GM_STEP && !c->gm_reorth)          ? 0
+                     : op == GM_NEXT                             ? 1
                                                                  : nv;
+    const double* src = op == GM_NEXT ? partials + (long)nv * nparts : partials;
     for (int i = wv; i < rows; i += ST / 64) {
         double acc = 0.0;
-        for (int t = lane; t < nparts; t += 64) acc += partials[(long)i * nparts + t];
+        for (int t = lane; t < nparts; t += 64) acc += src[(long)i * nparts + t];
         acc = wave_sum(acc);
         if (lane == 0) sums[i] = acc;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    if (op == GM_COEF) {
+        // w' = (w - V_j) - sum_i c_i V_i in the stored vectors is s_j^{-1} times
+        // the normalised Gram-Schmidt vector: H[i, j] = s_i s_j V_i^T (w - V_j)
+        // (+1 on the diagonal), c_i = s_i^2 V_i^T (w - V_j)
+        const double sj = gm[oS + j];
+        for (int i = 0; i < nv; ++i) {
+            const double si = gm[oS + i];
+            gm[oT + i] = si * si * sums[i];
+            gm[oH + i + (m + 1) * j] = si * sj * sums[i] + (i == j ? 1.0 : 0.0);
+        }
+        return;
+    }
+    if (op == GM_NEXT) {
+        // V_j = w' of column j - 1: H[j, j-1] = s_{j-1} ||V_j||, s_j = 1 / ||V_j||
+        const double S = sums[0];
+        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
+        const double nrm = sqrt(S);
+        gm[oS + j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        gm_givens(c, gm, m, j - 1, gm[oS + j - 1] * nrm);
+        return;
+    }
     if (op == GM_H1) {
         // coefficients of the shifted pass (kept for it in the h2 slot) and
         // the Hessenberg column of P^{-1} A = (P^{-1} A - I) + I
@@ -357,40 +428,13 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
         c->gm_scale = 1.0 / beta;
         for (int i = 0; i <= m; ++i) gm[oG + i] = 0.0;
         gm[oG] = beta;
+        for (int i = 0; i <= m; ++i) gm[oS + i] = 1.0;   // v_0 = w / beta is stored normalised
         c->gm_k = 0;
         c->gm_j = 0;
     } else if (op == GM_STEP || op == GM_H2S) {
         const double S = gm[oT];
         if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
-        const double hnext = sqrt(S);
-        double* H = gm + oH + (m + 1) * j;   // column j
-        H[j + 1] = hnext;
-        for (int i = 0; i < j; ++i) {
-            const double cs = gm[oCS + i], sn = gm[oSN + i];
-            const double t = cs * H[i] + sn * H[i + 1];
-            H[i + 1] = -sn * H[i] + cs * H[i + 1];
-            H[i] = t;
-        }
-        const double den = hypot(H[j], H[j + 1]);
-        double cs = 1.0, sn = 0.0;
-        if (den > 0.0) { cs = H[j] / den; sn = H[j + 1] / den; }
-        gm[oCS + j] = cs;
-        gm[oSN + j] = sn;
-        H[j] = den;
-        H[j + 1] = 0.0;
-        gm[oG + j + 1] = -sn * gm[oG + j];
-        gm[oG + j] = cs * gm[oG + j];
-        c->iters += 1;
-        c->gm_k = j + 1;
-        c->gm_j = j + 1;
-        const double res = gm[oG + j + 1];
-        c->rr = res * res;
-        c->gm_hnext = hnext;
-        c->gm_scale = hnext > 0.0 ? 1.0 / hnext : 0.0;
-        if (!gm_isfinite(res)) { c->status = 4; c->done = 1; }
-        else if (res * res <= c->thresh || hnext == 0.0) c->done = 1;
-        else if (c->iters >= c->maxit) { c->status = 2; c->done = 1; }
-        else if (j + 1 >= m) c->done = 2;   // cycle full: restart
+        gm_givens(c, gm, m, j, sqrt(S));
     }
 }
 

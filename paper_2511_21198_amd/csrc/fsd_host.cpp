@@ -226,6 +226,13 @@ struct MatvecOpts {
     int epi = EPI_NONE;
     const double* F = nullptr;
     int pro = PRO_NONE;
+    // PRO_ARNOLDI: basis V_0 .. V_{gs_nv-1} (gs_ld apart), coefficients at
+    // ctrl->gm + gs_hoff; the x pass is followed by the GM_NEXT step of
+    // column gs_nv - 1
+    const void* gs_V = nullptr;
+    long gs_ld = 0;
+    int gs_nv = 0;
+    int gs_hoff = 0;
 };
 
 // tmp: the four pass intermediates (default: the workspace's).
@@ -252,9 +259,24 @@ fsd_status op_matvec(fsd_problem P, const T* in, T* out, const MatvecOpts& o, co
     auto runs = [&](int kind) { return P->tune_kind < 0 || P->tune_kind == kind; };
     auto eng = [&](int kind) { return P->tune_kind == kind ? P->tune_eng : P->eng[fp][kind]; };
     if (runs(K_TOEP_X)) {
-        const int extra = o.pro == PRO_PUPDATE ? 2 : (o.pro == PRO_SCALE ? 1 : 0);
-        ProfScope ps(P, K_TOEP_X, is_f32<T>(), nb * (3 + extra));
-        HIP_TRY(launch_toep_x<T>(P->ax[0].L, A, nullptr, P->stream, eng(K_TOEP_X)));
+        const int extra = o.pro == PRO_PUPDATE ? 2
+                        : o.pro == PRO_SCALE   ? 1
+                        : o.pro == PRO_ARNOLDI ? o.gs_nv + 1
+                                               : 0;
+        int npx = 0;
+        if (o.pro == PRO_ARNOLDI) {
+            A.gs_V = static_cast<const T*>(o.gs_V);
+            A.gs_ld = o.gs_ld;
+            A.gs_nv = o.gs_nv;
+            A.gs_hoff = o.gs_hoff;
+            A.partials = P->partials;
+        }
+        {
+            ProfScope ps(P, K_TOEP_X, is_f32<T>(), nb * (3 + extra));
+            HIP_TRY(launch_toep_x<T>(P->ax[0].L, A, &npx, P->stream, eng(K_TOEP_X)));
+        }
+        if (o.pro == PRO_ARNOLDI)
+            HIP_TRY(gm_scalar(P->ctrl, P->partials, npx, 0, o.gs_nv, GM_NEXT, P->stream));
     }
     const double epi_bytes = o.epi == EPI_ADD_F ? (double)P->N * 8.0
                            : (o.epi == EPI_DOT_P || o.epi == EPI_RESID) ? nb : 0.0;
@@ -665,6 +687,14 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
 }
 
 // ------------------------------------------------------------ GMRES
+
+// The Gram-Schmidt prologue (PRO_ARNOLDI) exists on the wave engine's x pass.
+template <typename T>
+bool fused_arnoldi_ok(fsd_problem P) {
+    const int L = P->ax[0].L;
+    const int e = P->eng[is_f32<T>() ? 1 : 0][K_TOEP_X];
+    return (L == 64 || L == 128 || L == 256 || L == 512) && e != ENG_STAGE && e != ENG_STAGE_HALF;
+}
 // Left-preconditioned restarted GMRES (Section 3.2, ``one_side_system``):
 // stop when ||P^{-1}(b - A x_k)||_2 <= tol ||P^{-1} b||_2.
 // w_given (with x0_zero): v.w already holds P^{-1} b (P^{-1/2} b), applied
@@ -687,6 +717,9 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     // two-sided system: the basis lives in the P^{1/2} coordinates, every
     // preconditioner application is P^{-1/2}
     const bool split = P->solver == FSD_SOLVER_PGMRES2;
+    // one Gram-Schmidt pass on the wave engine's x pass: the update of
+    // v_{j+1} runs in the prologue of the next matvec (unnormalised basis)
+    const bool fused = !split && eta2 == 0.0 && fused_arnoldi_ok<T>(P);
     // ||P^{-1} b|| (||P^{-1/2} b||)
     if (!(w_given && x0_zero)) FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
     HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
@@ -705,7 +738,8 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         }
         HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
-        int chunk = std::max(2, P->last_iters - 1);
+        // the fused path learns of convergence one x pass later
+        int chunk = std::max(2, P->last_iters - (fused ? 0 : 1));
         int j = 0;
         const size_t rec0 = P->prof.size();
         for (;;) {
@@ -715,7 +749,18 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
                 for (int jj = j0; jj < j0 + cnt; ++jj) {
                     P->prof_tag = jj;
                     T* vj = v.V + (long)jj * Np;
-                    if (!split) {
+                    if (fused && jj > 0) {
+                        // V[j] = (w - V[j-1]) - sum_i c_i V_i and q = A V[j]; then the
+                        // Givens step of column j - 1
+                        MatvecOpts o;
+                        o.pro = PRO_ARNOLDI;
+                        o.gs_V = v.V;
+                        o.gs_ld = Np;
+                        o.gs_nv = jj;
+                        o.gs_hoff = h2off;
+                        FSD_TRY(op_matvec<T>(P, v.w, v.q, o, nullptr, nullptr, vj, P->ctrl, &np));
+                        FSD_TRY(op_precond<T>(P, v.q, v.w, P->ctrl, nullptr, nullptr));
+                    } else if (!split) {
                         // q = A v_j, with v_j = scale * (w or V[j]) written back into V[j]
                         MatvecOpts o;
                         o.pro = PRO_SCALE;
@@ -734,6 +779,11 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
                     {
                         ProfScope ps(P, K_GM_MDOT, is_f32<T>(), vb * (jj + 2));
                         HIP_TRY(gm_mdot<T>(v.V, Np, jj + 1, v.w, Np, P->partials, P->ctrl, &np, s));
+                    }
+                    if (fused) {
+                        // column j and the coefficients of the next prologue
+                        HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_COEF, s));
+                        continue;
                     }
                     HIP_TRY(gm_scalar(P->ctrl, P->partials, np, jj + 1, jj, GM_H1, s));
                     // first Gram-Schmidt pass on the shifted vector:
@@ -765,17 +815,35 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             // the first chunk of a cycle starts at column 0: a fixed launch
             // sequence (the others depend on where they start)
             if (j0 == 0 && cnt > 0)
-                FSD_TRY(run_chunk(P, chunk_key(is_f32<T>(), split ? 3 : 1, eta2 > 0.0, cnt), body));
+                FSD_TRY(run_chunk(P, chunk_key(is_f32<T>(), split ? 3 : fused ? 2 : 1, eta2 > 0.0,
+                                               cnt),
+                                  body));
             else
                 FSD_TRY(body());
             j += cnt;
             total_enq += cnt;
+            if (fused && j >= m) {
+                // the cycle is full: column m - 1 still needs ||V[m]||
+                P->prof_tag = -1;
+                {
+                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), (double)P->N * sizeof(T) * (m + 3));
+                    HIP_TRY(gm_maxpy<T>(v.V, Np, m, v.w, v.V + (long)m * Np, Np, P->ctrl, h2off,
+                                        MX_DOTS, P->partials, &np, s));
+                }
+                HIP_TRY(gm_scalar(P->ctrl, P->partials, np, m, m, GM_NEXT, s));
+            }
             FSD_TRY(read_ctrl(P));
             if (P->h_ctrl->done || j >= m) break;
             chunk = 2;
         }
         const Ctrl& c = *P->h_ctrl;
         prof_drop_skipped(P, rec0, c.gm_k);
+        if (fused && c.gm_k > 0) {
+            // the x pass of column gm_k ran: its prologue completed column gm_k - 1
+            for (size_t r = rec0; r < P->prof.size(); ++r)
+                if (P->prof[r].tag == c.gm_k && P->prof[r].kind / 2 == K_TOEP_X)
+                    P->prof[r].skip = false;
+        }
         for (size_t r = rec0; r < P->prof.size(); ++r) {   // second passes not taken
             ProfRec& pr = P->prof[r];
             if (pr.kind / 2 == K_GM_REORTH && pr.tag >= 0 && pr.tag < c.gm_k && !c.gm_rflag[pr.tag])
@@ -1297,6 +1365,9 @@ fsd_status fsd_init_problem(const fsd_params* p, fsd_problem* out) {
     P->N = (long)p->n[0] * P->rows;
     // partial-sum slots: the largest workgroup count of any reducing kernel
     int mp = std::max(kVecGrid, kGmGrid);
+    // the wave engine's x pass with the Gram-Schmidt prologue: at least 8 rows
+    // per workgroup (4 wavefronts of one line of two rows)
+    mp = std::max<long>(mp, (P->rows + 7) / 8);
     for (int i = 1; i < P->dim; ++i) {
         const int L = P->ax[i].L;
         const long outer = (i == 1) ? (P->dim == 3 ? p->n[2] : 1) : p->n[1];

@@ -77,6 +77,9 @@ enum Pro : int {
     PRO_NONE = 0,
     PRO_PUPDATE = 1,  // u = z + beta p (p = z when ctrl->first); p <- u
     PRO_SCALE = 2,    // u = scale * u_in, scale = ctrl->gm_scale (GMRES v_{j+1} = w / h)
+    PRO_ARNOLDI = 3,  // u = (u_in - V_{nv-1}) - sum_{i<nv} c_i V_i, c_i = ctrl->gm[hoff + i]
+                      // (GMRES Gram-Schmidt update, unnormalised); u -> pro_p and
+                      // the block partial of ||u||^2 -> partials[blockIdx.x]
 };
 
 // Geometry of one pass over the padded internal layout.
@@ -112,7 +115,11 @@ struct ToepArgs {
     const T* b;           // EPI_RESID
     double* partials;     // one double per workgroup
     int pro;
-    T* pro_p;             // PRO_PUPDATE: p (read and written)
+    T* pro_p;             // PRO_PUPDATE: p (read and written); PRO_SCALE / PRO_ARNOLDI: output
+    const T* gs_V;        // PRO_ARNOLDI: basis vectors V_0 .. V_{nv-1}, gs_ld apart
+    long gs_ld;
+    int gs_nv;
+    int gs_hoff;          // PRO_ARNOLDI: offset of the coefficients in ctrl->gm
     const Ctrl* ctrl;     // may be null (no early exit, no beta)
 };
 

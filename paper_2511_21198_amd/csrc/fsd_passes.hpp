@@ -84,6 +84,10 @@ hipError_t wave_toep_x(const ToepArgs<T>& a, int* nb, hipStream_t s) {
         case PRO_SCALE:
             hipLaunchKernelGGL((k2_toep_x<T, L, PRO_SCALE, LPLV>), dim3(g), dim3(NT), 0, s, a);
             break;
+        case PRO_ARNOLDI:
+            if (!a.ctrl || !a.gs_V || !a.partials || a.gs_nv < 1) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k2_toep_x<T, L, PRO_ARNOLDI, LPLV>), dim3(g), dim3(NT), 0, s, a);
+            break;
         default:
             hipLaunchKernelGGL((k2_toep_x<T, L, PRO_NONE, LPLV>), dim3(g), dim3(NT), 0, s, a);
     }
@@ -127,6 +131,7 @@ hipError_t toep_x_one(const ToepArgs<T>& a, int* nb, hipStream_t s, int eng) {
             return wave_toep_x<T, L, wave_lpl_default<T, L>()>(a, nb, s);
         }
     }
+    if (a.pro == PRO_ARNOLDI) return hipErrorInvalidValue;   // wave engine only
     return stage_x_launch<T, L, KToepX>(a, nb, s, eng);
 }
 

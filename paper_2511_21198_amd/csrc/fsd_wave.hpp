@@ -431,7 +431,81 @@ __global__ __launch_bounds__(256) void k2_toep_x(ToepArgs<T> a) {
 #pragma unroll
         for (int q = 4; q < 8; ++q) { xr[p][q] = T(0); xi[p][q] = T(0); }
     }
-    if constexpr (PRO != PRO_NONE) {
+    if constexpr (PRO == PRO_ARNOLDI) {
+        // Gram-Schmidt update of the GMRES basis in the prologue: first
+        // u_in - V_{nv-1} (exact where the two agree to a factor of 2: the
+        // preconditioned operator is close to the identity), then the
+        // projections c_i V_i, the loads of two basis vectors in flight at a time
+        const int nv = a.gs_nv;
+        const T* __restrict__ V = a.gs_V;
+        const long ld = a.gs_ld;
+        const double* cg = a.ctrl->gm + a.gs_hoff;
+        auto load_rows = [&](const T* __restrict__ src, T (&t)[LPL][2][4]) {
+#pragma unroll
+            for (int p = 0; p < LPL; ++p) {
+                const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int row = 2 * line + h;
+                    const bool rv = row < nrows;
+                    const long base = (long)row * P1;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const int e = tl + G * q;
+                        t[p][h][q] = (rv && e < NN) ? src[base + e] : T(0);
+                    }
+                }
+            }
+        };
+        auto sub = [&](const T (&t)[LPL][2][4], T c) {
+#pragma unroll
+            for (int p = 0; p < LPL; ++p) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    xr[p][q] -= c * t[p][0][q];
+                    xi[p][q] -= c * t[p][1][q];
+                }
+            }
+        };
+        T t0[LPL][2][4], t1[LPL][2][4];
+        load_rows(V + (long)(nv - 1) * ld, t0);
+        sub(t0, T(1));
+        int i = 0;
+        for (; i + 2 <= nv; i += 2) {
+            load_rows(V + (long)i * ld, t0);
+            load_rows(V + (long)(i + 1) * ld, t1);
+            sub(t0, (T)cg[i]);
+            sub(t1, (T)cg[i + 1]);
+        }
+        if (i < nv) {
+            load_rows(V + (long)i * ld, t0);
+            sub(t0, (T)cg[i]);
+        }
+        double nacc = 0.0;
+#pragma unroll
+        for (int p = 0; p < LPL; ++p) {
+            const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int row = 2 * line + h;
+                const bool rv = row < nrows;
+                const long base = (long)row * P1;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int e = tl + G * q;
+                    const T v = h == 0 ? xr[p][q] : xi[p][q];
+                    if (rv && e < NN) {
+                        st_nt(a.pro_p + base + e, v);
+                        nacc += (double)v * (double)v;
+                    }
+                }
+            }
+        }
+        __shared__ double s_nrm[WX<T, L, LPLV>::NW];
+        const double bs = block_sum<WX<T, L, LPLV>::NT>(nacc, s_nrm);
+        if (threadIdx.x == 0) a.partials[blockIdx.x] = bs;
+    }
+    if constexpr (PRO == PRO_PUPDATE || PRO == PRO_SCALE) {
 #pragma unroll
         for (int p = 0; p < LPL; ++p) {
             const int line = blockIdx.x * WX<T, L, LPLV>::LINES + wave * LW * LPL + g + LW * p;

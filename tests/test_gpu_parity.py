@@ -341,6 +341,42 @@ def test_gmres_reorth_threshold(fsd, precision, eta2):
     close(u_gpu, u_ref, 1e-10 if precision == "fp64" else 1e-8)
 
 
+@pytest.mark.parametrize("precision,restart", [("fp64", 20), ("fp64", 3), ("mixed", 20),
+                                               ("mixed", 4)])
+@pytest.mark.parametrize("case", [
+    (3, [31, 15, 23], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
+    (2, [127, 95], [0.45, 0.65], [1.5, 0.5], [0.5, 1.5]),
+    (3, [255, 7, 5], [0.7, 0.5, 0.3], [0.9, 1.1, 1.0], [1.2, 0.7, 0.8]),
+], ids=lambda c: f"{c[0]}d-" + "x".join(map(str, c[1])))
+def test_gmres_fused_gram_schmidt(fsd, case, precision, restart):
+    """One Gram-Schmidt pass with the update of v_{j+1} computed in the
+    prologue of the next matvec's x pass (unnormalised basis; x lengths of the
+    wave engine, L = 64 .. 512): the float64 solver with a zero
+    reorthogonalisation threshold and the float32 inner solves of mixed
+    precision take it.  CN steps against the oracle, with restarts (restart 3
+    and 4 close full cycles); float64 iteration counts within one of the
+    two-pass (DGKS) solver's, which keeps the unfused kernels."""
+    dim, n, d, kp, km = case
+    M = 4
+    tol = 1e-13 if precision == "fp64" else 1e-12
+    kw = dict(M=M, T=1.0, tol=tol, solver="gmres", precision=precision, inner_tol=1e-5,
+              restart=restart)
+    prob = fsd(dim, n, d, kp, km, reorth_eta2=0.0 if precision == "fp64" else None, **kw)
+    orc = op.Problem(dim, n, d, kp, km, T=1.0, M=M)
+    rng = np.random.default_rng(41)
+    u0 = rng.standard_normal(orc.shape)
+    F = workloads.random_grid(orc.shape, 43)
+    u_gpu, its = _run_gpu(prob, u0, lambda m: F, M)
+    u_ref, _ = cn.run(orc, u0, lambda m: F, tol=1e-13, x0_mode="prev", solver="gmres",
+                      restart=restart)
+    close(u_gpu, u_ref, 1e-10 if precision == "fp64" else 1e-8)
+    if precision == "fp64":
+        del prob
+        two = fsd(dim, n, d, kp, km, reorth_eta2=0.5, **kw)
+        _, its2 = _run_gpu(two, u0, lambda m: F, M)
+        assert all(abs(a - b) <= 1 for a, b in zip(its, its2)), (its, its2)
+
+
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 @pytest.mark.parametrize("case", [
     (3, [15, 31, 7], [0.4, 0.6, 0.8], [1.0, 0.8, 1.2], [0.5, 1.0, 0.3]),
