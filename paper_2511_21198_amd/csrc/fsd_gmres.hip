@@ -279,37 +279,53 @@ __global__ __launch_bounds__(GT) void k_scale(const T* in, T* out, long N, const
 // FP contraction (the subtraction can fuse with the multiply producing v).
 __device__ inline bool gm_isfinite(double v) { return __builtin_isfinite(v); }
 
-// Scalar GMRES steps (one workgroup; thread 0 updates the state).
+// Scalar GMRES steps (one workgroup).
 // Layout of ctrl->gm for restart m: H (m+1) x m column-major at 0,
-// cs at GM_CS, sn at GM_SN, g at GM_G (m+1), y at GM_Y (m), h2 at GM_T (m+1).
-// The nv sums of the partials are spread over the wavefronts (one value per
-// wavefront at a time, a fixed summation order per value).
+// cs at GM_CS, sn at GM_SN, g at GM_G (m+1), y at GM_Y (m), h2 at GM_T (m+1),
+// basis scales s at GM_T + m + 1 (m + 1).
+// The partial sums of each value are added by one or more wavefronts in a
+// fixed order (a row of many partials is split over several wavefronts).
+// Per-row work runs one thread per row; the serial recurrences (Givens
+// rotations, back substitution) run on thread 0 over copies staged in LDS,
+// since thread 0 reading device memory it has just written would wait for
+// each store.
 constexpr int ST = 1024;
+constexpr int SNW = ST / 64;
+
 // Column j of the Hessenberg matrix is complete up to H[j+1, j] = hnext:
-// apply the earlier rotations, form the new one, update g and test.
-__device__ inline void gm_givens(Ctrl* c, double* gm, int m, int j, double hnext) {
-    const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m;
-    double* H = gm + oH + (m + 1) * j;   // column j
-    H[j + 1] = hnext;
+// apply the earlier rotations, form the new one, update g and test.  Called
+// by every thread of the workgroup.
+__device__ inline void gm_givens(Ctrl* c, double* gm, int m, int j, double hnext, double* sH,
+                                 double* sCS, double* sSN) {
+    const int oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m;
+    const int tid = threadIdx.x;
+    double* H = gm + (m + 1) * j;   // column j
+    if (tid <= j) sH[tid] = H[tid];
+    if (tid < j) { sCS[tid] = gm[oCS + tid]; sSN[tid] = gm[oSN + tid]; }
+    __syncthreads();
+    if (tid != 0) return;
+    const double gj = gm[oG + j];
+    sH[j + 1] = hnext;
     for (int i = 0; i < j; ++i) {
-        const double cs = gm[oCS + i], sn = gm[oSN + i];
-        const double t = cs * H[i] + sn * H[i + 1];
-        H[i + 1] = -sn * H[i] + cs * H[i + 1];
-        H[i] = t;
+        const double cs = sCS[i], sn = sSN[i];
+        const double t = cs * sH[i] + sn * sH[i + 1];
+        sH[i + 1] = -sn * sH[i] + cs * sH[i + 1];
+        sH[i] = t;
     }
-    const double den = hypot(H[j], H[j + 1]);
+    const double den = hypot(sH[j], sH[j + 1]);
     double cs = 1.0, sn = 0.0;
-    if (den > 0.0) { cs = H[j] / den; sn = H[j + 1] / den; }
+    if (den > 0.0) { cs = sH[j] / den; sn = sH[j + 1] / den; }
+    sH[j] = den;
+    sH[j + 1] = 0.0;
+    for (int i = 0; i <= j + 1; ++i) H[i] = sH[i];
     gm[oCS + j] = cs;
     gm[oSN + j] = sn;
-    H[j] = den;
-    H[j + 1] = 0.0;
-    gm[oG + j + 1] = -sn * gm[oG + j];
-    gm[oG + j] = cs * gm[oG + j];
+    const double res = -sn * gj;
+    gm[oG + j + 1] = res;
+    gm[oG + j] = cs * gj;
     c->iters += 1;
     c->gm_k = j + 1;
     c->gm_j = j + 1;
-    const double res = gm[oG + j + 1];
     c->rr = res * res;
     c->gm_hnext = hnext;
     c->gm_scale = hnext > 0.0 ? 1.0 / hnext : 0.0;
@@ -322,26 +338,38 @@ __device__ inline void gm_givens(Ctrl* c, double* gm, int m, int j, double hnext
 __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
                                                   int nparts, int nv, int j, int op) {
     __shared__ double sums[kMaxRestart + 2];
+    __shared__ double red[SNW];
+    __shared__ double sH[kMaxRestart + 1], sCS[kMaxRestart], sSN[kMaxRestart];
+    __shared__ double sR[kMaxRestart * kMaxRestart];
     const int m = c->gm_m;
     const int oH = 0, oCS = (m + 1) * m, oSN = oCS + m, oG = oSN + m, oY = oG + m + 1, oT = oY + m;
-    const int oS = oT + m + 1;   // basis scales s_0 .. s_m
+    const int oS = oT + m + 1;
+    (void)oCS;
     double* gm = c->gm;
+    const int tid = threadIdx.x;
     if (op == GM_SOLVE) {
         // back substitution R y = g on the rotated Hessenberg matrix; the
         // update takes the stored basis vectors, so y_i carries s_i
-        if (threadIdx.x == 0) {
-            const int k = c->gm_k;
-            for (int i = k - 1; i >= 0; --i) {
-                double s = gm[oG + i];
-                for (int l = i + 1; l < k; ++l) s -= gm[oH + i + (m + 1) * l] * gm[oY + l];
-                gm[oY + i] = s / gm[oH + i + (m + 1) * i];
-            }
-            for (int i = 0; i < k; ++i) gm[oY + i] *= gm[oS + i];
+        const int k = c->gm_k;
+        for (int e = tid; e < k * k; e += ST) {
+            const int i = e % k, l = e / k;
+            if (i <= l) sR[i + kMaxRestart * l] = gm[oH + i + (m + 1) * l];
         }
+        for (int i = tid; i < k; i += ST) { sH[i] = gm[oG + i]; sCS[i] = gm[oS + i]; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = k - 1; i >= 0; --i) {
+                double s = sH[i];
+                for (int l = i + 1; l < k; ++l) s -= sR[i + kMaxRestart * l] * sSN[l];
+                sSN[i] = s / sR[i + kMaxRestart * i];
+            }
+        }
+        __syncthreads();
+        for (int i = tid; i < k; i += ST) gm[oY + i] = sSN[i] * sCS[i];
         return;
     }
     if (c->done) return;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = tid & 63, wv = tid >> 6;
     // GM_H1 / GM_H2 / GM_H2S carry one more row: ||w||^2 / ||w'||^2.  GM_STEP reads
     // a norm from the partials only after a second Gram-Schmidt pass.  GM_NEXT
     // reads the single row nv.
@@ -350,91 +378,137 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
                      : op == GM_NEXT                             ? 1
                                                                  : nv;
     const double* src = op == GM_NEXT ? partials + (long)nv * nparts : partials;
-    for (int i = wv; i < rows; i += ST / 64) {
+    if (rows > 0 && rows <= SNW) {
+        const int wpr = SNW / rows;   // wavefronts per row
+        const int r = wv / wpr, q = wv - r * wpr;
         double acc = 0.0;
-        for (int t = lane; t < nparts; t += 64) acc += src[(long)i * nparts + t];
+        if (r < rows) {
+            const double* p = src + (long)r * nparts;
+#pragma unroll 4
+            for (int t = q * 64 + lane; t < nparts; t += wpr * 64) acc += p[t];
+        }
         acc = wave_sum(acc);
-        if (lane == 0) sums[i] = acc;
+        if (lane == 0) red[wv] = acc;
+        __syncthreads();
+        if (tid < rows) {
+            double s = 0.0;
+            for (int k = 0; k < wpr; ++k) s += red[tid * wpr + k];
+            sums[tid] = s;
+        }
+    } else {
+        for (int i = wv; i < rows; i += SNW) {
+            double acc = 0.0;
+#pragma unroll 4
+            for (int t = lane; t < nparts; t += 64) acc += src[(long)i * nparts + t];
+            acc = wave_sum(acc);
+            if (lane == 0) sums[i] = acc;
+        }
     }
     __syncthreads();
-    if (threadIdx.x != 0) return;
     if (op == GM_COEF) {
         // w' = (w - V_j) - sum_i c_i V_i in the stored vectors is s_j^{-1} times
         // the normalised Gram-Schmidt vector: H[i, j] = s_i s_j V_i^T (w - V_j)
         // (+1 on the diagonal), c_i = s_i^2 V_i^T (w - V_j)
-        const double sj = gm[oS + j];
-        for (int i = 0; i < nv; ++i) {
-            const double si = gm[oS + i];
-            gm[oT + i] = si * si * sums[i];
-            gm[oH + i + (m + 1) * j] = si * sj * sums[i] + (i == j ? 1.0 : 0.0);
+        if (tid < nv) {
+            const double sj = gm[oS + j], si = gm[oS + tid];
+            gm[oT + tid] = si * si * sums[tid];
+            gm[oH + tid + (m + 1) * j] = si * sj * sums[tid] + (tid == j ? 1.0 : 0.0);
         }
         return;
     }
     if (op == GM_NEXT) {
         // V_j = w' of column j - 1: H[j, j-1] = s_{j-1} ||V_j||, s_j = 1 / ||V_j||
         const double S = sums[0];
-        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
+        if (!gm_isfinite(S)) {
+            if (tid == 0) { c->status = 4; c->done = 1; }
+            return;
+        }
         const double nrm = sqrt(S);
-        gm[oS + j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
-        gm_givens(c, gm, m, j - 1, gm[oS + j - 1] * nrm);
+        const double hnext = gm[oS + j - 1] * nrm;
+        if (tid == 0) gm[oS + j] = nrm > 0.0 ? 1.0 / nrm : 0.0;
+        gm_givens(c, gm, m, j - 1, hnext, sH, sCS, sSN);
         return;
     }
     if (op == GM_H1) {
         // coefficients of the shifted pass (kept for it in the h2 slot) and
         // the Hessenberg column of P^{-1} A = (P^{-1} A - I) + I
-        for (int i = 0; i < nv; ++i) {
-            gm[oT + i] = sums[i];
-            gm[oH + i + (m + 1) * j] = sums[i] + (i == j ? 1.0 : 0.0);
+        if (tid < nv) {
+            gm[oT + tid] = sums[tid];
+            gm[oH + tid + (m + 1) * j] = sums[tid] + (tid == j ? 1.0 : 0.0);
         }
-        c->gm_w2 = sums[nv];
-    } else if (op == GM_H2 || op == GM_H2S) {
+        if (tid == 0) c->gm_w2 = sums[nv];
+        return;
+    }
+    if (op == GM_H2 || op == GM_H2S) {
         // Daniel-Gragg-Kaufman-Stewart test: keep w' when the first pass
         // removed less than a fraction 1 - gm_eta2 of ||w||^2 (gm_eta2 = 0.5:
         // half); otherwise take the second pass (its coefficients h2 are
         // added to the Hessenberg column).  gm_eta2 = 0: never (the host
         // then does not launch the second pass).
         const double wp2 = sums[nv];
-        c->gm_wp2 = wp2;
         const int re = c->gm_eta2 > 0.0 && !(wp2 > c->gm_eta2 * c->gm_w2);
-        c->gm_reorth = re;
-        c->gm_rflag[j] = re;
-        c->gm_nreorth += re;
-        for (int i = 0; i < nv; ++i) {
-            gm[oT + i] = re ? sums[i] : 0.0;
-            if (re) gm[oH + i + (m + 1) * j] += sums[i];
+        if (tid < nv) {
+            gm[oT + tid] = re ? sums[tid] : 0.0;
+            if (re) gm[oH + tid + (m + 1) * j] += sums[tid];
         }
+        if (tid == 0) {
+            c->gm_wp2 = wp2;
+            c->gm_reorth = re;
+            c->gm_rflag[j] = re;
+            c->gm_nreorth += re;
+        }
+        if (op == GM_H2) return;
         // the combined op is only issued with a zero threshold (re = 0):
         // ||w'||^2 is the norm of the next basis vector
-        if (op == GM_H2S) gm[oT] = wp2;
-    } else if (op == GM_STEP) {
-        gm[oT] = c->gm_reorth ? sums[0] : c->gm_wp2;
-    } else {
-        for (int i = 0; i < nv; ++i) gm[oT + i] = sums[i];   // GM_PBB, GM_BETA: a single norm
+        if (tid == 0) gm[oT] = wp2;
+        if (!gm_isfinite(wp2)) {
+            if (tid == 0) { c->status = 4; c->done = 1; }
+            return;
+        }
+        __syncthreads();
+        gm_givens(c, gm, m, j, sqrt(wp2), sH, sCS, sSN);
+        return;
     }
-    if (threadIdx.x != 0) return;
+    if (op == GM_STEP) {
+        const double S = c->gm_reorth ? sums[0] : c->gm_wp2;
+        if (tid == 0) gm[oT] = S;
+        if (!gm_isfinite(S)) {
+            if (tid == 0) { c->status = 4; c->done = 1; }
+            return;
+        }
+        gm_givens(c, gm, m, j, sqrt(S), sH, sCS, sSN);
+        return;
+    }
+    // GM_PBB, GM_BETA: a single norm
+    const double S = sums[0];
     if (op == GM_PBB) {
-        const double S = gm[oT];
-        c->bb = S;
-        c->thresh = fmax(c->tol2 * S, c->abs2);
-        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; }
-        else if (S == 0.0) { c->rr = 0.0; c->done = 1; }
+        if (tid == 0) {
+            c->bb = S;
+            c->thresh = fmax(c->tol2 * S, c->abs2);
+            if (!gm_isfinite(S)) { c->status = 4; c->done = 1; }
+            else if (S == 0.0) { c->rr = 0.0; c->done = 1; }
+        }
     } else if (op == GM_BETA) {
-        const double S = gm[oT];
-        c->rr = S;
-        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
-        if (S <= c->thresh) { c->done = 1; c->gm_k = 0; return; }
-        const double beta = sqrt(S);
-        c->gm_beta = beta;
-        c->gm_scale = 1.0 / beta;
-        for (int i = 0; i <= m; ++i) gm[oG + i] = 0.0;
-        gm[oG] = beta;
-        for (int i = 0; i <= m; ++i) gm[oS + i] = 1.0;   // v_0 = w / beta is stored normalised
-        c->gm_k = 0;
-        c->gm_j = 0;
-    } else if (op == GM_STEP || op == GM_H2S) {
-        const double S = gm[oT];
-        if (!gm_isfinite(S)) { c->status = 4; c->done = 1; return; }
-        gm_givens(c, gm, m, j, sqrt(S));
+        const bool go = gm_isfinite(S) && !(S <= c->thresh);
+        if (tid == 0) {
+            c->rr = S;
+            if (!gm_isfinite(S)) { c->status = 4; c->done = 1; }
+            else if (S <= c->thresh) { c->done = 1; c->gm_k = 0; }
+            else {
+                const double beta = sqrt(S);
+                c->gm_beta = beta;
+                c->gm_scale = 1.0 / beta;
+                c->gm_k = 0;
+                c->gm_j = 0;
+            }
+        }
+        if (go) {
+            // g = beta e1; v_0 = w / beta is stored normalised (s = 1)
+            for (int i = tid; i <= m; i += ST) {
+                gm[oG + i] = i == 0 ? sqrt(S) : 0.0;
+                gm[oS + i] = 1.0;
+            }
+        }
     }
 }
 
