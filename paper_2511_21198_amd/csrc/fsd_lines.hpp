@@ -29,6 +29,8 @@
 // a coalesced row read or write.
 #pragma once
 
+#include <type_traits>
+
 #include "fsd_internal.h"
 
 namespace fsd {
@@ -253,6 +255,29 @@ __device__ inline TileTw<T, L> tile_twiddles(const T* __restrict__ tw, T* s_twr,
 template <typename T, int L, int NC>
 __device__ inline void fft_lines(T* re, T* im, const TileTw<T, L>& tw, int tid) {
     FFTRun<T, L, 0, 1, TileTw<T, L>::kLds ? 1 : 2, NC>::run(re, im, tw.r, tw.i, tid);
+}
+
+// Reciprocal for the Lambda^{-1} scale: v_rcp_f32 (1 ulp) for float;
+// v_rcp_f64 refined by two Newton steps (full double accuracy) for double.
+__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double fast_rcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+
+// Reciprocal square root for the Lambda^{-1/2} scale of the two-sided
+// system: v_rsq_f32 for float; v_rsq_f64 refined by two Newton steps
+// y <- y + y (1 - x y^2) / 2 for double.
+__device__ inline float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double fast_rsqrt(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    double e = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+    e = fma(-x * y, y, 1.0);
+    return fma(0.5 * y, e, y);
 }
 
 // ------------------------------------------------------------- reductions
@@ -649,8 +674,12 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
 
     double acc = 0.0;
     // the factors a_k, lc_k of a chunk of four entries are loaded together
-    // before the chunk's arithmetic (one wait for memory per chunk)
+    // before the chunk's arithmetic (one wait for memory per chunk); the
+    // scale (Lambda^{-1}, or Lambda^{-1/2} for the two-sided system) is a
+    // compile-time choice: a runtime select would evaluate both
     constexpr int NE = (NCL * L + NT - 1) / NT, EC = NE < 4 ? NE : 4;
+    auto scale_all = [&](auto half_c) {
+    constexpr bool H = decltype(half_c)::value;
     for (int c = 0; c < NE; c += EC) {
       T akc[EC], lkc[EC];
 #pragma unroll
@@ -676,8 +705,8 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
             const T ak = akc[q], lk = lkc[q];
             const T lam0 = ak * P0 + lk * Q0;
             const T lam1 = ak * P1v + lk * Q1v;
-            const T inv0 = P0 != T(0) ? (a.half ? T(1) / sqrt(lam0) : T(1) / lam0) : T(0);
-            const T inv1 = P1v != T(0) ? (a.half ? T(1) / sqrt(lam1) : T(1) / lam1) : T(0);
+            const T inv0 = P0 != T(0) ? (H ? fast_rsqrt(lam0) : fast_rcp(lam0)) : T(0);
+            const T inv1 = P1v != T(0) ? (H ? fast_rsqrt(lam1) : fast_rcp(lam1)) : T(0);
             const T s1 = -s_im[ad] * a.c;
             const T s2 = s_re[ad] * a.c;
             wr = s1 * inv0;
@@ -688,6 +717,9 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
         s_im[ad] = wi;
       }
     }
+    };
+    if (a.half) scale_all(std::true_type{});
+    else scale_all(std::false_type{});
     __syncthreads();
     fft_lines<T, L, NC>(s_re, s_im, tw, tid);
     const bool odd = xl & 1;

@@ -256,15 +256,24 @@ __global__ void k_ctrl_init(Ctrl* c, double tol2, int maxit, int restart, double
 }
 
 // Single-workgroup scalar step: S = sum of the partials in a fixed order,
-// then the Krylov scalar update selected by op.
-__global__ __launch_bounds__(VT) void k_scalar(Ctrl* c, const double* __restrict__ partials, int nparts,
-                                               int op) {
-    __shared__ double sb[VT / 64];
+// then the Krylov scalar update selected by op.  1024 threads, four loads in
+// flight per thread: the partials of a strided pass number a few thousand.
+constexpr int SVT = 1024;
+__global__ __launch_bounds__(SVT) void k_scalar(Ctrl* c, const double* __restrict__ partials,
+                                                int nparts, int op) {
+    __shared__ double sb[SVT / 64];
     if (c->done) return;
     double acc = 0.0;
-    for (int i = threadIdx.x; i < nparts; i += VT) acc += partials[i];
-    const double S = block_sum_vt(acc, sb);
+#pragma unroll 4
+    for (int i = threadIdx.x; i < nparts; i += SVT) acc += partials[i];
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) sb[w] = acc;
+    __syncthreads();
     if (threadIdx.x != 0) return;
+    double S = 0.0;
+#pragma unroll
+    for (int i = 0; i < SVT / 64; ++i) S += sb[i];
     switch (op) {
         case SC_BB:
             c->bb = S;
@@ -414,7 +423,7 @@ hipError_t ctrl_init(Ctrl* c, double tol2, int maxit, int restart, hipStream_t s
     return hipGetLastError();
 }
 hipError_t scalar_step(Ctrl* c, const double* partials, int nparts, int op, hipStream_t s) {
-    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(VT), 0, s, c, partials, nparts, op);
+    hipLaunchKernelGGL(k_scalar, dim3(1), dim3(SVT), 0, s, c, partials, nparts, op);
     return hipGetLastError();
 }
 

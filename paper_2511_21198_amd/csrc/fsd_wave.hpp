@@ -30,29 +30,6 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Reciprocal for the Lambda^{-1} scale: v_rcp_f32 (1 ulp) for float;
-// v_rcp_f64 refined by two Newton steps (full double accuracy) for double.
-__device__ inline float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ inline double fast_rcp(double x) {
-    double r = __builtin_amdgcn_rcp(x);
-    double e = fma(-x, r, 1.0);
-    r = fma(r, e, r);
-    e = fma(-x, r, 1.0);
-    return fma(r, e, r);
-}
-
-// Reciprocal square root for the Lambda^{-1/2} scale of the two-sided
-// system: v_rsq_f32 for float; v_rsq_f64 refined by two Newton steps
-// y <- y + y (1 - x y^2) / 2 for double.
-__device__ inline float fast_rsqrt(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ inline double fast_rsqrt(double x) {
-    double y = __builtin_amdgcn_rsq(x);
-    double e = fma(-x * y, y, 1.0);
-    y = fma(0.5 * y, e, y);
-    e = fma(-x * y, y, 1.0);
-    return fma(0.5 * y, e, y);
-}
-
 // Lambda^{-1} or, for the two-sided system, Lambda^{-1/2}
 template <typename T>
 __device__ inline T lam_inv(T lam, int half) { return half ? fast_rsqrt(lam) : fast_rcp(lam); }
