@@ -735,6 +735,229 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
     }
 }
 
+// ------------------------------------------ half-length DST-I (stage engine)
+// The DST-I of a real line x_1..x_n (H = n + 1 even) through one complex
+// FFT of length H of y_j = sin(pi j / H)(x_j + x_{H-j}) + (x_j - x_{H-j}) / 2
+// (y_0 = 0): with Y the DFT of a real y, S_{2f} = -Im Y_f and S_{2f+1} =
+// sum_{f' <= f} Re Y_{f'} - Re Y_0 / 2 (a standard reduction, derived from
+// the sine sums).  The two real lines of a complex line z = x' + i x'' are
+// separated by Y'_f = (Z_f + conj Z_{H-f}) / 2, Y''_f = (Z_f - conj Z_{H-f}) / 2i.
+// Against the odd extension of length L = 2H: half the radix work and half
+// the LDS per line.
+
+// y from x in place for every line of the tile (index 0 holds 0 and keeps it).
+// twL: the pass's interleaved table exp(-2 pi i e / L), Im = -sin(pi e / H).
+template <typename T, int H, int NC>
+__device__ inline void dsth_pre(T* re, T* im, const T* __restrict__ twL, int tid) {
+    using TH = Tile<T, H, NC>;
+    constexpr int HH = H / 2, LP = TH::LP;
+    for (int e = tid; e < NC * HH; e += TH::NT) {
+        const int ln = e / HH, j = e - ln * HH + 1;   // 1 .. H/2
+        const T sn = -twL[2 * j + 1];
+        const int a1 = ln * LP + TH::idx(j), a2 = ln * LP + TH::idx(H - j);
+        const T x1 = re[a1], x1m = re[a2], x2 = im[a1], x2m = im[a2];
+        const T p1 = sn * (x1 + x1m), m1 = T(0.5) * (x1 - x1m);
+        const T p2 = sn * (x2 + x2m), m2 = T(0.5) * (x2 - x2m);
+        re[a1] = p1 + m1;
+        re[a2] = p1 - m1;   // j = H/2: the same slot, m = 0
+        im[a1] = p2 + m2;
+        im[a2] = p2 - m2;
+    }
+}
+
+// DST coefficients S_k (k = 2f, 2f + 1) of both real lines of line sl from
+// the FFT Z in LDS, for the CH values f = st CH + q this thread owns
+// (threads st = 0 .. TPL-1 of the line): the chunk totals of C go through
+// LDS (tot1, tot2: NT entries), then the chunk is read again for the running
+// sums.  Ends after a barrier: the LDS lines may then be overwritten.
+template <typename T, int H, int NC, int TPL, int CH>
+__device__ inline void dsth_post(const T* re, const T* im, T* tot1, T* tot2, int sl, int st,
+                                 T (&s1)[2 * CH], T (&s2)[2 * CH]) {
+    using TH = Tile<T, H, NC>;
+    constexpr int HH = H / 2, LP = TH::LP;
+    const T* lr = re + sl * LP;
+    const T* li = im + sl * LP;
+    // C_f = (Re Z_f + Re Z_{H-f}, Im Z_f + Im Z_{H-f}) / 2, Z_H = Z_0
+    auto cpair = [&](int f, T& c1, T& c2, T& d1, T& d2) {
+        const int fm = f == 0 ? 0 : H - f;
+        const T zr = lr[TH::idx(f)], zi = li[TH::idx(f)];
+        const T br = lr[TH::idx(fm)], bi = li[TH::idx(fm)];
+        c1 = T(0.5) * (zr + br);
+        c2 = T(0.5) * (zi + bi);
+        d1 = -T(0.5) * (zi - bi);
+        d2 = T(0.5) * (zr - br);
+    };
+    T t1 = 0, t2 = 0;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int f = st * CH + q;
+        if (f < HH) {
+            T c1, c2, d1, d2;
+            cpair(f, c1, c2, d1, d2);
+            t1 += c1;
+            t2 += c2;
+        }
+    }
+    tot1[sl * TPL + st] = t1;
+    tot2[sl * TPL + st] = t2;
+    __syncthreads();
+    T o1 = -T(0.5) * lr[TH::idx(0)], o2 = -T(0.5) * li[TH::idx(0)];   // -C_0 / 2
+    for (int u = 0; u < st; ++u) {
+        o1 += tot1[sl * TPL + u];
+        o2 += tot2[sl * TPL + u];
+    }
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+        const int f = st * CH + q;
+        T c1 = 0, c2 = 0, d1 = 0, d2 = 0;
+        if (f < HH) cpair(f, c1, c2, d1, d2);
+        o1 += c1;
+        o2 += c2;
+        s1[2 * q] = d1;       // S_{2f} = -Im Y_f
+        s2[2 * q] = d2;
+        s1[2 * q + 1] = o1;   // S_{2f+1}
+        s2[2 * q + 1] = o2;
+    }
+    __syncthreads();
+}
+
+// Last-axis pass S Lambda^{-1} S (Lambda^{-1/2} for the two-sided system)
+// with the Parseval partials of (r, P^{-1} r), by the half-length DST-I:
+// the scaled coefficients go back to LDS in natural order (they are the
+// input of the second DST-I).  Tile: NC complex lines of the transform of
+// length H = L/2; the workgroup count equals the odd-extension kernel's for
+// the same NC.
+template <typename T, int L, int NC>
+__global__ __launch_bounds__((Tile<T, L / 2, NC>::NT)) void k_dstsh_s(DstArgs<T> a) {
+    constexpr int H = L / 2;
+    using TH = Tile<T, H, NC>;
+    constexpr int NCL = TH::NCL, NT = TH::NT, LP = TH::LP, TX = TH::TX;
+    constexpr int GRP = NT / TX;
+    constexpr int TPL = NT / NCL, CH = (H / 2 + TPL - 1) / TPL;
+    static_assert(H % 2 == 0 && NT % NCL == 0, "half-length tile");
+    constexpr bool TWL = twiddles_in_lds(H);
+    if (a.ctrl && a.ctrl->done) return;
+    __shared__ T s_re[NCL * LP];
+    __shared__ T s_im[NCL * LP];
+    __shared__ T s_twr[TWL ? H : 1], s_twi[TWL ? H : 1];
+    __shared__ T s_P[TX], s_Q[TX];
+    __shared__ T s_t1[NT], s_t2[NT];
+    __shared__ double s_red[NT / 64];
+    const int tid = threadIdx.x;
+    const int n = a.g.n, P1 = a.g.P1;
+    const long es = a.g.estride;
+    const int ntx = P1 / TX;
+    const int xt = blockIdx.x % ntx, o = blockIdx.x / ntx;
+    const int x0 = xt * TX;
+    const int xl = tid % TX, ig = tid / TX;
+    const int sl = tid / TPL, st = tid - sl * TPL;
+    const long base = (long)o * a.g.ostride + x0 + xl;
+    // the length-H twiddles are every other entry of the pass's table
+    if constexpr (TWL) {
+        gather_chunked<T, H, NT>(tid, H, [&](int e) { return a.tw[4 * e]; },
+                                 [&](int e, T v) { s_twr[e] = v; });
+        gather_chunked<T, H, NT>(tid, H, [&](int e) { return a.tw[4 * e + 1]; },
+                                 [&](int e, T v) { s_twi[e] = v; });
+    }
+    const T* twr = TWL ? s_twr : a.tw;
+    const T* twi = TWL ? s_twi : a.tw + 1;
+    // line factors before the tile's rows: one wait for memory
+    T fa1 = 0, fl1 = 0, fa2 = 0, fl2 = 0;
+    if (tid < TX && x0 + tid < a.g.nx) {
+        fa1 = a.a1[x0 + tid];
+        fl1 = a.lc1[x0 + tid];
+        if (a.dim == 3) {
+            fa2 = a.a2[o];
+            fl2 = a.lc2[o];
+        }
+    }
+    {
+        T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+        gather_chunked<T, H, GRP>(
+            ig, n, [&](int i) { return a.u[base + (long)i * es]; },
+            [&](int i, T v) { line[TH::idx(i + 1)] = v; });
+        if (ig == 0) line[TH::idx(0)] = T(0);
+    }
+    if (tid < TX) {
+        T P = 0, Q = 0;
+        if (x0 + tid < a.g.nx) {
+            if (a.dim == 2) {
+                P = fa1 + fl1;
+                Q = fa1;
+            } else {
+                P = fa2 * (fa1 + fl1) + fl2 * fa1;
+                Q = fa2 * fa1;
+            }
+        }
+        s_P[tid] = P;
+        s_Q[tid] = Q;
+    }
+    __syncthreads();
+    constexpr int TWS2 = TWL ? 1 : 4;
+    dsth_pre<T, H, NCL>(s_re, s_im, a.tw, tid);
+    __syncthreads();
+    FFTRun<T, H, 0, 1, TWS2, NCL>::run(s_re, s_im, twr, twi, tid);
+    T s1[2 * CH], s2[2 * CH];
+    dsth_post<T, H, NCL, TPL, CH>(s_re, s_im, s_t1, s_t2, sl, st, s1, s2);
+    // scale: c = sqrt(2 / H) makes the transform orthonormal
+    const T c = T(2) * a.c;
+    double acc = 0.0;
+    const T P0 = s_P[2 * sl], Q0 = s_Q[2 * sl], P1v = s_P[2 * sl + 1], Q1v = s_Q[2 * sl + 1];
+    auto scale_all = [&](auto half_c) {
+        constexpr bool HF = decltype(half_c)::value;
+        // this thread's a_k, lc_k (k = 2f, 2f + 1), all loads before the arithmetic
+        T ak[2 * CH], lk[2 * CH];
+#pragma unroll
+        for (int q = 0; q < 2 * CH; ++q) {
+            const int k = 2 * st * CH + q;
+            const bool ok = k >= 1 && k <= n;
+            ak[q] = ok ? a.a_last[k - 1] : T(0);
+            lk[q] = ok ? a.lc_last[k - 1] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < 2 * CH; ++q) {
+            const int k = 2 * st * CH + q;
+            if (k >= H) break;
+            T w1 = 0, w2 = 0;
+            if (k >= 1) {
+                const T lam0 = ak[q] * P0 + lk[q] * Q0;
+                const T lam1 = ak[q] * P1v + lk[q] * Q1v;
+                const T inv0 = P0 != T(0) ? (HF ? fast_rsqrt(lam0) : fast_rcp(lam0)) : T(0);
+                const T inv1 = P1v != T(0) ? (HF ? fast_rsqrt(lam1) : fast_rcp(lam1)) : T(0);
+                const T v1 = c * s1[q], v2 = c * s2[q];
+                w1 = v1 * inv0;
+                w2 = v2 * inv1;
+                acc += (double)v1 * (double)w1 + (double)v2 * (double)w2;
+            }
+            s_re[sl * LP + TH::idx(k)] = w1;   // k = 0: the zero of the next input
+            s_im[sl * LP + TH::idx(k)] = w2;
+        }
+    };
+    if (a.half) scale_all(std::true_type{});
+    else scale_all(std::false_type{});
+    __syncthreads();
+    dsth_pre<T, H, NCL>(s_re, s_im, a.tw, tid);
+    __syncthreads();
+    FFTRun<T, H, 0, 1, TWS2, NCL>::run(s_re, s_im, twr, twi, tid);
+    dsth_post<T, H, NCL, TPL, CH>(s_re, s_im, s_t1, s_t2, sl, st, s1, s2);
+#pragma unroll
+    for (int q = 0; q < 2 * CH; ++q) {
+        const int k = 2 * st * CH + q;
+        if (k >= H) break;
+        s_re[sl * LP + TH::idx(k)] = c * s1[q];
+        s_im[sl * LP + TH::idx(k)] = c * s2[q];
+    }
+    __syncthreads();
+    const T* line = ((xl & 1) ? s_im : s_re) + (xl >> 1) * LP;
+    const bool pad_line = x0 + xl >= a.g.nx;   // stored as exact zeros
+    for (int i = ig; i < n; i += GRP)
+        st_nt(a.o + base + (long)i * es, pad_line ? T(0) : line[TH::idx(i + 1)]);
+    if (a.partials) {
+        const double sm = block_sum<NT>(acc, s_red);
+        if (tid == 0) a.partials[blockIdx.x] = sm;
+    }
+}
+
 // ------------------------------------------------------------- launchers
 
 #define FSD_FOR_EACH_L(X) \

@@ -54,6 +54,24 @@ hipError_t stage_s_launch(const A& a, int* nb, hipStream_t s, int eng) {
     return hipGetLastError();
 }
 
+// The stage engine's last-axis scale pass by the half-length DST-I: the
+// tile of NC complex lines at length L/2, the same workgroup count as the
+// odd-extension kernel with NC lines.
+template <typename T, int L>
+hipError_t stage_dstsh_launch(const DstArgs<T>& a, int* nb, hipStream_t s, int eng) {
+    using NC = StageNC<T, L>;
+    if (eng == ENG_STAGE_HALF && NC::H != NC::D) {
+        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer, NC::H);
+        if (nb) *nb = g;
+        if (g) hipLaunchKernelGGL((k_dstsh_s<T, L, NC::H>), dim3(g), dim3(Tile<T, L / 2, NC::H>::NT), 0, s, a);
+    } else {
+        const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer, NC::D);
+        if (nb) *nb = g;
+        if (g) hipLaunchKernelGGL((k_dstsh_s<T, L, NC::D>), dim3(g), dim3(Tile<T, L / 2, NC::D>::NT), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
 // kernel handles of the stage engine, by tile shape
 template <typename T, int L, int NC> struct KToepX { static constexpr auto kernel = k_toep_x<T, L, NC>; };
 template <typename T, int L, int NC> struct KToepS { static constexpr auto kernel = k_toep_s<T, L, NC>; };
@@ -204,8 +222,13 @@ hipError_t dst_s_one(const DstArgs<T>& a, int* nb, hipStream_t s, int eng) {
             return wave_dst_s<T, L, SCALE, wave_lpl_default<T, L>()>(a, nb, s);
         }
     }
-    if constexpr (SCALE) return stage_s_launch<T, L, KDstsS>(a, nb, s, eng);
-    else return stage_s_launch<T, L, KDstS>(a, nb, s, eng);
+    if constexpr (SCALE) {
+        // lengths with an even half take the half-length DST-I
+        if constexpr (L >= 8 && (L / 2) % 2 == 0) return stage_dstsh_launch<T, L>(a, nb, s, eng);
+        else return stage_s_launch<T, L, KDstsS>(a, nb, s, eng);
+    } else {
+        return stage_s_launch<T, L, KDstS>(a, nb, s, eng);
+    }
 }
 
 #define FSD_W_CASE_TX(LL) case LL: return toep_x_one<FT, LL>(a, nb, s, eng);
