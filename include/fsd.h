@@ -248,7 +248,8 @@ fsd_status fsd_cn_step(fsd_problem prob, const double* d_u_prev, const double* d
  * of two, FSD_ENGINE_WAVE1, which launches twice the wavefronts), the
  * column engine (float32 strided passes of length 512; for DST passes with
  * the DST-I by the odd extension or by the half-length algorithm), and the
- * LDS-stage engine with its default tile or half of it.  All give the same
+ * LDS-stage engine with its default tile or half of it (its last-axis
+ * DST-Lambda-DST pass by the half-length DST-I).  All give the same
  * operator to rounding.  FSD_ENGINE_AUTO is the built-in choice per
  * length. */
 enum {

@@ -173,9 +173,11 @@ int gdst_col_blocks(const PassGeo& g);
 //   ENG_WAVE1       wave engine with one complex line per lane group
 //                   (float32; twice the wavefronts of ENG_WAVE).
 // Defaults: column engine for float32 strided passes of length 512 (the
-// half-length DST for the Lambda-scale pass), the wave engine for the
-// other lengths 64..512, the stage engine otherwise.  An engine a length
-// does not have falls back to the default.
+// half-length DST for the Lambda-scale pass), the stage engine for the
+// float64 Lambda-scale pass (half-length DST), the wave engine for the
+// other passes of lengths 64..512, the stage engine otherwise.  The stage
+// engine's Lambda-scale pass takes the half-length DST-I wherever n + 1 is
+// even.  An engine a length does not have falls back to the default.
 enum Engine : int { ENG_AUTO = 0, ENG_WAVE = 1, ENG_COL = 2, ENG_COLH = 3, ENG_STAGE = 4,
                     ENG_STAGE_HALF = 5, ENG_WAVE1 = 6, ENG_COUNT = 7 };
 

@@ -70,7 +70,7 @@ _KINDS = [
     (re.compile(r"k2?_toep_x\b"), "toep_x"),
     (re.compile(r"k2?_toep_s\b"), "toep_s"),
     (re.compile(r"k2?_dst_x\b"), "dst_x"),
-    (re.compile(r"k_dsts_s\b"), "dsts"),
+    (re.compile(r"k_dstsh?_s\b"), "dsts"),
     (re.compile(r"k2_dst_s\s*<\s*\w+\s*,\s*\d+\s*,\s*(true|1)\b"), "dsts"),
     (re.compile(r"k2?_dst_s\b"), "dst_y"),
     (re.compile(r"k_mdot\b"), "gm_mdot"),

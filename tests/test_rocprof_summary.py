@@ -28,13 +28,15 @@ def test_classify_matvec_and_preconditioner_passes():
         "void fsd::k2_dst_s<float, 256, false, 1>(fsd::DstArgs<float>)",
         "void fsd::k_dst_s<float, 512, 1>(fsd::DstArgs<float>)",
         "void fsd::k_dsts_s<float, 512, 1>(fsd::DstArgs<float>)",
+        "void fsd::k_dstsh_s<double, 512, 8>(fsd::DstArgs<double>)",
+        "void fsd::k2_toep_x<float, 512, 3, 2>(fsd::ToepArgs<float>)",
         "void fsd::k_mdot<float, 4>(fsd::MdotArgs)",
         "some_other_kernel",
     ]
     assert rs.classify(_rows(names)) == [
         "toep_x_f32", "toep_y_f32", "toep_z_f32", "dst_x_f32", "dst_y_f32", "dsts_z_f32",
         "dst_y_f32", "dsts_z_f64", "dst_y_f64", "dsts_z_f32", "dst_y_f32", "dst_y_f32",
-        "dsts_z_f32", "gm_mdot_f32", None]
+        "dsts_z_f32", "dsts_z_f64", "toep_x_f32", "gm_mdot_f32", None]
 
 
 def test_sq_summary_fractions(tmp_path):
