@@ -688,6 +688,22 @@ fsd_status pcg(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long m
 
 // ------------------------------------------------------------ GMRES
 
+// A right-hand side formed on first use: b = scale * src (float64 src cast
+// to the solver's type), for a mixed-precision inner GMRES that starts from
+// the given P^{-1} b and needs b itself only on a restart.
+struct LazyB {
+    const double* src = nullptr;
+    double scale = 1.0;
+};
+
+template <typename T>
+fsd_status ensure_b(fsd_problem P, const T* b, const LazyB*& lazy) {
+    if (!lazy) return FSD_OK;
+    HIP_TRY((vec_cast<double, T>(lazy->src, const_cast<T*>(b), P->Np, lazy->scale, P->stream)));
+    lazy = nullptr;
+    return FSD_OK;
+}
+
 // The Gram-Schmidt prologue (PRO_ARNOLDI) exists on the wave engine's x pass.
 template <typename T>
 bool fused_arnoldi_ok(fsd_problem P) {
@@ -701,7 +717,7 @@ bool fused_arnoldi_ok(fsd_problem P) {
 // by the caller; the mixed-precision loop passes its float64 P^{-1} r.
 template <typename T>
 fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
-                 double abs_tol, SolveOut& out, bool w_given = false) {
+                 double abs_tol, SolveOut& out, bool w_given = false, const LazyB* lazy = nullptr) {
     Vecs<T>& v = vecs<T>(P);
     hipStream_t s = P->stream;
     const long Np = P->Np;
@@ -721,7 +737,10 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     // v_{j+1} runs in the prologue of the next matvec (unnormalised basis)
     const bool fused = !split && eta2 == 0.0 && fused_arnoldi_ok<T>(P);
     // ||P^{-1} b|| (||P^{-1/2} b||)
-    if (!(w_given && x0_zero)) FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
+    if (!(w_given && x0_zero)) {
+        FSD_TRY(ensure_b<T>(P, b, lazy));
+        FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
+    }
     HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
     HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s));
     if (x0_zero) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
@@ -733,13 +752,15 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         // with x = 0, w still holds P^{-1} b and the partials of its norm
         // are still in place from above
         if (!(x0_zero && cycle == 0)) {
+            FSD_TRY(ensure_b<T>(P, b, lazy));
             FSD_TRY(first_residual<T>(P, x, b, v.r, P->ctrl, &np));
             FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr, split));
             HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         }
         HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
-        // the fused path learns of convergence one x pass later
-        int chunk = std::max(2, P->last_iters - (fused ? 0 : 1));
+        // the fused path learns of convergence one x pass later (and a
+        // further enqueued iteration measured cheaper than a second chunk)
+        int chunk = std::max(2, P->last_iters + (fused ? 1 : -1));
         int j = 0;
         const size_t rec0 = P->prof.size();
         for (;;) {
@@ -889,10 +910,12 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
 // abs_tol): ||r|| vs ||b|| for PCG, ||P^{-1} r|| vs ||P^{-1} b|| for GMRES.
 template <typename T>
 fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
-                  SolveOut& o, double abs_tol = 0.0, bool w_given = false) {
+                  SolveOut& o, double abs_tol = 0.0, bool w_given = false,
+                  const LazyB* lazy = nullptr) {
     P->prof_tag = -1;
     if (P->solver == FSD_SOLVER_PGMRES || P->solver == FSD_SOLVER_PGMRES2)
-        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o, w_given);
+        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o, w_given, lazy);
+    FSD_TRY(ensure_b<T>(P, b, lazy));
     return pcg<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
 }
 
@@ -1010,15 +1033,21 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
             if (nrm.r == 0.0 || (!skip && prec_rel <= tol)) { status = FSD_OK; break; }
             if (outer >= P->p.max_outer || iters >= maxit) break;
             const double rnorm = nrm.r;
-            HIP_TRY((vec_cast<double, float>(r, f.b, P->Np, 1.0 / rnorm, P->stream)));
+            // the inner GMRES given P^{-1} r needs r itself only on a restart:
+            // it is cast then (LazyB)
+            LazyB lb;
+            lb.src = r;
+            lb.scale = 1.0 / rnorm;
             if (left && !skip) HIP_TRY((vec_cast<double, float>(pz, f.w, P->Np, 1.0 / rnorm, P->stream)));
+            else HIP_TRY((vec_cast<double, float>(r, f.b, P->Np, 1.0 / rnorm, P->stream)));
             const double ref = left ? nrm.pb : nrm.b;
             SolveOut o;
             const int saved = P->last_iters;
             const int slot = std::min(outer, 3);
             P->last_iters = P->last_inner_iters[slot];
             FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o,
-                                  tol * ref / rnorm, left && !skip));
+                                  tol * ref / rnorm, left && !skip,
+                                  left && !skip ? &lb : nullptr));
             pred = prec_rel * std::max(o.relres, kInnerFloor);
             P->last_inner_iters[slot] = P->last_iters;
             P->last_iters = saved;
