@@ -406,10 +406,12 @@ fsd_status circ_precond(fsd_problem P, const double* in, double* out, const Ctrl
 // Preconditioner z = S_N Lambda^{-1} S_N r (Section 3, ``diag_tau_pre``):
 // DST-I along x, (y,) then DST-I / Lambda^{-1} / DST-I along the last axis,
 // then back.  With `partials`, the last-axis pass also leaves the Parseval
-// partial sums of (r, z).
+// partial sums of (r, z), or with `pnorm` those of ||z||^2 (S is orthogonal:
+// ||z|| is the norm of the scaled spectrum; a dot product after the passes
+// where the scale pass does not provide it).
 template <typename T>
 fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, double* partials,
-                      int* nparts, bool half = false) {
+                      int* nparts, bool half = false, bool pnorm = false) {
     if (P->pc != FSD_PC_TAU) {
         // comparators of Section 4; the Parseval partials become a dot product
         if (P->pc == FSD_PC_NONE) {
@@ -419,7 +421,8 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
         } else {
             return fail(FSD_EINVAL, "the circulant preconditioners run in float64 only");
         }
-        if (partials) HIP_TRY(vec_dot<T>(in, out, P->Np, partials, ctrl, nparts, P->stream));
+        if (partials)
+            HIP_TRY(vec_dot<T>(pnorm ? out : in, out, P->Np, partials, ctrl, nparts, P->stream));
         return FSD_OK;
     }
     Tables<T>& tb = tabs<T>(P);
@@ -498,7 +501,7 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
                 G.a2 = reinterpret_cast<const float*>(tb.a[1]);
                 G.lc2 = reinterpret_cast<const float*>(tb.lc[1]);
             }
-            G.partials = partials;
+            G.partials = pnorm ? nullptr : partials;
             G.half = half ? 1 : 0;
             HIP_TRY(launch_gdst_col(G, true, nparts, P->stream));
         } else {
@@ -508,7 +511,10 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
             S.a1 = tb.a[0];
             S.lc1 = tb.lc[0];
             if (P->dim == 3) { S.a2 = tb.a[1]; S.lc2 = tb.lc[1]; }
-            S.partials = partials;
+            // ||z||^2 from the float64 scale kernels (the float32 ones give (r, z) only)
+            const bool pn_here = pnorm && !is_f32<T>();
+            S.partials = pnorm && !pn_here ? nullptr : partials;
+            S.pnorm = pn_here ? 1 : 0;
             S.half = half ? 1 : 0;
             HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream, eng(kl)));
         }
@@ -519,6 +525,9 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
         cur = v.t[3];
     }
     FSD_TRY(x_pass(cur, out));
+    const bool pn_kernel = pnorm && !is_f32<T>() && !mfma(last);
+    if (pnorm && partials && !pn_kernel && P->tune_kind < 0)
+        HIP_TRY(vec_dot<T>(out, out, P->Np, partials, ctrl, nparts, P->stream));
     return FSD_OK;
 }
 
@@ -950,16 +959,15 @@ fsd_status outer_norms(fsd_problem P, const double* x, const double* b, double* 
         HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
         HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_BB, s));
         if (pz) {
-            FSD_TRY(op_precond<double>(P, b, pz, nullptr, nullptr, nullptr, split));
-            HIP_TRY(vec_dot<double>(pz, pz, P->Np, P->partials, nullptr, &np, s));
+            // ||P^{-1} b||^2 by Parseval from the scale pass
+            FSD_TRY(op_precond<double>(P, b, pz, nullptr, P->partials, &np, split, true));
             HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RZ, s));
         }
     }
     FSD_TRY(first_residual<double>(P, x, b, r, nullptr, &np));
     HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE, s));
     if (pz) {
-        FSD_TRY(op_precond<double>(P, r, pz, nullptr, nullptr, nullptr, split));
-        HIP_TRY(vec_dot<double>(pz, pz, P->Np, P->partials, nullptr, &np, s));
+        FSD_TRY(op_precond<double>(P, r, pz, nullptr, P->partials, &np, split, true));
         HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RR, s));
     }
     FSD_TRY(read_ctrl(P));

@@ -138,6 +138,8 @@ struct DstArgs {
     int dim;
     int half;             // scale pass: Lambda^{-1/2} (the two-sided system) instead of Lambda^{-1}
     double* partials;     // Parseval partials of (r, P^{-1} r)
+    int pnorm;            // float64 scale passes: the partials are ||P^{-1} r||^2 (Parseval
+                          // of the scaled spectrum) instead
     const Ctrl* ctrl;
 };
 

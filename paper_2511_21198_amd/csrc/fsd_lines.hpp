@@ -711,7 +711,9 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
             const T s2 = s_re[ad] * a.c;
             wr = s1 * inv0;
             wi = s2 * inv1;
-            if (f <= n) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
+            if (f <= n)
+                acc += (a.pnorm ? (double)wr : (double)s1) * (double)wr +
+                       (a.pnorm ? (double)wi : (double)s2) * (double)wi;
         }
         s_re[ad] = wr;
         s_im[ad] = wi;
@@ -927,7 +929,8 @@ __global__ __launch_bounds__((Tile<T, L / 2, NC>::NT)) void k_dstsh_s(DstArgs<T>
                 const T v1 = c * s1[q], v2 = c * s2[q];
                 w1 = v1 * inv0;
                 w2 = v2 * inv1;
-                acc += (double)v1 * (double)w1 + (double)v2 * (double)w2;
+                acc += (a.pnorm ? (double)w1 : (double)v1) * (double)w1 +
+                       (a.pnorm ? (double)w2 : (double)v2) * (double)w2;
             }
             s_re[sl * LP + TH::idx(k)] = w1;   // k = 0: the zero of the next input
             s_im[sl * LP + TH::idx(k)] = w2;

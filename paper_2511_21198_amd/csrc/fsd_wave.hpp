@@ -1070,7 +1070,9 @@ __attribute__((amdgpu_waves_per_eu(WS<T, L, LPLV>::MINW))) void k2_dst_s(DstArgs
                     const T s2 = xr[q] * a.c;
                     wr = s1 * inv0;
                     wi = s2 * inv1;
-                    if (f <= n) acc += (double)s1 * (double)wr + (double)s2 * (double)wi;
+                    if (f <= n)
+                        acc += (a.pnorm ? (double)wr : (double)s1) * (double)wr +
+                               (a.pnorm ? (double)wi : (double)s2) * (double)wi;
                 }
                 xr[q] = wr;
                 xi[q] = wi;
