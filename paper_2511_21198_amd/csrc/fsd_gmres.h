@@ -46,8 +46,10 @@ hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ct
                      hipStream_t s);
 template <typename T>
 hipError_t gm_scale(const T* in, T* out, long N, const Ctrl* ctrl, hipStream_t s);
+// GM_PBB / GM_BETA with nparts = 0 take the squared norm val instead of a
+// sum of partials.
 hipError_t gm_scalar(Ctrl* c, const double* partials, int nparts, int nv, int j, int op,
-                     hipStream_t s);
+                     hipStream_t s, double val = 0.0);
 hipError_t gm_restart(Ctrl* c, hipStream_t s);
 
 }  // namespace fsd

@@ -336,7 +336,7 @@ __device__ inline void gm_givens(Ctrl* c, double* gm, int m, int j, double hnext
 }
 
 __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restrict__ partials,
-                                                  int nparts, int nv, int j, int op) {
+                                                  int nparts, int nv, int j, int op, double val) {
     __shared__ double sums[kMaxRestart + 2];
     __shared__ double red[SNW];
     __shared__ double sH[kMaxRestart + 1], sCS[kMaxRestart], sSN[kMaxRestart];
@@ -479,8 +479,8 @@ __global__ __launch_bounds__(ST) void k_gm_scalar(Ctrl* c, const double* __restr
         gm_givens(c, gm, m, j, sqrt(S), sH, sCS, sSN);
         return;
     }
-    // GM_PBB, GM_BETA: a single norm
-    const double S = sums[0];
+    // GM_PBB, GM_BETA: a single norm (given as val without partials)
+    const double S = nparts > 0 ? sums[0] : val;
     if (op == GM_PBB) {
         if (tid == 0) {
             c->bb = S;
@@ -605,8 +605,8 @@ hipError_t gm_scale(const T* in, T* out, long N, const Ctrl* ctrl, hipStream_t s
 }
 
 hipError_t gm_scalar(Ctrl* c, const double* partials, int nparts, int nv, int j, int op,
-                     hipStream_t s) {
-    hipLaunchKernelGGL(k_gm_scalar, dim3(1), dim3(ST), 0, s, c, partials, nparts, nv, j, op);
+                     hipStream_t s, double val) {
+    hipLaunchKernelGGL(k_gm_scalar, dim3(1), dim3(ST), 0, s, c, partials, nparts, nv, j, op, val);
     return hipGetLastError();
 }
 

@@ -726,7 +726,8 @@ bool fused_arnoldi_ok(fsd_problem P) {
 // by the caller; the mixed-precision loop passes its float64 P^{-1} r.
 template <typename T>
 fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
-                 double abs_tol, SolveOut& out, bool w_given = false, const LazyB* lazy = nullptr) {
+                 double abs_tol, SolveOut& out, bool w_given = false, const LazyB* lazy = nullptr,
+                 double w_norm2 = -1.0) {
     Vecs<T>& v = vecs<T>(P);
     hipStream_t s = P->stream;
     const long Np = P->Np;
@@ -750,8 +751,11 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         FSD_TRY(ensure_b<T>(P, b, lazy));
         FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
     }
-    HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
-    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s));
+    // a given w may come with its squared norm (w_norm2 >= 0)
+    const bool wn_given = w_given && x0_zero && w_norm2 >= 0.0;
+    if (wn_given) np = 0;
+    else HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
+    HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s, w_norm2));
     if (x0_zero) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
     const int yoff = gm_off_y(m), h2off = gm_off_h2(m);
     bool converged = false;
@@ -766,7 +770,8 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             FSD_TRY(op_precond<T>(P, v.r, v.w, P->ctrl, nullptr, nullptr, split));
             HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
         }
-        HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_BETA, s));
+        HIP_TRY(gm_scalar(P->ctrl, P->partials, wn_given && cycle == 0 ? 0 : np, 1, 0, GM_BETA, s,
+                          w_norm2));
         // the fused path learns of convergence one x pass later (and a
         // further enqueued iteration measured cheaper than a second chunk)
         int chunk = std::max(2, P->last_iters + (fused ? 1 : -1));
@@ -920,10 +925,10 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
 template <typename T>
 fsd_status krylov(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long maxit,
                   SolveOut& o, double abs_tol = 0.0, bool w_given = false,
-                  const LazyB* lazy = nullptr) {
+                  const LazyB* lazy = nullptr, double w_norm2 = -1.0) {
     P->prof_tag = -1;
     if (P->solver == FSD_SOLVER_PGMRES || P->solver == FSD_SOLVER_PGMRES2)
-        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o, w_given, lazy);
+        return gmres<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o, w_given, lazy, w_norm2);
     FSD_TRY(ensure_b<T>(P, b, lazy));
     return pcg<T>(P, x, b, x0_zero, tol, maxit, abs_tol, o);
 }
@@ -1053,9 +1058,12 @@ fsd_status solve_internal(fsd_problem P, double* x, const double* b, bool x0_zer
             const int saved = P->last_iters;
             const int slot = std::min(outer, 3);
             P->last_iters = P->last_inner_iters[slot];
+            // ||w||^2 of the given first vector w = P^{-1} r / ||r|| from the
+            // float64 norm (w is its float32 rounding)
+            const double wn2 = left && !skip ? (nrm.pr / rnorm) * (nrm.pr / rnorm) : -1.0;
             FSD_TRY(krylov<float>(P, f.x, f.b, true, P->p.inner_tol, maxit - iters, o,
                                   tol * ref / rnorm, left && !skip,
-                                  left && !skip ? &lb : nullptr));
+                                  left && !skip ? &lb : nullptr, wn2));
             pred = prec_rel * std::max(o.relres, kInnerFloor);
             P->last_inner_iters[slot] = P->last_iters;
             P->last_iters = saved;
