@@ -41,9 +41,10 @@ hipError_t gm_mdot(const T* V, long ld, int nv, const T* w, long N, double* part
 template <typename T>
 hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, const Ctrl* ctrl,
                     int hoff, int mode, double* partials, int* nparts, hipStream_t s);
+// x += V y, or x = V y with overwrite (x not read)
 template <typename T>
 hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ctrl, int yoff,
-                     hipStream_t s);
+                     hipStream_t s, bool overwrite = false);
 template <typename T>
 hipError_t gm_scale(const T* in, T* out, long N, const Ctrl* ctrl, hipStream_t s);
 // GM_PBB / GM_BETA with nparts = 0 take the squared norm val instead of a

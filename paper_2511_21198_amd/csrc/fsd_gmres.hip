@@ -231,17 +231,18 @@ __global__ __launch_bounds__(GT) void k_maxpy(const T* __restrict__ V, long ld, 
     }
 }
 
-// x += sum_{i < k} y_i V_i with k = ctrl->gm_k and y in ctrl->gm (yoff).
+// x += sum_{i < k} y_i V_i with k = ctrl->gm_k and y in ctrl->gm (yoff);
+// with overwrite, x = sum_{i < k} y_i V_i (x = 0 for k = 0; x is not read).
 // The host launches the instance NV = k; any other k (k = 0 after an
 // immediate convergence) takes the predicated loop, which never touches a
 // basis vector beyond k (unwritten memory may hold NaN patterns).
 template <typename T, int NV, bool EXACT>
 __global__ __launch_bounds__(GT) void k_gm_update(T* x, const T* __restrict__ V, long ld, long N,
-                                                  const Ctrl* ctrl, int yoff) {
+                                                  const Ctrl* ctrl, int yoff, int overwrite) {
     using VT = typename Vec16<T>::type;
     constexpr int VW = Vec16<T>::W;
     const int k = ctrl->gm_k;
-    if (k <= 0) return;
+    if (k <= 0 && !overwrite) return;
     T y[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) y[i] = i < k ? (T)ctrl->gm[yoff + i] : T(0);
@@ -250,7 +251,13 @@ __global__ __launch_bounds__(GT) void k_gm_update(T* x, const T* __restrict__ V,
     VT* xv = reinterpret_cast<VT*>(x);
     const bool full = EXACT && k == NV;
     for (long e = blockIdx.x * (long)GT + threadIdx.x; e < NW; e += (long)gridDim.x * GT) {
-        VT acc = xv[e];
+        VT acc;
+        if (overwrite) {
+            acc.x = T(0); acc.y = T(0);
+            if constexpr (VW == 4) { acc.z = T(0); acc.w = T(0); }
+        } else {
+            acc = xv[e];
+        }
         VT v[NV];
         if (full) {
 #pragma unroll
@@ -591,10 +598,11 @@ hipError_t gm_maxpy(const T* V, long ld, int nv, const T* in, T* out, long N, co
 
 template <typename T>
 hipError_t gm_update(T* x, const T* V, long ld, long N, int kmax, const Ctrl* ctrl, int yoff,
-                     hipStream_t s) {
+                     hipStream_t s, bool overwrite) {
     if (!vec_ok(N, ld)) return hipErrorInvalidValue;
     const int g = ggrid(N);
-    FSD_NV_DISPATCH(k_gm_update, T, kmax, dim3(g), dim3(GT), 0, s, x, V, ld, N, ctrl, yoff);
+    FSD_NV_DISPATCH(k_gm_update, T, kmax, dim3(g), dim3(GT), 0, s, x, V, ld, N, ctrl, yoff,
+                    overwrite ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -621,7 +629,7 @@ hipError_t gm_restart(Ctrl* c, hipStream_t s) {
     template hipError_t gm_maxpy<T>(const T*, long, int, const T*, T*, long, const Ctrl*, int,  \
                                     int, double*, int*, hipStream_t);                           \
     template hipError_t gm_update<T>(T*, const T*, long, long, int, const Ctrl*, int,           \
-                                     hipStream_t);                                              \
+                                     hipStream_t, bool);                                        \
     template hipError_t gm_scale<T>(const T*, T*, long, const Ctrl*, hipStream_t);
 
 FSD_GM_INST(double)

@@ -756,7 +756,8 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     if (wn_given) np = 0;
     else HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
     HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s, w_norm2));
-    if (x0_zero) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
+    // with x0 = 0 the first cycle's update writes x = V y (left system): no fill
+    if (x0_zero && split) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
     const int yoff = gm_off_y(m), h2off = gm_off_h2(m);
     bool converged = false;
     long total_enq = 0;
@@ -888,7 +889,8 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         HIP_TRY(gm_scalar(P->ctrl, P->partials, 0, 0, 0, GM_SOLVE, s));
         if (!split) {
             ProfScope ps(P, K_GM_UPDATE, is_f32<T>(), (double)P->N * sizeof(T) * (c.gm_k + 2));
-            HIP_TRY(gm_update<T>(x, v.V, Np, Np, std::max(1, c.gm_k), P->ctrl, yoff, s));
+            HIP_TRY(gm_update<T>(x, v.V, Np, Np, std::max(1, c.gm_k), P->ctrl, yoff, s,
+                                 x0_zero && cycle == 0));
         } else if (c.gm_k > 0) {
             // x += P^{-1/2} (V y): the combination into z, its half
             // preconditioner into q (no early exit: the solve may be done), x += q
