@@ -888,9 +888,10 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         // x += V y over the columns of this cycle
         HIP_TRY(gm_scalar(P->ctrl, P->partials, 0, 0, 0, GM_SOLVE, s));
         if (!split) {
-            ProfScope ps(P, K_GM_UPDATE, is_f32<T>(), (double)P->N * sizeof(T) * (c.gm_k + 2));
-            HIP_TRY(gm_update<T>(x, v.V, Np, Np, std::max(1, c.gm_k), P->ctrl, yoff, s,
-                                 x0_zero && cycle == 0));
+            const bool overwrite = x0_zero && cycle == 0;   // x = V y: x not read
+            ProfScope ps(P, K_GM_UPDATE, is_f32<T>(),
+                         (double)P->N * sizeof(T) * (c.gm_k + (overwrite ? 1 : 2)));
+            HIP_TRY(gm_update<T>(x, v.V, Np, Np, std::max(1, c.gm_k), P->ctrl, yoff, s, overwrite));
         } else if (c.gm_k > 0) {
             // x += P^{-1/2} (V y): the combination into z, its half
             // preconditioner into q (no early exit: the solve may be done), x += q
