@@ -911,7 +911,8 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
         if (c.iters >= maxit) { out.status = FSD_ENOTCONV; break; }
         HIP_TRY(gm_restart(P->ctrl, s));
     }
-    FSD_TRY(read_ctrl(P));
+    // the control block as read after the last chunk: the solve and the
+    // update enqueued since do not change it (no further synchronisation)
     const Ctrl& c = *P->h_ctrl;
     out.iters = c.iters;
     out.relres = c.bb > 0 ? std::sqrt(c.rr / c.bb) : 0.0;
