@@ -135,10 +135,12 @@ typedef struct {
     double reorth_eta2;    /* GMRES reorthogonalisation test: a second
                               Gram-Schmidt pass when ||w'||^2 <= reorth_eta2
                               ||w||^2 after the first (0: never; 1 or more:
-                              always).  Negative (default): 0.5 for float64
-                              solves, 0 for the float32 inner solves of mixed
-                              precision, whose result the float64 defect
-                              correction checks. */
+                              always).  Negative (default): 0, one pass (the
+                              preconditioned operator is close to the
+                              identity and the pass works on w - v_j; the
+                              paper's iteration counts are reproduced with
+                              it); 0.5 is the Daniel-Gragg-Kaufman-Stewart
+                              test. */
     int precond;           /* fsd_precond (default FSD_PC_TAU) */
 } fsd_params;
 

@@ -351,9 +351,8 @@ def test_gmres_reorth_threshold(fsd, precision, eta2):
 def test_gmres_fused_gram_schmidt(fsd, case, precision, restart):
     """One Gram-Schmidt pass with the update of v_{j+1} computed in the
     prologue of the next matvec's x pass (unnormalised basis; x lengths of the
-    wave engine, L = 64 .. 512): the float64 solver with a zero
-    reorthogonalisation threshold and the float32 inner solves of mixed
-    precision take it.  CN steps against the oracle, with restarts (restart 3
+    wave engine, L = 64 .. 512): the default (zero reorthogonalisation
+    threshold) in both precisions.  CN steps against the oracle, with restarts (restart 3
     and 4 close full cycles); float64 iteration counts within one of the
     two-pass (DGKS) solver's, which keeps the unfused kernels."""
     dim, n, d, kp, km = case
