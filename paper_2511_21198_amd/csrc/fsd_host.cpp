@@ -859,10 +859,12 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
             j += cnt;
             total_enq += cnt;
             if (fused && j >= m) {
-                // the cycle is full: column m - 1 still needs ||V[m]||
-                P->prof_tag = -1;
+                // the cycle is full: column m - 1 still needs ||V[m]|| (tagged
+                // with that column: when an earlier column converged it
+                // returns at once and is not counted)
+                P->prof_tag = m - 1;
                 {
-                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), (double)P->N * sizeof(T) * (m + 3));
+                    ProfScope ps(P, K_GM_MAXPY, is_f32<T>(), (double)P->N * sizeof(T) * (m + 2));
                     HIP_TRY(gm_maxpy<T>(v.V, Np, m, v.w, v.V + (long)m * Np, Np, P->ctrl, h2off,
                                         MX_DOTS, P->partials, &np, s));
                 }
