@@ -409,9 +409,23 @@ fsd_status circ_precond(fsd_problem P, const double* in, double* out, const Ctrl
 // partial sums of (r, z), or with `pnorm` those of ||z||^2 (S is orthogonal:
 // ||z|| is the norm of the scaled spectrum; a dot product after the passes
 // where the scale pass does not provide it).
+// ||P^{-1} r||^2 alone (op_precond's norm_only) needs the scale pass to stop
+// after the scale: the float64 stage engine's half-length kernel does.
+template <typename T>
+bool norm_only_ok(fsd_problem P) {
+    if (!std::is_same<T, double>::value || P->pc != FSD_PC_TAU) return false;
+    const int last = P->dim - 1;
+    const int L = P->ax[last].L;
+    const int e = P->eng[0][last == 1 ? K_DSTS_Y : K_DSTS_Z];
+    return L >= 8 && (L / 2) % 2 == 0 && e != ENG_WAVE && e != ENG_WAVE1;
+}
+
 template <typename T>
 fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, double* partials,
-                      int* nparts, bool half = false, bool pnorm = false) {
+                      int* nparts, bool half = false, bool pnorm = false, bool norm_only = false) {
+    // norm_only: the partials of ||P^{-1} in||^2 only (out is not written)
+    if (norm_only && !(pnorm && partials && norm_only_ok<T>(P)))
+        return fail(FSD_EINVAL, "norm-only preconditioner pass not available");
     if (P->pc != FSD_PC_TAU) {
         // comparators of Section 4; the Parseval partials become a dot product
         if (P->pc == FSD_PC_NONE) {
@@ -489,7 +503,7 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
     const int kl = last == 1 ? K_DSTS_Y : K_DSTS_Z;
     if (runs(kl)) {
         const PassGeo gl = last == 1 ? geo_y(P) : geo_z(P);
-        const double nb = 2.0 * (double)P->N * sizeof(T);
+        const double nb = (norm_only ? 1.0 : 2.0) * (double)P->N * sizeof(T);
         ProfScope ps(P, last == 1 ? K_DSTS_Y : K_DSTS_Z, is_f32<T>(), nb);
         if (mfma(last)) {
             GdstArgs G = mg(last, gl, cur, mid);
@@ -516,9 +530,11 @@ fsd_status op_precond(fsd_problem P, const T* in, T* out, const Ctrl* ctrl, doub
             S.partials = pnorm && !pn_here ? nullptr : partials;
             S.pnorm = pn_here ? 1 : 0;
             S.half = half ? 1 : 0;
+            if (norm_only) S.o = nullptr;
             HIP_TRY(launch_dsts_s<T>(P->ax[last].L, S, nparts, P->stream, eng(kl)));
         }
     }
+    if (norm_only) return FSD_OK;
     cur = mid;
     if (P->dim == 3) {
         FSD_TRY(y_pass(cur, v.t[3]));
@@ -747,14 +763,20 @@ fsd_status gmres(fsd_problem P, T* x, const T* b, bool x0_zero, double tol, long
     // v_{j+1} runs in the prologue of the next matvec (unnormalised basis)
     const bool fused = !split && eta2 == 0.0 && fused_arnoldi_ok<T>(P);
     // ||P^{-1} b|| (||P^{-1/2} b||)
-    if (!(w_given && x0_zero)) {
+    // from x0 != 0 only the norm of P^{-1} b is needed (the first cycle forms
+    // its own residual): by Parseval from the scale pass where it can stop there
+    const bool pbb_norm_only = !x0_zero && !w_given && norm_only_ok<T>(P);
+    if (pbb_norm_only) {
+        FSD_TRY(ensure_b<T>(P, b, lazy));
+        FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, P->partials, &np, split, true, true));
+    } else if (!(w_given && x0_zero)) {
         FSD_TRY(ensure_b<T>(P, b, lazy));
         FSD_TRY(op_precond<T>(P, b, v.w, P->ctrl, nullptr, nullptr, split));
     }
     // a given w may come with its squared norm (w_norm2 >= 0)
     const bool wn_given = w_given && x0_zero && w_norm2 >= 0.0;
     if (wn_given) np = 0;
-    else HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
+    else if (!pbb_norm_only) HIP_TRY(vec_dot<T>(v.w, v.w, Np, P->partials, P->ctrl, &np, s));
     HIP_TRY(gm_scalar(P->ctrl, P->partials, np, 1, 0, GM_PBB, s, w_norm2));
     // with x0 = 0 the first cycle's update writes x = V y (left system): no fill
     if (x0_zero && split) HIP_TRY(vec_fill<T>(x, Np, T(0), s));
@@ -970,8 +992,11 @@ fsd_status outer_norms(fsd_problem P, const double* x, const double* b, double* 
         HIP_TRY(vec_dot<double>(b, b, P->Np, P->partials, nullptr, &np, s));
         HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_BB, s));
         if (pz) {
-            // ||P^{-1} b||^2 by Parseval from the scale pass
-            FSD_TRY(op_precond<double>(P, b, pz, nullptr, P->partials, &np, split, true));
+            // ||P^{-1} b||^2 by Parseval from the scale pass (P^{-1} b itself is
+            // not needed: the inverse transforms are skipped where the scale
+            // pass can stop there)
+            FSD_TRY(op_precond<double>(P, b, pz, nullptr, P->partials, &np, split, true,
+                                       norm_only_ok<double>(P)));
             HIP_TRY(scalar_step(P->ctrl, P->partials, np, SC_STORE_RZ, s));
         }
     }

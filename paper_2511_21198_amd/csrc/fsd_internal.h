@@ -139,7 +139,8 @@ struct DstArgs {
     int half;             // scale pass: Lambda^{-1/2} (the two-sided system) instead of Lambda^{-1}
     double* partials;     // Parseval partials of (r, P^{-1} r)
     int pnorm;            // float64 scale passes: the partials are ||P^{-1} r||^2 (Parseval
-                          // of the scaled spectrum) instead
+                          // of the scaled spectrum) instead; with o null the stage engine's
+                          // half-length scale pass leaves the partials only
     const Ctrl* ctrl;
 };
 

@@ -938,6 +938,12 @@ __global__ __launch_bounds__((Tile<T, L / 2, NC>::NT)) void k_dstsh_s(DstArgs<T>
     };
     if (a.half) scale_all(std::true_type{});
     else scale_all(std::false_type{});
+    if (!a.o) {
+        // the Parseval partials only (a norm of P^{-1} r whose vector is not needed)
+        const double sm = block_sum<NT>(acc, s_red);
+        if (tid == 0 && a.partials) a.partials[blockIdx.x] = sm;
+        return;
+    }
     __syncthreads();
     dsth_pre<T, H, NCL>(s_re, s_im, a.tw, tid);
     __syncthreads();
