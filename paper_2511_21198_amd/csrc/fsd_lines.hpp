@@ -56,11 +56,13 @@ __host__ __device__ constexpr Plan make_plan(int L) {
 }
 
 // NC: complex lines per tile (the tile shape; default lines_per_block).
-template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8)>
+// NTO > 0 overrides the thread count (more threads than butterflies: the
+// extra ones idle in the FFT stages).
+template <typename T, int L, int NC = lines_per_block(L, sizeof(T) == 8), int NTO = 0>
 struct Tile {
     static constexpr bool kF64 = sizeof(T) == 8;
     static constexpr int NCL = NC;
-    static constexpr int NT = threads_for_lines(L, NC);
+    static constexpr int NT = NTO > 0 ? NTO : threads_for_lines(L, NC);
     static constexpr int TX = 2 * NCL;          // real lines per tile
     static constexpr int SH = kF64 ? 4 : 5;     // LDS padding: one slot per 2^SH
     static constexpr int LP = L + (L >> SH) + 1; // padded line pitch in LDS
@@ -165,11 +167,11 @@ __device__ inline void dft(T* xr, T* xi) {
 // Twiddle t is (twr[t TWS2], twi[t TWS2]): split LDS arrays (TWS2 = 1) or
 // the interleaved global table (TWS2 = 2, twi = twr + 1).
 
-template <typename T, int L, int R, int M, int TWS2, int NC>
+template <typename T, int L, int R, int M, int TWS2, int NC, int NTO = 0>
 __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
                                  const T* __restrict__ twr, const T* __restrict__ twi,
                                  int tid) {
-    using TL = Tile<T, L, NC>;
+    using TL = Tile<T, L, NC, NTO>;
     constexpr int NCL = TL::NCL, NT = TL::NT, LP = TL::LP;
     constexpr int NBL = L / R;
     constexpr int NB = NCL * NBL;
@@ -226,14 +228,14 @@ __device__ inline void fft_stage(T* __restrict__ re, T* __restrict__ im,
     __syncthreads();
 }
 
-template <typename T, int L, int S, int M, int TWS2, int NC>
+template <typename T, int L, int S, int M, int TWS2, int NC, int NTO = 0>
 struct FFTRun {
     __device__ static inline void run(T* re, T* im, const T* twr, const T* twi, int tid) {
         constexpr Plan P = make_plan(L);
         if constexpr (S < P.nst) {
             constexpr int R = P.r[S];
-            fft_stage<T, L, R, M, TWS2, NC>(re, im, twr, twi, tid);
-            FFTRun<T, L, S + 1, M * R, TWS2, NC>::run(re, im, twr, twi, tid);
+            fft_stage<T, L, R, M, TWS2, NC, NTO>(re, im, twr, twi, tid);
+            FFTRun<T, L, S + 1, M * R, TWS2, NC, NTO>::run(re, im, twr, twi, tid);
         }
     }
 };
@@ -749,9 +751,9 @@ __global__ __launch_bounds__((Tile<T, L, NC>::NT)) void k_dsts_s(DstArgs<T> a) {
 
 // y from x in place for every line of the tile (index 0 holds 0 and keeps it).
 // twL: the pass's interleaved table exp(-2 pi i e / L), Im = -sin(pi e / H).
-template <typename T, int H, int NC>
+template <typename T, int H, int NC, int NTO = 0>
 __device__ inline void dsth_pre(T* re, T* im, const T* __restrict__ twL, int tid) {
-    using TH = Tile<T, H, NC>;
+    using TH = Tile<T, H, NC, NTO>;
     constexpr int HH = H / 2, LP = TH::LP;
     for (int e = tid; e < NC * HH; e += TH::NT) {
         const int ln = e / HH, j = e - ln * HH + 1;   // 1 .. H/2
@@ -772,10 +774,10 @@ __device__ inline void dsth_pre(T* re, T* im, const T* __restrict__ twL, int tid
 // (threads st = 0 .. TPL-1 of the line): the chunk totals of C go through
 // LDS (tot1, tot2: NT entries), then the chunk is read again for the running
 // sums.  Ends after a barrier: the LDS lines may then be overwritten.
-template <typename T, int H, int NC, int TPL, int CH>
+template <typename T, int H, int NC, int TPL, int CH, int NTO = 0>
 __device__ inline void dsth_post(const T* re, const T* im, T* tot1, T* tot2, int sl, int st,
                                  T (&s1)[2 * CH], T (&s2)[2 * CH]) {
-    using TH = Tile<T, H, NC>;
+    using TH = Tile<T, H, NC, NTO>;
     constexpr int HH = H / 2, LP = TH::LP;
     const T* lr = re + sl * LP;
     const T* li = im + sl * LP;
@@ -829,10 +831,19 @@ __device__ inline void dsth_post(const T* re, const T* im, T* tot1, T* tot2, int
 // input of the second DST-I).  Tile: NC complex lines of the transform of
 // length H = L/2; the workgroup count equals the odd-extension kernel's for
 // the same NC.
+// Float64 tiles take twice the threads of the FFT's butterflies: half the
+// DST coefficients per thread, fewer registers, more wavefronts per CU.
 template <typename T, int L, int NC>
-__global__ __launch_bounds__((Tile<T, L / 2, NC>::NT)) void k_dstsh_s(DstArgs<T> a) {
+constexpr int dstsh_nto() {
+    return sizeof(T) == 8 && 2 * threads_for_lines(L / 2, NC) <= 512 ? 2 * threads_for_lines(L / 2, NC)
+                                                                      : 0;
+}
+
+template <typename T, int L, int NC>
+__global__ __launch_bounds__((Tile<T, L / 2, NC, dstsh_nto<T, L, NC>()>::NT)) void k_dstsh_s(DstArgs<T> a) {
     constexpr int H = L / 2;
-    using TH = Tile<T, H, NC>;
+    constexpr int NTO = dstsh_nto<T, L, NC>();
+    using TH = Tile<T, H, NC, NTO>;
     constexpr int NCL = TH::NCL, NT = TH::NT, LP = TH::LP, TX = TH::TX;
     constexpr int GRP = NT / TX;
     constexpr int TPL = NT / NCL, CH = (H / 2 + TPL - 1) / TPL;
@@ -896,11 +907,11 @@ __global__ __launch_bounds__((Tile<T, L / 2, NC>::NT)) void k_dstsh_s(DstArgs<T>
     }
     __syncthreads();
     constexpr int TWS2 = TWL ? 1 : 4;
-    dsth_pre<T, H, NCL>(s_re, s_im, a.tw, tid);
+    dsth_pre<T, H, NCL, NTO>(s_re, s_im, a.tw, tid);
     __syncthreads();
-    FFTRun<T, H, 0, 1, TWS2, NCL>::run(s_re, s_im, twr, twi, tid);
+    FFTRun<T, H, 0, 1, TWS2, NCL, NTO>::run(s_re, s_im, twr, twi, tid);
     T s1[2 * CH], s2[2 * CH];
-    dsth_post<T, H, NCL, TPL, CH>(s_re, s_im, s_t1, s_t2, sl, st, s1, s2);
+    dsth_post<T, H, NCL, TPL, CH, NTO>(s_re, s_im, s_t1, s_t2, sl, st, s1, s2);
     // scale: c = sqrt(2 / H) makes the transform orthonormal
     const T c = T(2) * a.c;
     double acc = 0.0;
@@ -945,10 +956,10 @@ __global__ __launch_bounds__((Tile<T, L / 2, NC>::NT)) void k_dstsh_s(DstArgs<T>
         return;
     }
     __syncthreads();
-    dsth_pre<T, H, NCL>(s_re, s_im, a.tw, tid);
+    dsth_pre<T, H, NCL, NTO>(s_re, s_im, a.tw, tid);
     __syncthreads();
-    FFTRun<T, H, 0, 1, TWS2, NCL>::run(s_re, s_im, twr, twi, tid);
-    dsth_post<T, H, NCL, TPL, CH>(s_re, s_im, s_t1, s_t2, sl, st, s1, s2);
+    FFTRun<T, H, 0, 1, TWS2, NCL, NTO>::run(s_re, s_im, twr, twi, tid);
+    dsth_post<T, H, NCL, TPL, CH, NTO>(s_re, s_im, s_t1, s_t2, sl, st, s1, s2);
 #pragma unroll
     for (int q = 0; q < 2 * CH; ++q) {
         const int k = 2 * st * CH + q;

@@ -63,11 +63,13 @@ hipError_t stage_dstsh_launch(const DstArgs<T>& a, int* nb, hipStream_t s, int e
     if (eng == ENG_STAGE_HALF && NC::H != NC::D) {
         const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer, NC::H);
         if (nb) *nb = g;
-        if (g) hipLaunchKernelGGL((k_dstsh_s<T, L, NC::H>), dim3(g), dim3(Tile<T, L / 2, NC::H>::NT), 0, s, a);
+        if (g) hipLaunchKernelGGL((k_dstsh_s<T, L, NC::H>), dim3(g),
+                                  dim3(Tile<T, L / 2, NC::H, dstsh_nto<T, L, NC::H>()>::NT), 0, s, a);
     } else {
         const int g = s_blocks<T>(L, a.g.P1, a.g.n_outer, NC::D);
         if (nb) *nb = g;
-        if (g) hipLaunchKernelGGL((k_dstsh_s<T, L, NC::D>), dim3(g), dim3(Tile<T, L / 2, NC::D>::NT), 0, s, a);
+        if (g) hipLaunchKernelGGL((k_dstsh_s<T, L, NC::D>), dim3(g),
+                                  dim3(Tile<T, L / 2, NC::D, dstsh_nto<T, L, NC::D>()>::NT), 0, s, a);
     }
     return hipGetLastError();
 }
